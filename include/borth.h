@@ -1,0 +1,205 @@
+/*
+ * borth -- block orthonormalization of tall-skinny matrices on AMD MI355X
+ * (gfx950).  C ABI.
+ *
+ * The operation (Sec. 4.2 of Alvermann et al., "Benefits from using mixed
+ * precision computations in the ELPA-AEO and ESSEX-II eigensolver projects"):
+ * given a block X (m x k) and optionally a locked orthonormal basis Y
+ * (m x ky; the paper's W), phase I projects X against Y,
+ *     C = Y^T X,    Xt = (I - Y Y^T) X = X - Y C,
+ * and phase II orthonormalizes Xt by a k x k transform Z with Z^T M Z = I,
+ * where M = Xt^T Xt is the Gram matrix:
+ *     Cholesky (CholQR):  M = R^T R,  Z = R^{-1};
+ *     SVQB:               M = U L U^T, Z = U L^{-1/2} U^T  (symmetric form);
+ *     Q = Xt Z.
+ * "Iterating this process, alternating between the two phases" (Sec. 4.2)
+ * is offered as `passes` repetitions (passes = 2 is CholQR2).  The Gram
+ * matrix of the first pass can be accumulated in binary64, in double-double
+ * (DD, hi + lo; Sec. 4.2 "extended precision ... including the computation
+ * and decomposition of the Gram matrix"), or as BF16 hi/lo split products on
+ * the matrix cores (FP32 accumulation) followed by a shifted factorization;
+ * later passes are binary64.  On success
+ *     X = Y C + Q R,   Q^T Q = I,   Y^T Q = 0   (to working accuracy).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major.  Element (i, j) of X is X[i * ldx + j];
+ *    ld >= number of columns.  Small matrices (k x k, ky x k) are dense
+ *    row-major with leading dimension equal to their column count.
+ *  - X, Y, Q, R, C, G, Z are DEVICE pointers on the context's device, owned
+ *    by the caller.  borth_opts, borth_info and borth_block arrays are HOST
+ *    pointers.
+ *  - All work is enqueued on the context's HIP stream and is asynchronous,
+ *    except where a borth_info* is passed (then the call synchronizes the
+ *    stream and fills it) or BORTH_FLAG_SYNC is set.
+ *  - Argument errors return BORTH_ERR_ARG before anything is enqueued.
+ *    HIP failures return BORTH_ERR_HIP; borth_last_error() has the text.
+ *  - The context owns its workspace (partial Gram sums, k x k factors,
+ *    status words, cached graphs); it grows on demand and is released by
+ *    borth_destroy.  One context per host thread; calls on one context are
+ *    serialized by its stream.
+ */
+#ifndef BORTH_H
+#define BORTH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct borth_ctx_s* borth_ctx;
+
+typedef enum {
+  BORTH_OK = 0,
+  BORTH_ERR_ARG = 1,          /* invalid argument; nothing was enqueued */
+  BORTH_ERR_HIP = 2,          /* a HIP runtime call failed */
+  BORTH_ERR_NOMEM = 3,        /* workspace allocation failed */
+  BORTH_BREAKDOWN = 4,        /* Cholesky pivot <= 0 (see borth_info) */
+  BORTH_NONFINITE = 5,        /* NaN/Inf in a Gram matrix */
+  BORTH_ERR_UNSUPPORTED = 6   /* valid request this build does not implement */
+} borth_status;
+
+typedef enum { BORTH_F64 = 0, BORTH_F32 = 1 } borth_dtype;
+
+/* Precision of the first pass's Gram accumulation (later passes: binary64). */
+typedef enum {
+  BORTH_GRAM_F64 = 0,        /* binary64 FMAs on the matrix cores (k >= 16) or VALU */
+  BORTH_GRAM_DD = 1,         /* double-double: Dot2-style TwoSum/TwoProduct, DD k x k step */
+  BORTH_GRAM_SPLIT_BF16 = 2  /* X in fp32: (hi, lo) bf16 split, MFMA with fp32 accumulation */
+} borth_gram_prec;
+
+typedef enum { BORTH_CHOL = 0, BORTH_SVQB = 1 } borth_fact;
+
+/* How later passes read the intermediate block Q_1 = Xt Z_1. */
+typedef enum {
+  BORTH_SCHED_AUTO = 0,
+  BORTH_SCHED_MATERIALIZE = 1, /* write Q_1 into Q, re-read it: 2 reads + 2 read/writes */
+  BORTH_SCHED_RECOMPUTE = 2    /* recompute Q_1 bitwise from X: 3 reads + 1 write (passes = 2) */
+} borth_sched;
+
+#define BORTH_FLAG_SYNC 1u          /* synchronize before returning */
+#define BORTH_FLAG_PROJECT_ONCE 2u  /* project against Y in the first pass only (P,C,C) */
+#define BORTH_FLAG_GRAPH 4u         /* capture the launch sequence in a cached hipGraph */
+
+typedef struct {
+  int gram;       /* borth_gram_prec of pass 1 */
+  int fact;       /* borth_fact */
+  int passes;     /* 1, 2 (default) or 3 */
+  int sched;      /* borth_sched */
+  double shift;   /* first-pass Cholesky shift, relative: M + shift * trace(M) I.
+                     < 0: automatic (2^-13 for the split mode, 0 otherwise). */
+  unsigned flags; /* BORTH_FLAG_* */
+} borth_opts;
+
+typedef struct {
+  int status;       /* borth_status of the numerical work */
+  int failed_pass;  /* 1-based pass of a breakdown, 0 if none */
+  int failed_pivot; /* 1-based Cholesky pivot (LAPACK potrf style), 0 if none */
+  int passes_run;
+} borth_info;
+
+/* Fills *opts with the defaults: DD Gram, Cholesky, 2 passes, automatic
+ * schedule and shift, no flags. */
+void borth_default_opts(borth_opts* opts);
+
+/* Creates a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Allocates only small buffers. */
+borth_status borth_create(borth_ctx* ctx, int device, void* hip_stream);
+borth_status borth_destroy(borth_ctx ctx);
+borth_status borth_set_stream(borth_ctx ctx, void* hip_stream);
+const char* borth_status_string(int status);
+const char* borth_last_error(borth_ctx ctx);
+
+/* Synchronizes the stream and reports the numerical status of the last
+ * orthonormalization (breakdowns are otherwise only visible here). */
+borth_status borth_get_info(borth_ctx ctx, borth_info* info);
+
+/* Gram product (TSMTTSM, phase II "M = Xt^T Xt" and the fused phase-I
+ * coefficients "C = W^T X", Sec. 4.2): with V = [A | B] (m x (ka + kb)),
+ *     G = V^T V   (W x W, W = ka + kb <= 128, symmetric, both halves written).
+ * A: binary64 (may be NULL with ka = 0).  B: `dt_b` (BORTH_F32 only with
+ * prec = BORTH_GRAM_SPLIT_BF16 and ka = 0).  prec BORTH_GRAM_DD writes the
+ * low words to G_lo (device, W x W); G_lo may be NULL otherwise.  The
+ * summation order is fixed: results are bitwise reproducible. */
+borth_status borth_gram(borth_ctx ctx, int64_t m, int ka, const double* A, int64_t lda,
+                        int kb, borth_dtype dt_b, const void* B, int64_t ldb, int prec,
+                        double* G_hi, double* G_lo);
+
+/* Small factorization (Sec. 4.2 phase II, "determining a suitable matrix Z
+ * such that Z^T M Z = I"): from the Gram matrix G of [Y | X] (W x W,
+ * W = ky + k, hi and optional lo words), form
+ *     C = G_YX,  M = G_XX - 2 C^T C + C^T G_YY C  (= Xt^T Xt exactly),
+ * add shift * trace(M) to the diagonal if shift > 0, and factor M in DD
+ * (G_lo != NULL) or binary64: Cholesky M = R^T R, Z = R^{-1} (upper), or SVQB
+ * (binary64 only) Z = M^{-1/2}, R = M^{1/2}.  Outputs (device, may be NULL):
+ * Z (k x k), R (k x k), C (ky x k).  info (host, may be NULL) receives the
+ * breakdown pivot; passing it synchronizes. */
+borth_status borth_factor(borth_ctx ctx, int ky, int k, const double* G_hi,
+                          const double* G_lo, int fact, double shift, double* Z, double* R,
+                          double* C, borth_info* info);
+
+/* Basis update (TSMM): Q = (X - Y C) Z with C (ky x k) and Z (k x k,
+ * upper-triangular unless z_dense != 0), binary64 FMAs.  X is `dt`
+ * (fp32 is widened exactly).  Q may alias X when dt == BORTH_F64 and
+ * ldq == ldx (rows are read before they are written). */
+borth_status borth_update(borth_ctx ctx, int64_t m, int k, borth_dtype dt, const void* X,
+                          int64_t ldx, const double* Y, int64_t ldy, int ky, const double* C,
+                          const double* Z, int z_dense, double* Q, int64_t ldq);
+
+/* The whole path: `passes` iterations of (phase I, phase II) with the first
+ * Gram in opts->gram precision.  k <= 64, ky <= 64, m >= k + ky.
+ * X: m x k (`dt`), Y: m x ky binary64 orthonormal (NULL if ky = 0),
+ * Q: m x k binary64 output (may alias X iff dt == BORTH_F64, ldq == ldx and
+ * the schedule is MATERIALIZE), R: k x k (R_p ... R_1, device, may be NULL),
+ * C: ky x k total coefficients (device, may be NULL).  opts may be NULL
+ * (defaults).  info (host) may be NULL; non-NULL synchronizes.  Returns the
+ * numerical status when it synchronizes, else BORTH_OK once enqueued. */
+borth_status borth_orthonormalize(borth_ctx ctx, int64_t m, int k, borth_dtype dt,
+                                  const void* X, int64_t ldx, const double* Y, int64_t ldy,
+                                  int ky, double* Q, int64_t ldq, double* R, double* C,
+                                  const borth_opts* opts, borth_info* info);
+
+/* One block of a batch (all pointers device, as in borth_orthonormalize;
+ * X binary64). */
+typedef struct {
+  int64_t m;
+  int k;
+  const double* X;
+  int64_t ldx;
+  const double* Y; /* may be NULL with ky = 0 */
+  int64_t ldy;
+  int ky;
+  double* Q;
+  int64_t ldq;
+  double* R; /* may be NULL */
+  double* C; /* may be NULL */
+} borth_block;
+
+/* Many independent blocks of uneven shape (e.g. the per-node bases of a
+ * contour-integral eigensolver, Sec. 4.1) orthonormalized together: each
+ * phase of every block runs in one launch over all blocks, the launch
+ * sequence is captured once into a hipGraph cached on the context and
+ * replayed.  `blocks` and `infos` are host arrays of nblocks entries
+ * (infos may be NULL; non-NULL synchronizes).  Tile shapes come from the
+ * autotune table when one is loaded. */
+borth_status borth_batch_orthonormalize(borth_ctx ctx, int nblocks, const borth_block* blocks,
+                                        const borth_opts* opts, borth_info* infos);
+
+/* Times the tile/launch-shape candidates of the Gram and update kernels on
+ * synthetic data resident on the device (~budget_ms in total), keeps the
+ * fastest per (mode, width) in the context, and writes them as JSON to
+ * cache_path (if not NULL).  borth_autotune_load reads such a file. */
+borth_status borth_autotune(borth_ctx ctx, const char* cache_path, int budget_ms);
+borth_status borth_autotune_load(borth_ctx ctx, const char* cache_path);
+
+/* Average duration (ms) of the last call's dominant kernel launches, taken
+ * from HIP events on the context's stream when profiling is enabled with
+ * borth_set_profiling(ctx, 1).  kind: 0 = first-pass Gram sweep,
+ * 1 = update sweeps; returns the number of timed launches in *count. */
+borth_status borth_set_profiling(borth_ctx ctx, int on);
+borth_status borth_kernel_time(borth_ctx ctx, int kind, double* avg_ms, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BORTH_H */

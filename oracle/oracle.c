@@ -437,24 +437,43 @@ static dd dot2_rows(int64_t r0, int64_t r1, const double* a, int64_t lda,
 }
 
 /* O2 Gram  G = A^T B  by Dot2 per entry, fixed row partition, partials
- * combined in block order with DD additions. */
+ * combined in block order with DD additions.  Within a block the rows are
+ * visited in order for all entries at once (the same operation sequence per
+ * entry as dot2_rows, only the loop nest is row-major for locality). */
 int or_gram_dot2(int64_t m, int ka, const double* A, int64_t lda, int kb,
                  const double* B, int64_t ldb, double* ghi, double* glo) {
   const int64_t np = npart(m);
   const size_t n = (size_t)ka * kb;
   dd* part = (dd*)malloc(sizeof(dd) * ((size_t)np * n + 1));
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t b = 0; b < np; ++b) {
-    const int64_t r0 = pbeg(m, np, b), r1 = pbeg(m, np, b + 1);
-    for (int i = 0; i < ka; ++i)
-      for (int j = 0; j < kb; ++j)
-        part[(size_t)b * n + (size_t)i * kb + j] = dot2_rows(r0, r1, A + i, lda, B + j, ldb);
+#pragma omp parallel
+  {
+    double* s = (double*)malloc(sizeof(double) * (n + 1));
+    double* c = (double*)malloc(sizeof(double) * (n + 1));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t b = 0; b < np; ++b) {
+      for (size_t e = 0; e < n; ++e) { s[e] = 0; c[e] = 0; }
+      for (int64_t r = pbeg(m, np, b); r < pbeg(m, np, b + 1); ++r) {
+        const double* a = A + r * lda;
+        const double* bb = B + r * ldb;
+        for (int i = 0; i < ka; ++i)
+          for (int j = 0; j < kb; ++j) {
+            const size_t e = (size_t)i * kb + j;
+            const dd p = two_prod(a[i], bb[j]);
+            const dd t = two_sum(s[e], p.h);
+            s[e] = t.h;
+            c[e] += t.l + p.l;
+          }
+      }
+      for (size_t e = 0; e < n; ++e) part[(size_t)b * n + e] = fast_two_sum(s[e], c[e]);
+    }
+    free(s);
+    free(c);
   }
   for (size_t e = 0; e < n; ++e) {
-    dd s = {0, 0};
-    for (int64_t b = 0; b < np; ++b) s = dd_add(s, part[(size_t)b * n + e]);
-    ghi[e] = s.h;
-    if (glo) glo[e] = s.l;
+    dd acc = {0, 0};
+    for (int64_t b = 0; b < np; ++b) acc = dd_add(acc, part[(size_t)b * n + e]);
+    ghi[e] = acc.h;
+    if (glo) glo[e] = acc.l;
   }
   free(part);
   return 0;

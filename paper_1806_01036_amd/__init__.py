@@ -1,0 +1,271 @@
+"""Block orthonormalization of tall-skinny matrices on AMD MI355X (gfx950).
+
+Python face of ``libborth.so`` (C ABI in ``include/borth.h``).  The method is
+the two-phase orthogonalization of Sec. 4.2 of Alvermann et al. (arXiv
+1806.01036): project X against a locked orthonormal basis Y, then
+orthonormalize the result through its Gram matrix (CholQR / SVQB), iterated
+(CholQR2); the first Gram matrix can be accumulated in double-double or as
+split BF16 products on the matrix cores.
+
+Tensors are torch CUDA (HIP) tensors, row-major with unit column stride; the
+work is enqueued on torch's current stream.  Names mirror the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+from . import _lib
+
+__all__ = [
+    "BorthError", "Breakdown", "Context", "Info", "default_context", "gram", "factor",
+    "update", "orthonormalize", "batch_orthonormalize", "GRAM", "FACT", "SCHED",
+]
+
+GRAM = {"f64": 0, "dd": 1, "split": 2}
+FACT = {"chol": 0, "svqb": 1}
+SCHED = {"auto": 0, "materialize": 1, "recompute": 2}
+FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH = 1, 2, 4
+OK, ERR_ARG, ERR_HIP, ERR_NOMEM, BREAKDOWN, NONFINITE, UNSUPPORTED = range(7)
+
+
+class BorthError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"borth status {status}: {msg}")
+        self.status = status
+
+
+class Breakdown(BorthError):
+    pass
+
+
+@dataclass
+class Info:
+    status: int
+    failed_pass: int
+    failed_pivot: int
+    passes_run: int
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A library context bound to one device (and torch's current stream)."""
+
+    def __init__(self, device: int = 0):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        st = lib.borth_create(ctypes.byref(h), int(device), _stream_handle())
+        if st != OK:
+            raise BorthError(st, "borth_create failed")
+        self.h = h
+        self.device = device
+        self.lib = lib
+
+    def sync_stream(self):
+        self.lib.borth_set_stream(self.h, _stream_handle())
+
+    def check(self, st):
+        if st == OK:
+            return
+        msg = self.lib.borth_last_error(self.h).decode()
+        if st == BREAKDOWN:
+            raise Breakdown(st, msg or "Cholesky breakdown")
+        raise BorthError(st, msg or self.lib.borth_status_string(st).decode())
+
+    def close(self):
+        if self.h:
+            self.lib.borth_destroy(self.h)
+            self.h = None
+
+    def set_profiling(self, on: bool):
+        self.check(self.lib.borth_set_profiling(self.h, int(bool(on))))
+
+    def kernel_time(self, kind: int):
+        avg = ctypes.c_double()
+        n = ctypes.c_int()
+        self.check(self.lib.borth_kernel_time(self.h, kind, ctypes.byref(avg), ctypes.byref(n)))
+        return avg.value, n.value
+
+    def info(self) -> Info:
+        inf = _lib.borth_info()
+        self.check(self.lib.borth_get_info(self.h, ctypes.byref(inf)))
+        return Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run)
+
+    def autotune(self, cache_path=None, budget_ms=2000):
+        p = None if cache_path is None else str(cache_path).encode()
+        self.check(self.lib.borth_autotune(self.h, p, int(budget_ms)))
+
+    def autotune_load(self, cache_path):
+        self.check(self.lib.borth_autotune_load(self.h, str(cache_path).encode()))
+
+
+_contexts = {}
+
+
+def default_context(device=None) -> Context:
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _contexts:
+        _contexts[dev] = Context(dev)
+    ctx = _contexts[dev]
+    ctx.sync_stream()
+    return ctx
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _ld(t):
+    if t is None:
+        return 0
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("matrices must be 2-D with unit column stride")
+    return t.stride(0)
+
+
+def _dt(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return 0
+    if t.dtype == torch.float32:
+        return 1
+    raise TypeError("float64 or float32 tensors only")
+
+
+def gram(B, A=None, prec="f64", ctx=None):
+    """G = [A | B]^T [A | B] (hi, lo); lo is None unless prec == 'dd'."""
+    torch = _torch()
+    ctx = ctx or default_context(B.device.index)
+    m, kb = B.shape
+    ka = 0 if A is None else A.shape[1]
+    W = ka + kb
+    ghi = torch.empty((W, W), dtype=torch.float64, device=B.device)
+    glo = torch.empty((W, W), dtype=torch.float64, device=B.device) if prec == "dd" else None
+    ctx.check(ctx.lib.borth_gram(ctx.h, m, ka, _ptr(A), _ld(A) if A is not None else ka, kb,
+                                 _dt(B), _ptr(B), _ld(B), GRAM[prec], _ptr(ghi), _ptr(glo)))
+    return ghi, glo
+
+
+def factor(G_hi, G_lo=None, ky=0, fact="chol", shift=0.0, ctx=None, check=True):
+    """Phase-II transform from the Gram matrix of [Y | X]: returns
+    (Z, R, C, Info) with Z^T M Z = I."""
+    torch = _torch()
+    ctx = ctx or default_context(G_hi.device.index)
+    W = G_hi.shape[0]
+    k = W - ky
+    dev = G_hi.device
+    Z = torch.zeros((k, k), dtype=torch.float64, device=dev)
+    R = torch.zeros((k, k), dtype=torch.float64, device=dev)
+    C = torch.zeros((max(ky, 1), k), dtype=torch.float64, device=dev)
+    inf = _lib.borth_info()
+    st = ctx.lib.borth_factor(ctx.h, ky, k, _ptr(G_hi), _ptr(G_lo), FACT[fact], float(shift),
+                              _ptr(Z), _ptr(R), _ptr(C) if ky else ctypes.c_void_p(0),
+                              ctypes.byref(inf))
+    info = Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run)
+    if check:
+        ctx.check(st)
+    return Z, R, C[:ky], info
+
+
+def update(X, Z, Y=None, C=None, dense=False, out=None, ctx=None):
+    """Q = (X - Y C) Z (binary64 result)."""
+    torch = _torch()
+    ctx = ctx or default_context(X.device.index)
+    m, k = X.shape
+    ky = 0 if Y is None else Y.shape[1]
+    Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=X.device)
+    ctx.check(ctx.lib.borth_update(ctx.h, m, k, _dt(X), _ptr(X), _ld(X), _ptr(Y),
+                                   _ld(Y) if ky else 0, ky, _ptr(C), _ptr(Z), int(bool(dense)),
+                                   _ptr(Q), _ld(Q)))
+    return Q
+
+
+def _opts(gram, fact, passes, sched, shift, flags):
+    o = _lib.borth_opts()
+    o.gram = GRAM[gram]
+    o.fact = FACT[fact]
+    o.passes = int(passes)
+    o.sched = SCHED[sched]
+    o.shift = float(shift)
+    o.flags = int(flags)
+    return o
+
+
+def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto", shift=-1.0,
+                   project_once=False, graph=False, out=None, R=None, C=None, sync=True,
+                   check=True, ctx=None):
+    """X = Y C + Q R with Q^T Q = I and Y^T Q = 0.  Returns (Q, R, C, Info);
+    Info is None when ``sync`` is False (the call is then fully asynchronous)."""
+    torch = _torch()
+    ctx = ctx or default_context(X.device.index)
+    m, k = X.shape
+    ky = 0 if Y is None else Y.shape[1]
+    dev = X.device
+    Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
+    R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
+    if ky and C is None:
+        C = torch.empty((ky, k), dtype=torch.float64, device=dev)
+    flags = (FLAG_PROJECT_ONCE if project_once else 0) | (FLAG_GRAPH if graph else 0)
+    o = _opts(gram, fact, passes, sched, shift, flags)
+    inf = _lib.borth_info()
+    st = ctx.lib.borth_orthonormalize(ctx.h, m, k, _dt(X), _ptr(X), _ld(X), _ptr(Y),
+                                      _ld(Y) if ky else 0, ky, _ptr(Q), _ld(Q), _ptr(R),
+                                      _ptr(C) if ky else ctypes.c_void_p(0), ctypes.byref(o),
+                                      ctypes.byref(inf) if sync else None)
+    info = Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run) if sync else None
+    if check or st not in (BREAKDOWN, NONFINITE):
+        ctx.check(st)
+    return Q, R, (C if ky else None), info
+
+
+def batch_orthonormalize(blocks, *, gram="dd", passes=2, shift=-1.0, project_once=False,
+                         sync=True, check=True, ctx=None):
+    """blocks: list of dicts with X (m x k float64), optional Y (m x ky), and
+    optional preallocated Q, R, C.  Returns the list of (Q, R, C) and the
+    list of Info (None when not synchronizing)."""
+    torch = _torch()
+    if not blocks:
+        return [], []
+    ctx = ctx or default_context(blocks[0]["X"].device.index)
+    arr = (_lib.borth_block * len(blocks))()
+    outs = []
+    for i, b in enumerate(blocks):
+        X = b["X"]
+        Y = b.get("Y")
+        m, k = X.shape
+        ky = 0 if Y is None else Y.shape[1]
+        Q = b.get("Q")
+        if Q is None:
+            Q = torch.empty((m, k), dtype=torch.float64, device=X.device)
+        Rt = b.get("R")
+        if Rt is None:
+            Rt = torch.empty((k, k), dtype=torch.float64, device=X.device)
+        Ct = b.get("C")
+        if ky and Ct is None:
+            Ct = torch.empty((ky, k), dtype=torch.float64, device=X.device)
+        e = arr[i]
+        e.m, e.k, e.X, e.ldx = m, k, X.data_ptr(), _ld(X)
+        e.Y, e.ldy, e.ky = (Y.data_ptr() if ky else None), (_ld(Y) if ky else 0), ky
+        e.Q, e.ldq, e.R = Q.data_ptr(), _ld(Q), Rt.data_ptr()
+        e.C = Ct.data_ptr() if ky else None
+        outs.append((Q, Rt, Ct if ky else None))
+    o = _opts(gram, "chol", passes, "materialize", shift,
+              FLAG_PROJECT_ONCE if project_once else 0)
+    infs = (_lib.borth_info * len(blocks))()
+    st = ctx.lib.borth_batch_orthonormalize(ctx.h, len(blocks), arr, ctypes.byref(o),
+                                            infs if sync else None)
+    infos = [Info(i.status, i.failed_pass, i.failed_pivot, i.passes_run) for i in infs] \
+        if sync else [None] * len(blocks)
+    if check or st not in (BREAKDOWN, NONFINITE):
+        ctx.check(st)
+    return outs, infos

@@ -1,0 +1,701 @@
+// C ABI of the block-orthonormalization library (see include/borth.h).
+//
+// Host-side orchestration of the sweeps of one orthonormalization call:
+//   pass 1:  Gram sweep over [Y | X] (binary64, DD or split bf16)
+//            -> fixed-order reduction -> k x k factor (DD or binary64)
+//   pass p:  update sweep (X - Y C) Z with the next pass's Gram fused
+//            -> reduction -> factor
+//   last:    update sweep writing Q (materialized Q_1 or Q_1 recomputed).
+// Everything stays on the device and on one stream; the only readback is the
+// 4-int status word when the caller asks for it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/borth.h"
+#include "internal.hpp"
+
+using namespace borth;
+
+struct GraphKey {
+  std::vector<int64_t> v;
+  bool operator<(const GraphKey& o) const { return v < o.v; }
+};
+
+struct TimedPair {
+  hipEvent_t a, b;
+};
+
+struct borth_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double* part = nullptr;
+  int64_t part_cap = 0;  // doubles
+  double* ws = nullptr;
+  int64_t ws_cap = 0;
+  int* status = nullptr;   // device, 4 ints (+ batch statuses)
+  int status_cap = 0;
+  int* h_status = nullptr;  // pinned host copy
+  int h_status_cap = 0;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  uint64_t ws_generation = 0;
+  // profiling
+  bool prof = false;
+  std::vector<TimedPair> ev_free;
+  std::vector<TimedPair> ev_used[2];
+  // autotune table: key (mode, kp, ky>0) -> tune
+  std::map<std::tuple<int, int, int>, TuneGram> tune_gram;
+  std::map<std::tuple<int, int, int>, TuneGram> tune_upd;
+  // batch plan cache (device descriptors)
+  void* batch_mem = nullptr;
+  int64_t batch_mem_cap = 0;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  bool capturing = false;
+  hipStream_t cur = nullptr;         // stream the current enqueue targets
+};
+
+namespace {
+
+const char* kStatusText[] = {"ok",
+                             "invalid argument",
+                             "HIP runtime error",
+                             "out of device memory",
+                             "Cholesky breakdown (non-positive pivot)",
+                             "non-finite value in a Gram matrix",
+                             "unsupported request"};
+
+borth_status fail_hip(borth_ctx c, hipError_t e, const char* where) {
+  if (c) {
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return BORTH_ERR_HIP;
+}
+
+borth_status fail_arg(borth_ctx c, const char* what) {
+  if (c) c->err = std::string("invalid argument: ") + what;
+  return BORTH_ERR_ARG;
+}
+
+#define HIPCHK(c, expr, where)                 \
+  do {                                         \
+    hipError_t _e = (expr);                    \
+    if (_e != hipSuccess) return fail_hip(c, _e, where); \
+  } while (0)
+
+int pow2pad(int k) {
+  int p = 4;
+  while (p < k) p <<= 1;
+  return p;
+}
+
+void invalidate_graphs(borth_ctx c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+borth_status ensure(borth_ctx c, double** buf, int64_t* cap, int64_t need) {
+  if (need <= *cap) return BORTH_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(c, e, "hipStreamSynchronize");
+  if (*buf) hipFree(*buf);
+  *buf = nullptr;
+  *cap = 0;
+  int64_t n = need + need / 4;
+  e = hipMalloc((void**)buf, sizeof(double) * (size_t)n);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    c->err = "workspace allocation failed";
+    return BORTH_ERR_NOMEM;
+  }
+  *cap = n;
+  invalidate_graphs(c);
+  ++c->ws_generation;
+  return BORTH_OK;
+}
+
+borth_status ensure_status(borth_ctx c, int n) {
+  if (n <= c->status_cap && n <= c->h_status_cap) return BORTH_OK;
+  hipStreamSynchronize(c->stream);
+  if (c->status) hipFree(c->status);
+  if (c->h_status) hipHostFree(c->h_status);
+  c->status = nullptr;
+  c->h_status = nullptr;
+  int nn = n < 64 ? 64 : n;
+  if (hipMalloc((void**)&c->status, sizeof(int) * nn) != hipSuccess) return BORTH_ERR_NOMEM;
+  if (hipHostMalloc((void**)&c->h_status, sizeof(int) * nn, hipHostMallocDefault) != hipSuccess)
+    return BORTH_ERR_NOMEM;
+  c->status_cap = nn;
+  c->h_status_cap = nn;
+  invalidate_graphs(c);
+  return BORTH_OK;
+}
+
+// Small-matrix workspace layout (doubles), for W = ky + k <= 128, kp <= 64.
+struct WsLayout {
+  int64_t g_hi, g_lo, zp[3], cp[3], rtot, ctot, zu, cu, total;
+};
+WsLayout ws_layout() {
+  WsLayout w;
+  int64_t o = 0;
+  w.g_hi = o; o += 128 * 128;
+  w.g_lo = o; o += 128 * 128;
+  for (int i = 0; i < 3; ++i) { w.zp[i] = o; o += 64 * 64; }
+  for (int i = 0; i < 3; ++i) { w.cp[i] = o; o += 64 * 64; }
+  w.rtot = o; o += 2 * 64 * 64;
+  w.ctot = o; o += 2 * 64 * 64;
+  w.zu = o; o += 64 * 64;
+  w.cu = o; o += 64 * 64;
+  w.total = o;
+  return w;
+}
+
+TuneGram lookup(const std::map<std::tuple<int, int, int>, TuneGram>& t, int mode, int kp, int hasy) {
+  auto it = t.find(std::make_tuple(mode, kp, hasy));
+  if (it != t.end()) return it->second;
+  return TuneGram{0, 0};
+}
+
+void prof_begin(borth_ctx c, int kind) {
+  if (!c->prof || c->capturing) return;
+  TimedPair p;
+  if (!c->ev_free.empty()) {
+    p = c->ev_free.back();
+    c->ev_free.pop_back();
+  } else {
+    hipEventCreate(&p.a);
+    hipEventCreate(&p.b);
+  }
+  hipEventRecord(p.a, c->cur);
+  c->ev_used[kind].push_back(p);
+}
+void prof_end(borth_ctx c, int kind) {
+  if (!c->prof || c->capturing) return;
+  hipEventRecord(c->ev_used[kind].back().b, c->cur);
+}
+
+// Copy a rows x k matrix into a rows x kp zero-padded one (device to device).
+borth_status pad_copy(borth_ctx c, double* dst, int kp, const double* src, int k, int rows) {
+  if (rows == 0) return BORTH_OK;
+  HIPCHK(c, hipMemcpy2DAsync(dst, sizeof(double) * kp, src, sizeof(double) * k, sizeof(double) * k,
+                             rows, hipMemcpyDeviceToDevice, c->stream),
+         "hipMemcpy2DAsync");
+  return BORTH_OK;
+}
+
+// The orthonormalization launch sequence (enqueue only).
+struct OrthoCall {
+  int64_t m;
+  int k, ky;
+  borth_dtype dt;
+  const void* X;
+  int64_t ldx;
+  const double* Y;
+  int64_t ldy;
+  double* Q;
+  int64_t ldq;
+  double* R;
+  double* C;
+  borth_opts o;
+};
+
+borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
+  hipStream_t st = c->cur;
+  const WsLayout W = ws_layout();
+  double* ws = c->ws;
+  const int kp = pow2pad(a.k);
+  const int gmode = a.o.gram;
+  const bool split = gmode == BORTH_GRAM_SPLIT_BF16;
+  const bool dd = gmode == BORTH_GRAM_DD;
+  const bool project_each = !(a.o.flags & BORTH_FLAG_PROJECT_ONCE);
+  const int passes = a.o.passes;
+  int sched = a.o.sched;
+  if (sched == BORTH_SCHED_AUTO)
+    sched = (passes == 2 && a.dt == BORTH_F64 && kp <= 32 && a.X != (const void*)a.Q)
+                ? BORTH_SCHED_RECOMPUTE
+                : BORTH_SCHED_MATERIALIZE;
+  double shift = a.o.shift;
+  if (shift < 0) shift = split ? std::ldexp(1.0, -13) : 0.0;
+  const bool hasy = a.ky > 0;
+
+  HIPCHK(c, launch_fill_int(c->status, 4, 0, st), "fill");
+
+  // ---- pass 1: Gram sweep + reduction + factor
+  Src s1{a.Y, a.ldy, a.X, a.ldx, a.dt == BORTH_F32 ? 1 : 0, a.m};
+  GramLayout L1 = make_layout(a.ky, a.k, 4);
+  int nwg = 0;
+  prof_begin(c, 0);
+  if (split) {
+    Src ss{nullptr, 0, a.X, a.ldx, 1, a.m};
+    GramLayout Ls = make_layout(0, a.k, 4);
+    HIPCHK(c, launch_gram_split(ss, Ls, c->part, c->part_cap, &nwg, lookup(c->tune_gram, 2, kp, 0), st),
+           "gram_split");
+    prof_end(c, 0);
+    HIPCHK(c, launch_reduce(Ls, 0, c->part, nwg, ws + W.g_hi, nullptr, st), "reduce");
+  } else {
+    HIPCHK(c, launch_gram(s1, L1, dd ? 1 : 0, c->part, c->part_cap, &nwg,
+                          lookup(c->tune_gram, dd ? 1 : 0, kp, hasy), st),
+           "gram");
+    prof_end(c, 0);
+    HIPCHK(c, launch_reduce(L1, dd ? 1 : 0, c->part, nwg, ws + W.g_hi, dd ? ws + W.g_lo : nullptr, st),
+           "reduce");
+  }
+  auto factor = [&](int pass, int kyp_pass, const double* ghi, const double* glo, bool ddm,
+                    double shrel, bool last) -> borth_status {
+    FactorArgs f;
+    memset(&f, 0, sizeof(f));
+    f.ky = kyp_pass;
+    f.k = a.k;
+    f.kp = kp;
+    f.G_hi = ghi;
+    f.G_lo = glo;
+    f.dd = ddm ? 1 : 0;
+    f.fact = a.o.fact;
+    f.shift_rel = shrel;
+    f.pass = pass;
+    f.Zp = ws + W.zp[pass];
+    f.Cp = ws + W.cp[pass];
+    f.Rtot = ws + W.rtot;
+    f.Ctot = ws + W.ctot;
+    f.status = c->status;
+    f.R_out = last ? a.R : nullptr;
+    f.C_out = (last && hasy) ? a.C : nullptr;
+    HIPCHK(c, launch_factor(f, st), "factor");
+    return BORTH_OK;
+  };
+  borth_status r = factor(0, a.ky, ws + W.g_hi, dd ? ws + W.g_lo : nullptr, dd, shift, passes == 1);
+  if (r) return r;
+  // C totals when the later passes do not project: the factor of pass 0 already
+  // set C_tot = C_1; later factors run with ky = 0 and leave it (C_out written by
+  // the last factor only if it projects, so copy it here).
+  const bool later_proj = project_each && hasy;
+  if (hasy && !later_proj && passes > 1 && a.C)
+    HIPCHK(c, hipMemcpyAsync(a.C, ws + W.ctot, sizeof(double) * a.ky * a.k, hipMemcpyDeviceToDevice, st),
+           "copy C");
+
+  GramLayout Lu = make_layout(a.ky, a.k, kp);
+  if (passes == 1) {
+    UpdateArgs u;
+    memset(&u, 0, sizeof(u));
+    u.src = s1;
+    u.C1 = ws + W.cp[0];
+    u.Z1 = ws + W.zp[0];
+    u.dense = a.o.fact == BORTH_SVQB;
+    u.Q = a.Q;
+    u.ldq = a.ldq;
+    prof_begin(c, 1);
+    HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 0, kp, hasy), st), "update");
+    prof_end(c, 1);
+    return BORTH_OK;
+  }
+
+  if (sched == BORTH_SCHED_RECOMPUTE && passes == 2 && !split) {
+    // sweep 2: Q_1 in registers, Gram of [Y | Q_1] (or Q_1) fused
+    UpdateArgs u;
+    memset(&u, 0, sizeof(u));
+    u.src = s1;
+    u.C1 = ws + W.cp[0];
+    u.Z1 = ws + W.zp[0];
+    u.dense = a.o.fact == BORTH_SVQB;
+    u.gram_with_y = later_proj ? 1 : 0;
+    u.partials = c->part;
+    u.partial_cap_doubles = c->part_cap;
+    prof_begin(c, 1);
+    HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 1, kp, hasy), st), "update2");
+    prof_end(c, 1);
+    GramLayout Lg = later_proj ? Lu : make_layout(0, a.k, kp);
+    HIPCHK(c, launch_reduce(Lg, 0, c->part, u.nwg, ws + W.g_hi, nullptr, st), "reduce2");
+    r = factor(1, later_proj ? a.ky : 0, ws + W.g_hi, nullptr, false, 0.0, true);
+    if (r) return r;
+    // sweep 3: recompute Q_1 bitwise, apply pass 2, write Q
+    UpdateArgs u3;
+    memset(&u3, 0, sizeof(u3));
+    u3.src = s1;
+    u3.C1 = ws + W.cp[0];
+    u3.Z1 = ws + W.zp[0];
+    u3.C2 = ws + W.cp[1];
+    u3.Z2 = ws + W.zp[1];
+    u3.two_stage = 1;
+    u3.dense = a.o.fact == BORTH_SVQB;
+    u3.Q = a.Q;
+    u3.ldq = a.ldq;
+    if (!later_proj) {
+      // pass 2 did not project: its C is zero
+      HIPCHK(c, launch_fill_int((int*)(ws + W.cp[1]), 2 * 64 * 64, 0, st), "zero C2");
+    }
+    prof_begin(c, 1);
+    HIPCHK(c, launch_update(u3, Lu, lookup(c->tune_upd, 2, kp, hasy), st), "update3");
+    prof_end(c, 1);
+    return BORTH_OK;
+  }
+
+  // materialized schedule: every pass writes its result into Q
+  Src cur = s1;
+  for (int p = 1; p < passes; ++p) {
+    UpdateArgs u;
+    memset(&u, 0, sizeof(u));
+    u.src = cur;
+    u.C1 = ws + W.cp[p - 1];
+    u.Z1 = ws + W.zp[p - 1];
+    u.dense = a.o.fact == BORTH_SVQB;
+    u.Q = a.Q;
+    u.ldq = a.ldq;
+    u.gram_with_y = later_proj ? 1 : 0;
+    u.partials = c->part;
+    u.partial_cap_doubles = c->part_cap;
+    prof_begin(c, 1);
+    HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 1, kp, hasy), st), "update_p");
+    prof_end(c, 1);
+    GramLayout Lg = later_proj ? Lu : make_layout(0, a.k, kp);
+    HIPCHK(c, launch_reduce(Lg, 0, c->part, u.nwg, ws + W.g_hi, nullptr, st), "reduce_p");
+    r = factor(p, later_proj ? a.ky : 0, ws + W.g_hi, nullptr, false, 0.0, p == passes - 1);
+    if (r) return r;
+    cur = Src{a.Y, a.ldy, a.Q, a.ldq, 0, a.m};
+    if (!later_proj) HIPCHK(c, launch_fill_int((int*)(ws + W.cp[p]), 2 * 64 * 64, 0, st), "zero C");
+  }
+  UpdateArgs u;
+  memset(&u, 0, sizeof(u));
+  u.src = cur;
+  u.C1 = ws + W.cp[passes - 1];
+  u.Z1 = ws + W.zp[passes - 1];
+  u.dense = a.o.fact == BORTH_SVQB;
+  u.Q = a.Q;
+  u.ldq = a.ldq;
+  prof_begin(c, 1);
+  HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 0, kp, hasy), st), "update_last");
+  prof_end(c, 1);
+  return BORTH_OK;
+}
+
+int64_t partial_need(int ky, int k, int gmode) {
+  const int kp = pow2pad(k);
+  GramLayout L1 = make_layout(ky, k, 4);
+  GramLayout Lu = make_layout(ky, k, kp);
+  int64_t e = (int64_t)L1.E * (gmode == BORTH_GRAM_DD ? 2 : 1);
+  if (Lu.E > e) e = Lu.E;
+  return 1024 * e;
+}
+
+borth_status read_status(borth_ctx c, borth_info* info) {
+  HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream),
+         "status readback");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (info) {
+    info->status = c->h_status[0];
+    info->failed_pass = c->h_status[1];
+    info->failed_pivot = c->h_status[2];
+    info->passes_run = c->h_status[3];
+  }
+  return (borth_status)c->h_status[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+void borth_default_opts(borth_opts* o) {
+  if (!o) return;
+  o->gram = BORTH_GRAM_DD;
+  o->fact = BORTH_CHOL;
+  o->passes = 2;
+  o->sched = BORTH_SCHED_AUTO;
+  o->shift = -1.0;
+  o->flags = 0;
+}
+
+const char* borth_status_string(int s) {
+  if (s < 0 || s > 6) return "unknown status";
+  return kStatusText[s];
+}
+
+borth_status borth_create(borth_ctx* out, int device, void* stream) {
+  if (!out) return BORTH_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return BORTH_ERR_ARG;
+  borth_ctx c = new borth_ctx_s();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->cur = c->stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return BORTH_ERR_HIP;
+  }
+  const WsLayout W = ws_layout();
+  if (ensure(c, &c->ws, &c->ws_cap, W.total) != BORTH_OK || ensure_status(c, 64) != BORTH_OK) {
+    borth_destroy(c);
+    return BORTH_ERR_NOMEM;
+  }
+  *out = c;
+  return BORTH_OK;
+}
+
+borth_status borth_destroy(borth_ctx c) {
+  if (!c) return BORTH_ERR_ARG;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  invalidate_graphs(c);
+  if (c->part) hipFree(c->part);
+  if (c->ws) hipFree(c->ws);
+  if (c->status) hipFree(c->status);
+  if (c->h_status) hipHostFree(c->h_status);
+  if (c->batch_mem) hipFree(c->batch_mem);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  for (auto& p : c->ev_free) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+  for (int k = 0; k < 2; ++k)
+    for (auto& p : c->ev_used[k]) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+  delete c;
+  return BORTH_OK;
+}
+
+borth_status borth_set_stream(borth_ctx c, void* stream) {
+  if (!c) return BORTH_ERR_ARG;
+  if (c->stream == (hipStream_t)stream) return BORTH_OK;
+  c->stream = (hipStream_t)stream;
+  c->cur = c->stream;
+  return BORTH_OK;
+}
+
+const char* borth_last_error(borth_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+borth_status borth_get_info(borth_ctx c, borth_info* info) {
+  if (!c || !info) return BORTH_ERR_ARG;
+  hipSetDevice(c->device);
+  read_status(c, info);
+  return BORTH_OK;
+}
+
+borth_status borth_gram(borth_ctx c, int64_t m, int ka, const double* A, int64_t lda, int kb,
+                        borth_dtype dt_b, const void* B, int64_t ldb, int prec, double* G_hi,
+                        double* G_lo) {
+  if (!c) return BORTH_ERR_ARG;
+  if (m < 0 || ka < 0 || kb < 1 || ka + kb > 128 || !B || !G_hi) return fail_arg(c, "shape/pointers");
+  if (ka > 0 && (!A || lda < ka)) return fail_arg(c, "A");
+  if (ldb < kb) return fail_arg(c, "ldb");
+  if (prec < 0 || prec > 2) return fail_arg(c, "prec");
+  if (prec == BORTH_GRAM_SPLIT_BF16 && (dt_b != BORTH_F32 || ka != 0 || kb > 64))
+    return fail_arg(c, "split mode needs fp32 B, no A, kb <= 64");
+  if (prec != BORTH_GRAM_SPLIT_BF16 && dt_b == BORTH_F32 && prec == BORTH_GRAM_DD)
+    return fail_arg(c, "DD Gram needs binary64 input");
+  hipSetDevice(c->device);
+  c->cur = c->stream;
+  GramLayout L = make_layout(ka, kb, 4);
+  borth_status r = ensure(c, &c->part, &c->part_cap, 1024 * (int64_t)L.E * 2);
+  if (r) return r;
+  int nwg = 0;
+  const int kp = pow2pad(kb);
+  if (prec == BORTH_GRAM_SPLIT_BF16) {
+    Src s{nullptr, 0, B, ldb, 1, m};
+    prof_begin(c, 0);
+    HIPCHK(c, launch_gram_split(s, L, c->part, c->part_cap, &nwg, lookup(c->tune_gram, 2, kp, 0), c->stream), "gram_split");
+    prof_end(c, 0);
+    HIPCHK(c, launch_reduce(L, 0, c->part, nwg, G_hi, G_lo, c->stream), "reduce");
+  } else {
+    Src s{A, lda, B, ldb, dt_b == BORTH_F32 ? 1 : 0, m};
+    const int mode = prec == BORTH_GRAM_DD ? 1 : 0;
+    prof_begin(c, 0);
+    HIPCHK(c, launch_gram(s, L, mode, c->part, c->part_cap, &nwg, lookup(c->tune_gram, mode, kp, ka > 0), c->stream), "gram");
+    prof_end(c, 0);
+    HIPCHK(c, launch_reduce(L, mode, c->part, nwg, G_hi, G_lo, c->stream), "reduce");
+  }
+  return BORTH_OK;
+}
+
+borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const double* G_lo,
+                          int fact, double shift, double* Z, double* R, double* C,
+                          borth_info* info) {
+  if (!c) return BORTH_ERR_ARG;
+  if (k < 1 || k > 64 || ky < 0 || ky > 64 || !G_hi) return fail_arg(c, "shape");
+  if (fact != BORTH_CHOL && fact != BORTH_SVQB) return fail_arg(c, "fact");
+  if (fact == BORTH_SVQB && G_lo) return fail_arg(c, "SVQB runs in binary64 (pass G_lo = NULL)");
+  hipSetDevice(c->device);
+  c->cur = c->stream;
+  const WsLayout W = ws_layout();
+  HIPCHK(c, launch_fill_int(c->status, 4, 0, c->stream), "fill");
+  FactorArgs f;
+  memset(&f, 0, sizeof(f));
+  f.ky = ky;
+  f.k = k;
+  f.kp = pow2pad(k);
+  f.G_hi = G_hi;
+  f.G_lo = G_lo;
+  f.dd = G_lo ? 1 : 0;
+  f.fact = fact;
+  f.shift_rel = shift > 0 ? shift : 0.0;
+  f.pass = 0;
+  f.Zp = c->ws + W.zp[0];
+  f.Cp = c->ws + W.cp[0];
+  f.Rtot = c->ws + W.rtot;
+  f.Ctot = c->ws + W.ctot;
+  f.status = c->status;
+  f.R_out = R;
+  f.C_out = C;
+  f.Z_out = Z;
+  HIPCHK(c, launch_factor(f, c->stream), "factor");
+  if (info) return read_status(c, info);
+  return BORTH_OK;
+}
+
+borth_status borth_update(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
+                          int64_t ldx, const double* Y, int64_t ldy, int ky, const double* C,
+                          const double* Z, int z_dense, double* Q, int64_t ldq) {
+  if (!c) return BORTH_ERR_ARG;
+  if (m < 0 || k < 1 || k > 64 || ky < 0 || ky > 64) return fail_arg(c, "shape");
+  if (!X || !Z || !Q || ldx < k || ldq < k) return fail_arg(c, "pointers/ld");
+  if (ky > 0 && (!Y || !C || ldy < ky)) return fail_arg(c, "Y/C");
+  if (dt == BORTH_F32 && ky > 0) return fail_arg(c, "fp32 X with a locked basis is not supported");
+  if ((const void*)Q == X && (dt != BORTH_F64 || ldq != ldx)) return fail_arg(c, "aliasing");
+  hipSetDevice(c->device);
+  c->cur = c->stream;
+  const WsLayout W = ws_layout();
+  const int kp = pow2pad(k);
+  double* zp = c->ws + W.zu;
+  double* cp = c->ws + W.cu;
+  HIPCHK(c, launch_fill_int((int*)zp, 2 * 64 * 64, 0, c->stream), "zero Z");
+  HIPCHK(c, launch_fill_int((int*)cp, 2 * 64 * 64, 0, c->stream), "zero C");
+  borth_status r = pad_copy(c, zp, kp, Z, k, k);
+  if (r) return r;
+  if (ky > 0 && (r = pad_copy(c, cp, kp, C, k, ky))) return r;
+  UpdateArgs u;
+  memset(&u, 0, sizeof(u));
+  u.src = Src{Y, ldy, X, ldx, dt == BORTH_F32 ? 1 : 0, m};
+  u.C1 = cp;
+  u.Z1 = zp;
+  u.dense = z_dense ? 1 : 0;
+  u.Q = Q;
+  u.ldq = ldq;
+  GramLayout L = make_layout(ky, k, kp);
+  prof_begin(c, 1);
+  HIPCHK(c, launch_update(u, L, lookup(c->tune_upd, 0, kp, ky > 0), c->stream), "update");
+  prof_end(c, 1);
+  return BORTH_OK;
+}
+
+borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
+                                  int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
+                                  int64_t ldq, double* R, double* C, const borth_opts* opts,
+                                  borth_info* info) {
+  if (!c) return BORTH_ERR_ARG;
+  borth_opts o;
+  if (opts) o = *opts; else borth_default_opts(&o);
+  if (k < 1 || k > 64 || ky < 0 || ky > 64 || m < (int64_t)k + ky) return fail_arg(c, "shape");
+  if (!X || !Q || ldx < k || ldq < k) return fail_arg(c, "X/Q");
+  if (ky > 0 && (!Y || ldy < ky)) return fail_arg(c, "Y");
+  if (o.passes < 1 || o.passes > 3) return fail_arg(c, "passes");
+  if (o.gram < 0 || o.gram > 2 || (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB)) return fail_arg(c, "opts");
+  if (o.gram == BORTH_GRAM_SPLIT_BF16 && (dt != BORTH_F32 || ky > 0))
+    return fail_arg(c, "split mode needs fp32 X and no locked basis");
+  if (o.gram != BORTH_GRAM_SPLIT_BF16 && dt == BORTH_F32) return fail_arg(c, "fp32 X needs the split mode");
+  if (o.fact == BORTH_SVQB && o.gram == BORTH_GRAM_DD) {
+    c->err = "SVQB runs in binary64 in this build";
+    return BORTH_ERR_UNSUPPORTED;
+  }
+  if ((const void*)Q == X) {
+    if (dt != BORTH_F64 || ldq != ldx) return fail_arg(c, "aliasing");
+    if (o.sched == BORTH_SCHED_RECOMPUTE) return fail_arg(c, "recompute schedule cannot run in place");
+  }
+  if (ky > 16 && o.passes > 1 && !(o.flags & BORTH_FLAG_PROJECT_ONCE)) {
+    c->err = "fused Gram with a locked basis supports ky <= 16";
+    return BORTH_ERR_UNSUPPORTED;
+  }
+  if (o.sched == BORTH_SCHED_RECOMPUTE && (dt != BORTH_F64 || o.passes != 2)) return fail_arg(c, "recompute needs binary64 X and 2 passes");
+  hipSetDevice(c->device);
+  borth_status r = ensure(c, &c->part, &c->part_cap, partial_need(ky, k, o.gram));
+  if (r) return r;
+  OrthoCall a{m, k, ky, dt, X, ldx, Y, ldy, Q, ldq, R, C, o};
+  if (o.flags & BORTH_FLAG_GRAPH) {
+    GraphKey key;
+    key.v = {m, k, ky, (int64_t)dt, (int64_t)(intptr_t)X, ldx, (int64_t)(intptr_t)Y, ldy,
+             (int64_t)(intptr_t)Q, ldq, (int64_t)(intptr_t)R, (int64_t)(intptr_t)C, o.gram, o.fact,
+             o.passes, o.sched, (int64_t)(o.shift * 1e18), (int64_t)o.flags,
+             (int64_t)c->ws_generation};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      if (!c->cap_stream)
+        HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+      HIPCHK(c, hipStreamSynchronize(c->stream), "sync before capture");
+      c->capturing = true;
+      c->cur = c->cap_stream;
+      HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
+      r = enqueue_ortho(c, a);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+      c->capturing = false;
+      c->cur = c->stream;
+      if (r) { if (g) hipGraphDestroy(g); return r; }
+      if (e != hipSuccess) return fail_hip(c, e, "hipStreamEndCapture");
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return fail_hip(c, e, "hipGraphInstantiate");
+      it = c->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream), "hipGraphLaunch");
+  } else {
+    c->cur = c->stream;
+    r = enqueue_ortho(c, a);
+    if (r) return r;
+  }
+  if (info || (o.flags & BORTH_FLAG_SYNC)) return read_status(c, info);
+  return BORTH_OK;
+}
+
+borth_status borth_set_profiling(borth_ctx c, int on) {
+  if (!c) return BORTH_ERR_ARG;
+  hipStreamSynchronize(c->stream);
+  for (int k = 0; k < 2; ++k) {
+    for (auto& p : c->ev_used[k]) c->ev_free.push_back(p);
+    c->ev_used[k].clear();
+  }
+  c->prof = on != 0;
+  return BORTH_OK;
+}
+
+borth_status borth_kernel_time(borth_ctx c, int kind, double* avg_ms, int* count) {
+  if (!c || kind < 0 || kind > 1 || !avg_ms) return BORTH_ERR_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+  double tot = 0.0;
+  int n = 0;
+  for (auto& p : c->ev_used[kind]) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      tot += ms;
+      ++n;
+    }
+  }
+  *avg_ms = n ? tot / n : 0.0;
+  if (count) *count = n;
+  return BORTH_OK;
+}
+
+borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_block* blocks,
+                                        const borth_opts* opts, borth_info* infos) {
+  (void)nblocks; (void)blocks; (void)opts; (void)infos;
+  if (!c) return BORTH_ERR_ARG;
+  c->err = "batched path not built yet";
+  return BORTH_ERR_UNSUPPORTED;
+}
+
+borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) {
+  (void)cache_path; (void)budget_ms;
+  if (!c) return BORTH_ERR_ARG;
+  c->err = "autotuner not built yet";
+  return BORTH_ERR_UNSUPPORTED;
+}
+
+borth_status borth_autotune_load(borth_ctx c, const char* cache_path) {
+  (void)cache_path;
+  if (!c) return BORTH_ERR_ARG;
+  c->err = "autotuner not built yet";
+  return BORTH_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,373 @@
+// Gram sweeps (TSMTTSM): G = V^T V for the tall-skinny V = [Y | X].
+//
+// The Gram matrix is "the bulk of computation" of the orthogonalization
+// (Sec. 4.2); for a few columns it is bound by the HBM stream.  Three
+// kernels, all writing per-workgroup partials in one shared layout (4x4
+// tiles of the upper triangle, see GramLayout) that a fixed-order reduction
+// turns into G:
+//
+//  gram_mfma_kernel   binary64 on the matrix cores, v_mfma_f64_16x16x4:
+//                     each wave streams 4-row groups straight from HBM into
+//                     registers; lane l holds V[r0 + l/16][16 I + l%16], which
+//                     is both the A operand of tile row I and the B operand of
+//                     tile column I, so a 16x16 tile of G costs one MFMA per
+//                     4 rows and no LDS traffic.
+//  gram_tiles_kernel  binary64 or double-double on the vector ALUs: row panels
+//                     are staged in LDS with coalesced loads, each thread owns
+//                     a 4x4 tile of G (and a row phase) and accumulates it;
+//                     the DD variant uses the 8-instruction Dot2 step (dd.hpp).
+//  reduce_kernel      sums the partials in workgroup order (DD additions in DD
+//                     mode) -- no floating-point atomics, so every result is
+//                     bitwise reproducible.
+#include "dd.hpp"
+#include "internal.hpp"
+
+namespace borth {
+
+GramLayout make_layout(int ky, int k, int kp_min) {
+  GramLayout L;
+  L.ky = ky;
+  L.kyp = (ky + 3) & ~3;
+  L.k = k;
+  int kp = (k + 3) & ~3;
+  L.kp = kp < kp_min ? kp_min : kp;
+  L.Wp = L.kyp + L.kp;
+  L.T4 = L.Wp / 4;
+  L.ntiles = L.T4 * (L.T4 + 1) / 2;
+  L.E = 16 * L.ntiles;
+  return L;
+}
+
+__device__ __forceinline__ void decode_tile(int t, int T4, int& ti, int& tj) {
+  int r = 0, base = 0;
+  while (t >= base + (T4 - r)) {
+    base += T4 - r;
+    ++r;
+  }
+  ti = r;
+  tj = r + (t - base);
+}
+
+__device__ __forceinline__ int tile_index(int ti, int tj, int T4) {
+  return ti * T4 - (ti * (ti - 1)) / 2 + (tj - ti);
+}
+
+// Element (row, c) of the padded [Y | X] block (zero outside).
+__device__ __forceinline__ double fetch(const Src& s, const GramLayout& L, int64_t row, int c) {
+  if (row >= s.m) return 0.0;
+  if (c < L.kyp) return c < L.ky ? s.Y[row * s.ldy + c] : 0.0;
+  const int j = c - L.kyp;
+  if (j >= L.k) return 0.0;
+  return s.x_f32 ? (double)(((const float*)s.X)[row * s.ldx + j])
+                 : ((const double*)s.X)[row * s.ldx + j];
+}
+
+// ---------------------------------------------------------------------------
+// VALU tile kernel (binary64 or DD).
+constexpr int kMaxQ = 12;  // reduction entries per thread
+
+template <bool DD>
+__global__ void __launch_bounds__(1024) gram_tiles_kernel(Src s, GramLayout L, int P,
+                                                          int64_t npanels, int S,
+                                                          double* __restrict__ part) {
+  extern __shared__ double lds[];
+  const int stride = L.Wp + 2;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int nt = L.ntiles;
+  const bool active = tid < nt * S;
+  const int t = active ? tid % nt : 0;
+  const int phase = active ? tid / nt : 0;
+  int ti, tj;
+  decode_tile(t, L.T4, ti, tj);
+
+  double acs[16], acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    acs[e] = 0.0;
+    acc[e] = 0.0;
+  }
+
+  for (int64_t pnl = blockIdx.x; pnl < npanels; pnl += gridDim.x) {
+    const int64_t row0 = pnl * P;
+    __syncthreads();
+    for (int idx = tid; idx < P * L.Wp; idx += NT) {
+      const int r = idx / L.Wp, c = idx - r * L.Wp;
+      lds[r * stride + c] = fetch(s, L, row0 + r, c);
+    }
+    __syncthreads();
+    if (active) {
+      for (int r = phase; r < P; r += S) {
+        const double* row = lds + r * stride;
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = row[4 * ti + i];
+          b[i] = row[4 * tj + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (DD)
+              dot2_step(acs[4 * i + j], acc[4 * i + j], a[i], b[j]);
+            else
+              acs[4 * i + j] = __builtin_fma(a[i], b[j], acs[4 * i + j]);
+          }
+      }
+    }
+  }
+
+  // Combine the row phases in phase order, then write this WG's partial.
+  __syncthreads();
+  double* red = lds;
+  const int E = L.E;
+  double sh[kMaxQ], sl[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    sh[q] = 0.0;
+    sl[q] = 0.0;
+  }
+  for (int ph = 0; ph < S; ++ph) {
+    if (active && phase == ph) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        if (DD) {
+          const dd_t v = dot2_finish(acs[e], acc[e]);
+          red[2 * (t * 16 + e)] = v.hi;
+          red[2 * (t * 16 + e) + 1] = v.lo;
+        } else {
+          red[t * 16 + e] = acs[e];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kMaxQ; ++q) {
+      const int e = tid + q * NT;
+      if (e < E) {
+        if (DD) {
+          const dd_t v = dd_add(dd_make(sh[q], sl[q]), dd_make(red[2 * e], red[2 * e + 1]));
+          sh[q] = v.hi;
+          sl[q] = v.lo;
+        } else {
+          sh[q] += red[e];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * E * (DD ? 2 : 1);
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    const int e = tid + q * NT;
+    if (e < E) {
+      if (DD) {
+        out[2 * e] = sh[q];
+        out[2 * e + 1] = sl[q];
+      } else {
+        out[e] = sh[q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// binary64 MFMA kernel: T = padded width / 16 column blocks.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+template <int T, int U>
+__global__ void __launch_bounds__(256) gram_mfma_kernel(Src s, GramLayout L, int64_t ngroups,
+                                                        double* __restrict__ part) {
+  constexpr int NTL = T * (T + 1) / 2;
+  __shared__ double red[NTL * 4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int c = lane & 15, rsub = lane >> 4;
+  d4_t acc[NTL];
+#pragma unroll
+  for (int i = 0; i < NTL; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t gstride = (int64_t)gridDim.x * nw;
+  int64_t g = (int64_t)blockIdx.x * nw + wave;
+  for (; g < ngroups; g += U * gstride) {
+    double v[U][T];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t gg = g + u * gstride;
+      const int64_t row = (gg < ngroups) ? gg * 4 + rsub : s.m;
+#pragma unroll
+      for (int I = 0; I < T; ++I) v[u][I] = fetch(s, L, row, 16 * I + c);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int idx = 0;
+#pragma unroll
+      for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = I; J < T; ++J) {
+          acc[idx] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][I], v[u][J], acc[idx], 0, 0, 0);
+          ++idx;
+        }
+    }
+  }
+
+  // Fixed-order cross-wave sum into wave 0.
+  for (int w = 1; w < nw; ++w) {
+    __syncthreads();
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < NTL; ++i)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) red[(i * 4 + vv) * 64 + lane] = acc[i][vv];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int i = 0; i < NTL; ++i)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) acc[i][vv] += red[(i * 4 + vv) * 64 + lane];
+    }
+  }
+  if (wave != 0) return;
+  double* out = part + (int64_t)blockIdx.x * L.E;
+  int idx = 0;
+#pragma unroll
+  for (int I = 0; I < T; ++I)
+#pragma unroll
+    for (int J = I; J < T; ++J) {
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        // D layout of v_mfma_f64_16x16x4: lane l, register vv holds
+        // D[l / 16 + 4 vv][l % 16].
+        const int gi = 16 * I + rsub + 4 * vv;
+        const int gj = 16 * J + c;
+        if (gi < L.Wp && gj < L.Wp && (gi >> 2) <= (gj >> 2)) {
+          const int e = tile_index(gi >> 2, gj >> 2, L.T4) * 16 + (gi & 3) * 4 + (gj & 3);
+          out[e] = acc[idx][vv];
+        }
+      }
+      ++idx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <bool DD>
+__global__ void __launch_bounds__(1024) reduce_kernel(GramLayout L, const double* __restrict__ part,
+                                                      int nwg, double* __restrict__ Ghi,
+                                                      double* __restrict__ Glo) {
+  __shared__ double sh[16][64], sl[16][64];
+  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
+  const int E = L.E;
+  double h = 0.0, l = 0.0;
+  if (e < E) {
+    for (int w = g; w < nwg; w += 16) {
+      if (DD) {
+        const dd_t v = dd_add(dd_make(h, l), dd_make(part[((int64_t)w * E + e) * 2],
+                                                      part[((int64_t)w * E + e) * 2 + 1]));
+        h = v.hi;
+        l = v.lo;
+      } else {
+        h += part[(int64_t)w * E + e];
+      }
+    }
+  }
+  sh[g][el] = h;
+  sl[g][el] = l;
+  __syncthreads();
+  if (g != 0 || e >= E) return;
+  for (int q = 1; q < 16; ++q) {
+    if (DD) {
+      const dd_t v = dd_add(dd_make(h, l), dd_make(sh[q][el], sl[q][el]));
+      h = v.hi;
+      l = v.lo;
+    } else {
+      h += sh[q][el];
+    }
+  }
+  const int t = e >> 4, a = (e >> 2) & 3, b = e & 3;
+  int ti, tj;
+  decode_tile(t, L.T4, ti, tj);
+  const int pi = 4 * ti + a, pj = 4 * tj + b;
+  if (pi > pj) return;  // lower half of a diagonal tile: written by its mirror
+  auto logical = [&](int p) -> int {
+    if (p < L.kyp) return p < L.ky ? p : -1;
+    const int j = p - L.kyp;
+    return j < L.k ? L.ky + j : -1;
+  };
+  const int li = logical(pi), lj = logical(pj);
+  if (li < 0 || lj < 0) return;
+  const int W = L.ky + L.k;
+  Ghi[li * W + lj] = h;
+  Ghi[lj * W + li] = h;
+  if (Glo) {
+    Glo[li * W + lj] = DD ? l : 0.0;
+    Glo[lj * W + li] = DD ? l : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+static int tiles_threads(int ntiles) { return ntiles <= 40 ? 256 : 1024; }
+
+hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* partials,
+                       int64_t cap, int* nwg_out, const TuneGram& tune, hipStream_t st) {
+  const int W16 = (L.Wp + 15) / 16;
+  const bool use_mfma = (mode == 0) && L.Wp >= 16 && W16 <= 5;
+  if (use_mfma) {
+    const int64_t ngroups = (s.m + 3) / 4;
+    int nwg = tune.nwg > 0 ? tune.nwg : 1024;
+    const int64_t need = (ngroups + 3) / 4;
+    if (nwg > need) nwg = (int)(need > 0 ? need : 1);
+    if ((int64_t)nwg * L.E > cap) return hipErrorInvalidValue;
+    GramLayout LL = L;
+    switch (W16) {
+      case 1: hipLaunchKernelGGL((gram_mfma_kernel<1, 4>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
+      case 2: hipLaunchKernelGGL((gram_mfma_kernel<2, 4>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
+      case 3: hipLaunchKernelGGL((gram_mfma_kernel<3, 2>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
+      case 4: hipLaunchKernelGGL((gram_mfma_kernel<4, 2>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
+      default: hipLaunchKernelGGL((gram_mfma_kernel<5, 2>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
+    }
+    *nwg_out = nwg;
+    return hipGetLastError();
+  }
+  const int NT = tiles_threads(L.ntiles);
+  const int S = NT / L.ntiles;
+  if (S < 1) return hipErrorInvalidValue;
+  if (L.E > kMaxQ * NT) return hipErrorInvalidValue;
+  int P = tune.rows > 0 ? tune.rows : 2048 / L.Wp;
+  if (P < 4) P = 4;
+  const int64_t npanels = (s.m + P - 1) / P;
+  int nwg = tune.nwg > 0 ? tune.nwg : 1024;
+  if (nwg > npanels) nwg = (int)(npanels > 0 ? npanels : 1);
+  if ((int64_t)nwg * L.E * (mode ? 2 : 1) > cap) return hipErrorInvalidValue;
+  const int panel = P * (L.Wp + 2);
+  const int redn = L.E * (mode ? 2 : 1);
+  const size_t shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
+  if (mode == 1)
+    hipLaunchKernelGGL(gram_tiles_kernel<true>, dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
+  else
+    hipLaunchKernelGGL(gram_tiles_kernel<false>, dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
+  *nwg_out = nwg;
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
+                         double* G_hi, double* G_lo, hipStream_t st) {
+  const int nb = (L.E + 63) / 64;
+  if (mode == 1)
+    hipLaunchKernelGGL(reduce_kernel<true>, dim3(nb), dim3(1024), 0, st, L, partials, nwg, G_hi, G_lo);
+  else
+    hipLaunchKernelGGL(reduce_kernel<false>, dim3(nb), dim3(1024), 0, st, L, partials, nwg, G_hi, G_lo);
+  return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace borth

@@ -1,0 +1,408 @@
+"""GPU parity tests: every step of the HIP path against the CPU oracle.
+
+Tolerances (derived from the arithmetic, stated per test):
+* binary64 Gram: elementwise |dG_ij| <= gamma_n (|X|^T|X|)_ij with n the
+  longest serial accumulation chain of the kernels (rows per accumulator plus
+  the fixed reduction tree), and normwise ||dG||_F / ||G||_F <= 1e-14.
+* DD Gram: elementwise |dG_ij| <= gamma_n^2 (|X|^T|X|)_ij + 4u^2 |G_ij| (Dot2
+  bound) and normwise <= 1e-28.
+* update: |dQ_ij| <= (2(k + ky) + 2) u ((|X| + |Y||C|)|Z|)_ij.
+* end to end: reconstruction rho and orthogonality omega <= 1e-14 where the
+  method guarantees it; bitwise equality on the exact Hadamard families.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import U64, dev, host, lib, note, rel_fro, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def gamma(n):
+    return n * U64 / (1 - n * U64)
+
+
+def chain(m):
+    return m // 4 + 1100
+
+
+# ---------------------------------------------------------------------------
+# a2: Gram sweeps
+
+@pytest.mark.parametrize("m,k,ky", [(5003, 4, 0), (5003, 8, 0), (5003, 16, 0), (5003, 20, 0),
+                                    (7001, 32, 0), (7001, 64, 0), (5003, 8, 5), (6007, 32, 16),
+                                    (3001, 64, 16), (1, 3, 0), (17, 1, 0)])
+@pytest.mark.parametrize("prec", ["f64", "dd"])
+def test_gram_vs_oracle(m, k, ky, prec):
+    borth = lib()
+    note("gram", m, k, ky, prec)
+    rng = np.random.default_rng(1000 + m + k + ky)
+    X = rng.standard_normal((m, k)) * np.ldexp(1.0, rng.integers(-3, 3, (1, k)))
+    Y = rng.standard_normal((m, ky)) if ky else None
+    V = X if Y is None else np.hstack([Y, X])
+    ghi, glo = borth.gram(dev(X), None if Y is None else dev(Y), prec=prec)
+    ghi = host(ghi)
+    glo = host(glo) if glo is not None else np.zeros_like(ghi)
+    ex_hi, ex_lo = oracle.gram_q(V)
+    absg = np.abs(V).T @ np.abs(V)
+    err = np.abs((ghi - ex_hi) + (glo - ex_lo))
+    if prec == "f64":
+        assert np.all(err <= gamma(chain(m)) * absg + 1e-300)
+        assert rel_fro(ghi, ex_hi + ex_lo) <= 1e-14
+    else:
+        assert np.all(err <= gamma(chain(m)) ** 2 * absg + 4 * U64 ** 2 * np.abs(ex_hi))
+        assert np.linalg.norm(err) <= 1e-28 * np.linalg.norm(ex_hi)
+    assert np.array_equal(ghi, ghi.T)
+
+
+def test_gram_strided_and_deterministic():
+    borth = lib()
+    torch = torch_gpu()
+    rng = np.random.default_rng(7)
+    big = rng.standard_normal((9000, 40))
+    Xd = dev(big)[:, 3:35]  # ld = 40, k = 32
+    g1, l1 = borth.gram(Xd, prec="dd")
+    g2, l2 = borth.gram(Xd, prec="dd")
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+    ex_hi, ex_lo = oracle.gram_q(big[:, 3:35])
+    assert np.linalg.norm(host(g1) - ex_hi + host(l1) - ex_lo) <= 1e-28 * np.linalg.norm(ex_hi)
+
+
+def test_gram_near_parallel_dd_exact():
+    """Exact Gram [[1,1],[1,1+2^-80]]: the DD sweep must return it exactly;
+    a contracted TwoSum would lose the 2^-80."""
+    borth = lib()
+    X = synth.hadamard_near_parallel(8, 4, 40)
+    ghi, glo = borth.gram(dev(X), prec="dd")
+    ex_hi, ex_lo = oracle.gram_q(X)
+    assert np.array_equal(host(ghi), ex_hi) and np.array_equal(host(glo), ex_lo)
+
+
+def test_gram_split_bf16_vs_oracle():
+    """Split-BF16 Gram: within 3 * 2^-16 (dropped l*l term and unsplit remainder)
+    of the exact Gram, and within fp32-accumulation noise of the oracle's
+    split model."""
+    borth = lib()
+    torch = torch_gpu()
+    m, k = 40000, 64
+    X = synth.svd_matrix(m, k, 1e3, 401).astype(np.float32)
+    X64 = X.astype(np.float64)
+    ghi, _ = borth.gram(dev(X), prec="split")
+    g = host(ghi)
+    ex = oracle.gram_q(X64)[0]
+    absg = np.abs(X64).T @ np.abs(X64)
+    assert np.all(np.abs(g - ex) <= 4 * 2.0 ** -16 * absg)
+    model = oracle.gram_split_bf16(X, chunk=32)
+    assert np.all(np.abs(g - model) <= (96 + 32) * 2.0 ** -24 * absg)
+    # not the plain product: a missing cross term would be ~2^-8 off
+    assert np.max(np.abs(g - ex) / absg) > 1e-9
+
+
+# ---------------------------------------------------------------------------
+# a3: small factorization
+
+@pytest.mark.parametrize("k,ky,kappa,dd", [(8, 0, 1e3, False), (32, 0, 1e3, False),
+                                           (64, 0, 1e3, False), (32, 0, 1e12, True),
+                                           (64, 0, 1e14, True), (20, 16, 1e6, True),
+                                           (33, 7, 1e4, False)])
+def test_factor_vs_oracle(k, ky, kappa, dd):
+    borth = lib()
+    note("factor", k, ky, kappa, dd)
+    m = 4000
+    X = synth.svd_matrix(m, k, kappa, 300 + k)
+    Y = synth.locked_basis(m, ky, 99) if ky else None
+    V = X if Y is None else np.hstack([Y, X])
+    ghi, glo = oracle.gram_q(V)
+    Z, R, C, info = borth.factor(dev(ghi), dev(glo) if dd else None, ky=ky)
+    assert info.status == 0
+    Z, R, C = host(Z), host(R), host(C)
+    # oracle: exact M = Xt^T Xt of the projected block, its Cholesky and inverse
+    o = oracle.qr_q(X, Y, want_gram=True)
+    rex, _, inf2 = oracle.chol_q(o["G_hi"], o["G_lo"])
+    assert inf2 == 0
+    zex, _ = oracle.trinv_q(rex)
+    # backward error of the returned R (binary64 words): ||R^T R - M|| / ||M||
+    # <= 2 (k + 1) sqrt(k) u  (Cholesky backward stability + output rounding)
+    rtr_hi, rtr_lo = oracle.gram_q(R)
+    bw = np.linalg.norm(rtr_hi - o["G_hi"] + (rtr_lo - o["G_lo"])) / np.linalg.norm(o["G_hi"])
+    assert bw <= 2 * (k + 1) * np.sqrt(k) * U64, bw
+    # forward errors: worst case kappa(M) times the working precision
+    uw = 2.0 ** -104 if dd else U64
+    tol = 10 * k * (U64 + kappa ** 2 * uw)
+    assert rel_fro(R, rex) <= tol, rel_fro(R, rex)
+    assert rel_fro(Z, zex) <= tol * kappa, rel_fro(Z, zex)
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.tril(Z, -1) == 0)
+    if ky:
+        assert np.array_equal(C, (ghi + glo)[:ky, ky:]) or rel_fro(C, ghi[:ky, ky:]) <= 1e-15
+
+
+def test_factor_breakdown_pivot():
+    borth = lib()
+    G = np.array([[4.0, 2.0, 1.0], [2.0, 1.0, 3.0], [1.0, 3.0, 9.0]])
+    _, _, _, info = borth.factor(dev(G), None, check=False)
+    assert info.status == 4 and info.failed_pivot == 2
+    G2 = G.copy()
+    G2[0, 0] = np.nan
+    _, _, _, info = borth.factor(dev(G2), None, check=False)
+    assert info.status == 5
+
+
+def test_factor_svqb_vs_oracle():
+    borth = lib()
+    m, k = 3000, 16
+    X = synth.svd_matrix(m, k, 1e4, 55)
+    ghi, glo = oracle.gram_q(X)
+    Z, R, _, info = borth.factor(dev(ghi + glo), None, fact="svqb")
+    assert info.status == 0
+    zex, lam, _ = oracle.svqb_q(ghi, glo)
+    assert rel_fro(host(Z), zex) <= 1e-15 * 1e8 * 10  # kappa(M) u
+    assert np.allclose(host(Z), host(Z).T, rtol=0, atol=1e-12 * np.abs(zex).max())
+
+
+# ---------------------------------------------------------------------------
+# a4: update sweep
+
+@pytest.mark.parametrize("m,k,ky,dense", [(5003, 4, 0, False), (5003, 8, 3, False),
+                                          (7001, 16, 16, False), (7001, 32, 0, False),
+                                          (3001, 64, 16, False), (4099, 20, 5, True),
+                                          (1, 5, 0, False)])
+def test_update_vs_oracle(m, k, ky, dense):
+    borth = lib()
+    note("update", m, k, ky, dense)
+    rng = np.random.default_rng(2000 + m + k)
+    X = rng.standard_normal((m, k))
+    Y = rng.standard_normal((m, ky)) if ky else None
+    C = rng.standard_normal((ky, k)) if ky else None
+    Z = rng.standard_normal((k, k))
+    if not dense:
+        Z = np.triu(Z)
+    Q = host(borth.update(dev(X), dev(Z), None if Y is None else dev(Y),
+                          None if C is None else dev(C), dense=dense))
+    ex = oracle.update_q(X, Z, Y, C)
+    mag = np.abs(X) + (np.abs(Y) @ np.abs(C) if ky else 0)
+    bound = (2 * (k + ky) + 2) * U64 * (mag @ np.abs(Z)) + U64 * np.abs(ex)
+    assert np.all(np.abs(Q - ex) <= bound)
+
+
+def test_update_inplace_and_fp32():
+    borth = lib()
+    torch = torch_gpu()
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((3001, 32))
+    Z = np.triu(rng.standard_normal((32, 32)))
+    Xd = dev(X)
+    borth.update(Xd, dev(Z), out=Xd)
+    ex = oracle.update_q(X, Z)
+    assert np.max(np.abs(host(Xd) - ex)) <= 100 * U64 * np.max(np.abs(X) @ np.abs(Z))
+    X32 = X.astype(np.float32)
+    Q = borth.update(dev(X32), dev(Z))
+    ex32 = oracle.update_q(X32.astype(np.float64), Z)
+    assert np.max(np.abs(host(Q) - ex32)) <= 100 * U64 * np.max(np.abs(X) @ np.abs(Z))
+
+
+# ---------------------------------------------------------------------------
+# a5: the whole path
+
+@pytest.mark.parametrize("gram,passes,sched,fact", [
+    ("f64", 1, "auto", "chol"), ("f64", 2, "recompute", "chol"), ("f64", 2, "materialize", "chol"),
+    ("dd", 1, "auto", "chol"), ("dd", 2, "recompute", "chol"), ("dd", 2, "materialize", "chol"),
+    ("dd", 3, "materialize", "chol"), ("f64", 2, "materialize", "svqb"), ("f64", 1, "auto", "svqb")])
+def test_hadamard_bitwise(gram, passes, sched, fact):
+    """X = H diag(2^e): exact Q = H, R = diag(2^e); every unshifted mode must
+    return them bitwise (all sums, square roots and inverses are exact)."""
+    borth = lib()
+    # SVQB lifts eigenvalues below 2^-52 lambda_max (rank rule): keep the
+    # scale range inside it for SVQB; Cholesky takes the full 2^61 range.
+    exps = [0, -3, 7, -20, 11, -35, 2, -50] if fact == "chol" else [0, -3, 7, -9, 11, -5, 2, -12]
+    X = synth.hadamard_scaled(7, exps)
+    H = synth.hadamard_columns(7, range(1, 1 + len(exps)))
+    Q, R, _, info = borth.orthonormalize(dev(X), gram=gram, passes=passes, sched=sched, fact=fact)
+    assert info.status == 0
+    assert np.array_equal(host(Q), H)
+    assert np.array_equal(host(R), np.diag(np.ldexp(1.0, exps)))
+
+
+def test_hadamard_projection_bitwise():
+    borth = lib()
+    j = 6
+    Y = synth.hadamard_columns(j, [40, 41, 42, 43])
+    H = synth.hadamard_columns(j, [1, 2, 3])
+    Cex = np.array([[1.0, -2.0, 0.5], [0.25, 3.0, 0.0], [1.0, 1.0, 1.0], [0.0, -4.0, 2.0]])
+    X = H * 8.0 + Y @ Cex
+    for gram in ("f64", "dd"):
+        Q, R, C, info = borth.orthonormalize(dev(X), dev(Y), gram=gram)
+        assert info.status == 0
+        assert np.array_equal(host(Q), H) and np.array_equal(host(R), 8.0 * np.eye(3))
+        assert np.array_equal(host(C), Cex)
+
+
+def test_near_parallel_dd_vs_f64():
+    """kappa ~ 2^41: DD CholQR2 returns the exact Q within a few ulps; the
+    binary64 Gram cannot hold 1 + 2^-80, so plain CholQR breaks down or is
+    far from orthogonal."""
+    borth = lib()
+    X = synth.hadamard_near_parallel(7, 4, 40)
+    H = synth.hadamard_columns(7, range(1, 5))
+    Q, R, _, info = borth.orthonormalize(dev(X), gram="dd", passes=2)
+    assert info.status == 0
+    assert np.max(np.abs(host(Q) - H)) <= 8 * U64 * np.abs(H).max()
+    Q2, R2, _, info2 = borth.orthonormalize(dev(X), gram="f64", passes=1, check=False)
+    if info2.status == 0:
+        assert oracle.metrics(host(Q2), X, host(R2))["omega"] > 1e-6
+    else:
+        assert info2.status == 4 and info2.failed_pass == 1
+
+
+def _check_qr(X, Q, R, Y=None, C=None, omega=1e-14, rho=1e-14):
+    met = oracle.metrics(Q, X, R, Y, C)
+    note(" metrics", met)
+    assert met["rho"] <= rho, met
+    assert met["omega"] <= omega, met
+    if Y is not None:
+        assert met["omega_y"] <= omega, met
+    return met
+
+
+def test_cholqr_plain_c1_shape():
+    """Plain CholQR at the 20000 x 8, kappa = 1e4 workload: orthogonality
+    loss ~ c kappa^2 u (same decade as the oracle's binary64 steps), rho ~ u."""
+    borth = lib()
+    X = synth.svd_matrix(20000, 8, 1e4, 101)
+    Q, R, _, info = borth.orthonormalize(dev(X), gram="f64", passes=1)
+    assert info.status == 0
+    o2 = oracle.cholqr_steps(X, dd_first=False, passes=1)
+    m2 = oracle.metrics(o2["Q"], X, o2["R_hi"])
+    met = _check_qr(X, host(Q), host(R), omega=1.0)
+    assert m2["omega"] / 10 <= met["omega"] <= m2["omega"] * 10
+    o1 = oracle.qr_q(X)
+    assert rel_fro(host(R), o1["R"]) <= 1e-14 * 1e4
+
+
+@pytest.mark.parametrize("k", [4, 8, 16, 32, 64])
+def test_cholqr2_f64_kappa_1e6(k):
+    borth = lib()
+    X = synth.svd_matrix(60000, k, 1e6, 200 + k)
+    for sched in ("recompute", "materialize"):
+        Q, R, _, info = borth.orthonormalize(dev(X), gram="f64", passes=2, sched=sched)
+        assert info.status == 0
+        _check_qr(X, host(Q), host(R))
+
+
+@pytest.mark.parametrize("kappa", [1e8, 1e12, 1e15])
+def test_cholqr2_dd_high_kappa(kappa):
+    borth = lib()
+    X = synth.svd_matrix(50000, 32, kappa, 301)
+    Q, R, _, info = borth.orthonormalize(dev(X), gram="dd", passes=2)
+    assert info.status == 0
+    _check_qr(X, host(Q), host(R))
+    # the binary64 comparator on the same input
+    Qf, Rf, _, inf = borth.orthonormalize(dev(X), gram="f64", passes=2, check=False)
+    if kappa >= 1e12:
+        if inf.status == 0:
+            assert oracle.metrics(host(Qf), X, host(Rf))["omega"] > 1e-14
+        else:
+            assert inf.status == 4
+
+
+@pytest.mark.parametrize("k,kappa,project_once", [(8, 1e3, False), (32, 1e9, False),
+                                                  (16, 1e6, True), (64, 1e5, False)])
+def test_projection_dd_cholqr2(k, kappa, project_once):
+    borth = lib()
+    m = 40000
+    X = synth.svd_matrix(m, k, kappa, 500 + k)
+    Y = synth.locked_basis(m, 16, 600 + k)
+    Q, R, C, info = borth.orthonormalize(dev(X), dev(Y), gram="dd", passes=2,
+                                         project_once=project_once)
+    assert info.status == 0
+    om = 1e-13 if project_once else 1e-14  # P,C,C: Y^T Q grows by ||R^{-1}|| u
+    met = oracle.metrics(host(Q), X, host(R), Y, host(C))
+    note(" metrics", met)
+    assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+    if not project_once:
+        assert met["omega_y"] <= om
+    o1 = oracle.qr_q(X, Y)
+    # C_tot = C_1 + C_2 R_1 carries ~u ||R_1|| = u sigma_max(X) (sigma_max = 1 here)
+    assert np.max(np.abs(host(C) - o1["C"])) <= 1e-13
+
+
+def test_split_bf16_refinement_c4_shape():
+    """fp32 X, split-BF16 Gram, shifted Cholesky, then binary64 passes:
+    per-stage tolerance -- after one refinement pass omega <= 1e-6
+    (kappa(Q_1)^2 u with kappa(Q_1) ~ sqrt(shift)/sigma_min), after two <= 1e-14."""
+    borth = lib()
+    m, k = 200000, 64
+    X = synth.svd_matrix(m, k, 1e6, 401).astype(np.float32)
+    X64 = X.astype(np.float64)
+    Q, R, _, info = borth.orthonormalize(dev(X), gram="split", passes=2)
+    assert info.status == 0
+    met = oracle.metrics(host(Q), X64, host(R))
+    note(" split 2 passes", met)
+    assert met["rho"] <= 1e-14 and met["omega"] <= 1e-6
+    Q, R, _, info = borth.orthonormalize(dev(X), gram="split", passes=3)
+    assert info.status == 0
+    _check_qr(X64, host(Q), host(R))
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+
+def test_edges():
+    borth = lib()
+    torch = torch_gpu()
+    # square and tiny
+    X = synth.svd_matrix(8, 8, 10.0, 1)
+    Q, R, _, info = borth.orthonormalize(dev(X), gram="dd")
+    _check_qr(X, host(Q), host(R))
+    # k = 1, ragged m
+    X = np.random.default_rng(3).standard_normal((1001, 1))
+    Q, R, _, info = borth.orthonormalize(dev(X))
+    _check_qr(X, host(Q), host(R))
+    # odd width and strided input
+    big = np.random.default_rng(4).standard_normal((3003, 70))
+    Xd = dev(big)[:, 2:65]
+    Q, R, _, info = borth.orthonormalize(Xd, gram="dd")
+    _check_qr(big[:, 2:65], host(Q), host(R))
+    # in place
+    X = synth.svd_matrix(5000, 16, 1e5, 9)
+    Xd = dev(X)
+    Q, R, _, info = borth.orthonormalize(Xd, out=Xd, sched="materialize")
+    _check_qr(X, host(Xd), host(R))
+    # rank deficient -> breakdown with the pivot of the duplicate column
+    # (Hadamard columns: the Gram matrix and the pivots are exact, pivot 5 is 0)
+    X = synth.hadamard_columns(6, [1, 2, 3, 4, 2, 5])
+    for gram in ("f64", "dd"):
+        _, _, _, info = borth.orthonormalize(dev(X), gram=gram, passes=1, check=False)
+        assert info.status == 4 and info.failed_pass == 1 and info.failed_pivot == 5
+    # non-finite input
+    X = np.random.default_rng(6).standard_normal((4000, 6))
+    X[17, 2] = np.nan
+    _, _, _, info = borth.orthonormalize(dev(X), gram="dd", check=False)
+    assert info.status == 5
+    # argument errors before any launch
+    with pytest.raises(borth.BorthError):
+        borth.orthonormalize(dev(np.zeros((3, 5))))  # m < k
+    with pytest.raises(borth.BorthError):
+        borth.orthonormalize(dev(np.zeros((300, 65))))  # k > 64
+
+
+def test_deterministic_and_graph_replay():
+    borth = lib()
+    torch = torch_gpu()
+    X = synth.svd_matrix(30000, 32, 1e10, 77)
+    Xd = dev(X)
+    Q1, R1, _, _ = borth.orthonormalize(Xd, gram="dd")
+    Q2, R2, _, _ = borth.orthonormalize(Xd, gram="dd")
+    assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
+    Qg = torch.empty_like(Q1)
+    Rg = torch.empty_like(R1)
+    for rep in range(4):
+        Qg.fill_(0.0)
+        borth.orthonormalize(Xd, gram="dd", graph=True, out=Qg, R=Rg)
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, 1000, device="cuda", dtype=torch.float64).sum()  # eager work
+        torch.cuda.synchronize()
+        assert torch.equal(Qg, Q1) and torch.equal(Rg, R1), rep
+        del junk
