@@ -141,7 +141,7 @@ borth_status ensure_status(borth_ctx c, int n) {
 
 // Small-matrix workspace layout (doubles), for W = ky + k <= 128, kp <= 64.
 struct WsLayout {
-  int64_t g_hi, g_lo, zp[3], cp[3], rtot, ctot, zu, cu, total;
+  int64_t g_hi, g_lo, zp[3], cp[3], wp[3], rtot, ctot, zu, cu, total;
 };
 WsLayout ws_layout() {
   WsLayout w;
@@ -150,6 +150,7 @@ WsLayout ws_layout() {
   w.g_lo = o; o += 128 * 128;
   for (int i = 0; i < 3; ++i) { w.zp[i] = o; o += 64 * 64; }
   for (int i = 0; i < 3; ++i) { w.cp[i] = o; o += 64 * 64; }
+  for (int i = 0; i < 3; ++i) { w.wp[i] = o; o += 64 * 64; }
   w.rtot = o; o += 2 * 64 * 64;
   w.ctot = o; o += 2 * 64 * 64;
   w.zu = o; o += 64 * 64;
@@ -263,6 +264,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     f.pass = pass;
     f.Zp = ws + W.zp[pass];
     f.Cp = ws + W.cp[pass];
+    f.Wp = ws + W.wp[pass];
     f.Rtot = ws + W.rtot;
     f.Ctot = ws + W.ctot;
     f.status = c->status;
@@ -286,7 +288,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     UpdateArgs u;
     memset(&u, 0, sizeof(u));
     u.src = s1;
-    u.C1 = ws + W.cp[0];
+    u.W1 = ws + W.wp[0];
     u.Z1 = ws + W.zp[0];
     u.dense = a.o.fact == BORTH_SVQB;
     u.Q = a.Q;
@@ -302,7 +304,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     UpdateArgs u;
     memset(&u, 0, sizeof(u));
     u.src = s1;
-    u.C1 = ws + W.cp[0];
+    u.W1 = ws + W.wp[0];
     u.Z1 = ws + W.zp[0];
     u.dense = a.o.fact == BORTH_SVQB;
     u.gram_with_y = later_proj ? 1 : 0;
@@ -311,17 +313,16 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 1, kp, hasy), st), "update2");
     prof_end(c, 1);
-    GramLayout Lg = later_proj ? Lu : make_layout(0, a.k, kp);
-    HIPCHK(c, launch_reduce(Lg, 0, c->part, u.nwg, ws + W.g_hi, nullptr, st), "reduce2");
+    HIPCHK(c, launch_reduce(u.glayout, 0, c->part, u.nwg, ws + W.g_hi, nullptr, st), "reduce2");
     r = factor(1, later_proj ? a.ky : 0, ws + W.g_hi, nullptr, false, 0.0, true);
     if (r) return r;
     // sweep 3: recompute Q_1 bitwise, apply pass 2, write Q
     UpdateArgs u3;
     memset(&u3, 0, sizeof(u3));
     u3.src = s1;
-    u3.C1 = ws + W.cp[0];
+    u3.W1 = ws + W.wp[0];
     u3.Z1 = ws + W.zp[0];
-    u3.C2 = ws + W.cp[1];
+    u3.W2 = ws + W.wp[1];
     u3.Z2 = ws + W.zp[1];
     u3.two_stage = 1;
     u3.dense = a.o.fact == BORTH_SVQB;
@@ -329,7 +330,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     u3.ldq = a.ldq;
     if (!later_proj) {
       // pass 2 did not project: its C is zero
-      HIPCHK(c, launch_fill_int((int*)(ws + W.cp[1]), 2 * 64 * 64, 0, st), "zero C2");
+      HIPCHK(c, launch_fill_int((int*)(ws + W.wp[1]), 2 * 64 * 64, 0, st), "zero W2");
     }
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u3, Lu, lookup(c->tune_upd, 2, kp, hasy), st), "update3");
@@ -343,7 +344,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     UpdateArgs u;
     memset(&u, 0, sizeof(u));
     u.src = cur;
-    u.C1 = ws + W.cp[p - 1];
+    u.W1 = ws + W.wp[p - 1];
     u.Z1 = ws + W.zp[p - 1];
     u.dense = a.o.fact == BORTH_SVQB;
     u.Q = a.Q;
@@ -354,17 +355,16 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 1, kp, hasy), st), "update_p");
     prof_end(c, 1);
-    GramLayout Lg = later_proj ? Lu : make_layout(0, a.k, kp);
-    HIPCHK(c, launch_reduce(Lg, 0, c->part, u.nwg, ws + W.g_hi, nullptr, st), "reduce_p");
+    HIPCHK(c, launch_reduce(u.glayout, 0, c->part, u.nwg, ws + W.g_hi, nullptr, st), "reduce_p");
     r = factor(p, later_proj ? a.ky : 0, ws + W.g_hi, nullptr, false, 0.0, p == passes - 1);
     if (r) return r;
     cur = Src{a.Y, a.ldy, a.Q, a.ldq, 0, a.m};
-    if (!later_proj) HIPCHK(c, launch_fill_int((int*)(ws + W.cp[p]), 2 * 64 * 64, 0, st), "zero C");
+    if (!later_proj) HIPCHK(c, launch_fill_int((int*)(ws + W.wp[p]), 2 * 64 * 64, 0, st), "zero W");
   }
   UpdateArgs u;
   memset(&u, 0, sizeof(u));
   u.src = cur;
-  u.C1 = ws + W.cp[passes - 1];
+  u.W1 = ws + W.wp[passes - 1];
   u.Z1 = ws + W.zp[passes - 1];
   u.dense = a.o.fact == BORTH_SVQB;
   u.Q = a.Q;
@@ -378,7 +378,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
 int64_t partial_need(int ky, int k, int gmode) {
   const int kp = pow2pad(k);
   GramLayout L1 = make_layout(ky, k, 4);
-  GramLayout Lu = make_layout(ky, k, kp);
+  GramLayout Lu = make_layout(ky <= 16 && ky > 0 ? 16 : ky, k, kp);
   int64_t e = (int64_t)L1.E * (gmode == BORTH_GRAM_DD ? 2 : 1);
   if (Lu.E > e) e = Lu.E;
   return 1024 * e;
@@ -487,6 +487,12 @@ borth_status borth_gram(borth_ctx c, int64_t m, int ka, const double* A, int64_t
     return fail_arg(c, "DD Gram needs binary64 input");
   hipSetDevice(c->device);
   c->cur = c->stream;
+  if (m == 0) {  // empty block: G = 0 (the sweeps assume at least one row)
+    const int W = ka + kb;
+    HIPCHK(c, launch_fill_int((int*)G_hi, 2 * W * W, 0, c->stream), "zero G");
+    if (G_lo) HIPCHK(c, launch_fill_int((int*)G_lo, 2 * W * W, 0, c->stream), "zero G");
+    return BORTH_OK;
+  }
   GramLayout L = make_layout(ka, kb, 4);
   borth_status r = ensure(c, &c->part, &c->part_cap, 1024 * (int64_t)L.E * 2);
   if (r) return r;
@@ -533,6 +539,7 @@ borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const 
   f.pass = 0;
   f.Zp = c->ws + W.zp[0];
   f.Cp = c->ws + W.cp[0];
+  f.Wp = c->ws + W.wp[0];
   f.Rtot = c->ws + W.rtot;
   f.Ctot = c->ws + W.ctot;
   f.status = c->status;
@@ -563,11 +570,11 @@ borth_status borth_update(borth_ctx c, int64_t m, int k, borth_dtype dt, const v
   HIPCHK(c, launch_fill_int((int*)cp, 2 * 64 * 64, 0, c->stream), "zero C");
   borth_status r = pad_copy(c, zp, kp, Z, k, k);
   if (r) return r;
-  if (ky > 0 && (r = pad_copy(c, cp, kp, C, k, ky))) return r;
+  if (ky > 0) HIPCHK(c, launch_neg_cz(C, Z, cp, ky, k, kp, c->stream), "neg_cz");
   UpdateArgs u;
   memset(&u, 0, sizeof(u));
   u.src = Src{Y, ldy, X, ldx, dt == BORTH_F32 ? 1 : 0, m};
-  u.C1 = cp;
+  u.W1 = cp;
   u.Z1 = zp;
   u.dense = z_dense ? 1 : 0;
   u.Q = Q;

@@ -288,6 +288,17 @@ __global__ void __launch_bounds__(NTF) factor_kernel(FactorArgs a) {
     const int l = e / kp, j = e - l * kp;
     a.Cp[e] = j < k ? a.G_hi[l * W + ky + j] + (a.G_lo ? a.G_lo[l * W + ky + j] : 0.0) : 0.0;
   }
+  // W = -C Z_hi (in DD, rounded): the update applies (S - Y C) Z_hi as
+  // S Z_hi + Y W.
+  __syncthreads();
+  for (int e = tid; e < ky * kp; e += NTF) {
+    const int l = e / kp, j = e - l * kp;
+    dd_t w = dd_from(0.0);
+    if (j < k)
+      for (int i = 0; i <= j; ++i)
+        w = A::add(w, A::mul(ld_g(a.G_hi, a.G_lo, l * W + ky + i), dd_from(a.Zp[i * kp + j])));
+    a.Wp[e] = -(w.hi + w.lo);
+  }
 
   // Totals: X = Y C_tot + X_cur R_tot; after this pass
   //   C_tot += C_p R_tot_old,  R_tot = R_p R_tot_old   (DD, first pass: R_p, C_p).
@@ -525,6 +536,15 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs a) {
   for (int e = tid; e < ky * kp; e += NTF) {
     const int l = e / kp, j = e - l * kp;
     a.Cp[e] = j < k ? a.G_hi[l * W + ky + j] + (a.G_lo ? a.G_lo[l * W + ky + j] : 0.0) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < ky * kp; e += NTF) {
+    const int l = e / kp, j = e - l * kp;
+    double w = 0.0;
+    if (j < k)
+      for (int i = 0; i < k; ++i)
+        w = __builtin_fma(a.G_hi[l * W + ky + i] + (a.G_lo ? a.G_lo[l * W + ky + i] : 0.0), a.Zp[i * kp + j], w);
+    a.Wp[e] = -w;
   }
   __syncthreads();
   // totals in binary64 (R_p dense): C_tot += C_p R_tot_old; R_tot = R_p R_tot_old

@@ -52,24 +52,28 @@ __device__ __forceinline__ int tile_index(int ti, int tj, int T4) {
   return ti * T4 - (ti * (ti - 1)) / 2 + (tj - ti);
 }
 
-// Element (row, c) of the padded [Y | X] block (zero outside).
+// Element (row, c) of the padded [Y | X] block (zero outside; X binary64).
+// The load is unconditional -- row clamped to m - 1, column to 0 -- so that
+// consecutive fetches issue back to back; the zero is selected afterwards.
 __device__ __forceinline__ double fetch(const Src& s, const GramLayout& L, int64_t row, int c) {
-  if (row >= s.m) return 0.0;
-  if (c < L.kyp) return c < L.ky ? s.Y[row * s.ldy + c] : 0.0;
+  const bool isy = c < L.kyp;
   const int j = c - L.kyp;
-  if (j >= L.k) return 0.0;
-  return s.x_f32 ? (double)(((const float*)s.X)[row * s.ldx + j])
-                 : ((const double*)s.X)[row * s.ldx + j];
+  const bool ok = row < s.m && (isy ? c < L.ky : j < L.k);
+  const int64_t rc = row < s.m ? row : s.m - 1;
+  const double* p = isy ? s.Y + rc * s.ldy + (c < L.ky ? c : 0)
+                        : (const double*)s.X + rc * s.ldx + (j < L.k ? j : 0);
+  const double v = *p;
+  return ok ? v : 0.0;
 }
 
 // ---------------------------------------------------------------------------
 // VALU tile kernel (binary64 or DD).
 constexpr int kMaxQ = 12;  // reduction entries per thread
 
-template <bool DD>
-__global__ void __launch_bounds__(1024) gram_tiles_kernel(Src s, GramLayout L, int P,
-                                                          int64_t npanels, int S,
-                                                          double* __restrict__ part) {
+template <bool DD, int NTB>
+__global__ void __launch_bounds__(NTB) gram_tiles_kernel(Src s, GramLayout L, int P,
+                                                         int64_t npanels, int S,
+                                                         double* __restrict__ part) {
   extern __shared__ double lds[];
   const int stride = L.Wp + 2;
   const int tid = threadIdx.x, NT = blockDim.x;
@@ -87,14 +91,45 @@ __global__ void __launch_bounds__(1024) gram_tiles_kernel(Src s, GramLayout L, i
     acc[e] = 0.0;
   }
 
+  // Panel loads: thread t owns column lc = t % Wp and rows lr + q RS
+  // (RS = NT / Wp rows per step, P = NQ RS rows per panel), so one pointer and
+  // one stride per thread address all its loads.  The next panel's loads are
+  // issued into registers before the current panel is processed, so HBM
+  // latency overlaps the arithmetic.
+  constexpr int NQ = 8;
+  const int RS = NT / L.Wp;
+  const int lc = tid % L.Wp, lr = tid / L.Wp;
+  const bool isy = lc < L.kyp;
+  const bool ldr = lr < RS && (isy ? lc < L.ky : lc - L.kyp < L.k);
+  const int64_t ld = isy ? s.ldy : s.ldx;
+  // column clamped to a valid one; loads below are unconditional
+  const double* bd = isy ? s.Y + (lc < L.ky ? lc : 0)
+                         : (const double*)s.X + (lc - L.kyp < L.k ? lc - L.kyp : 0);
+  double pf[NQ];
+  auto fetch_panel = [&](int64_t pnl) {
+    const int64_t row0 = pnl * P + lr;
+    const int64_t mlast = s.m - 1;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int64_t row = row0 + q * RS;
+      v[q] = bd[(row < s.m ? row : mlast) * ld];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int64_t row = row0 + q * RS;
+      pf[q] = (ldr && pnl < npanels && row < s.m) ? v[q] : 0.0;
+    }
+  };
+  fetch_panel(blockIdx.x);
   for (int64_t pnl = blockIdx.x; pnl < npanels; pnl += gridDim.x) {
-    const int64_t row0 = pnl * P;
     __syncthreads();
-    for (int idx = tid; idx < P * L.Wp; idx += NT) {
-      const int r = idx / L.Wp, c = idx - r * L.Wp;
-      lds[r * stride + c] = fetch(s, L, row0 + r, c);
+    if (lr < RS) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) lds[(lr + q * RS) * stride + lc] = pf[q];
     }
     __syncthreads();
+    fetch_panel(pnl + gridDim.x);
     if (active) {
       for (int r = phase; r < P; r += S) {
         const double* row = lds + r * stride;
@@ -333,8 +368,7 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
   const int S = NT / L.ntiles;
   if (S < 1) return hipErrorInvalidValue;
   if (L.E > kMaxQ * NT) return hipErrorInvalidValue;
-  int P = tune.rows > 0 ? tune.rows : 2048 / L.Wp;
-  if (P < 4) P = 4;
+  const int P = 8 * (NT / L.Wp);  // rows per panel: 8 load steps of NT / Wp rows
   const int64_t npanels = (s.m + P - 1) / P;
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   if (nwg > npanels) nwg = (int)(npanels > 0 ? npanels : 1);
@@ -342,10 +376,17 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
   const int panel = P * (L.Wp + 2);
   const int redn = L.E * (mode ? 2 : 1);
   const size_t shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
-  if (mode == 1)
-    hipLaunchKernelGGL(gram_tiles_kernel<true>, dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
-  else
-    hipLaunchKernelGGL(gram_tiles_kernel<false>, dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
+  if (NT == 256) {
+    if (mode == 1)
+      hipLaunchKernelGGL((gram_tiles_kernel<true, 256>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
+    else
+      hipLaunchKernelGGL((gram_tiles_kernel<false, 256>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
+  } else {
+    if (mode == 1)
+      hipLaunchKernelGGL((gram_tiles_kernel<true, 1024>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
+    else
+      hipLaunchKernelGGL((gram_tiles_kernel<false, 1024>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
+  }
   *nwg_out = nwg;
   return hipGetLastError();
 }

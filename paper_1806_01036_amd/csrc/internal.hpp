@@ -65,6 +65,7 @@ struct FactorArgs {
   int pass;                 // 0-based; pass 0 initializes the totals
   double* Zp;               // kp x kp (zero padded), binary64 hi words
   double* Cp;               // ky x kp  (hi words of this pass's C)
+  double* Wp;               // ky x kp  W = -C Z (the update's Y coefficients)
   double* Rtot;             // 2 * k * k  (DD totals, hi then lo)
   double* Ctot;             // 2 * ky * k
   int* status;              // [code, pass, pivot, passes_run]
@@ -83,13 +84,16 @@ hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 struct UpdateArgs {
   int gram_with_y;
   Src src;
-  const double* C1; const double* Z1;  // kyp x kp / kp x kp (padded)
-  const double* C2; const double* Z2;
+  // Stage s computes T = S Z_s + Y W_s with W_s = -C_s Z_s (== (S - Y C_s) Z_s):
+  // Z_s kp x kp, W_s ky x kp (row-major, zero padded beyond k).
+  const double* W1; const double* Z1;
+  const double* W2; const double* Z2;
   int two_stage;
   int dense;                           // Z dense (SVQB)
   double* Q; int64_t ldq;
   double* partials; int64_t partial_cap_doubles;
   int nwg;                             // out: partials written
+  GramLayout glayout;                  // out: layout of those partials
 };
 hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tune,
                          hipStream_t st);
@@ -101,8 +105,9 @@ struct UpdDev {
   const void* X;
   int64_t ldx;
   int64_t m;
-  int ky, kyp, k, Wp;  // LDS panel: [Y (kyp) | S (K)], Wp = kyp + K
-  int gbase, gWp, gT4, gE;  // fused Gram: columns [gbase, gbase + gWp) of the panel
+  int ky, kyp, k;  // kyp: ky rounded up to a multiple of 4 (selects the Y class)
+  int gE;          // entries per partial of the fused Gram
+  int zbase;       // 0 (passed at run time on purpose)
   int dense;
   double* Q;
   int64_t ldq;
@@ -115,6 +120,10 @@ hipError_t launch_update_k8(const UpdDev&, const UpdateArgs&, int nwg, hipStream
 hipError_t launch_update_k16(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
 hipError_t launch_update_k32(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
 hipError_t launch_update_k64(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
+
+// W = -C Z (ky x kp, zero padded) for the public update entry point.
+hipError_t launch_neg_cz(const double* C, const double* Z, double* W, int ky, int k, int kp,
+                         hipStream_t st);
 
 // Fill helper (graph-safe replacement for hipMemsetAsync).
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);

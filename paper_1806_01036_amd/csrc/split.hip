@@ -51,13 +51,25 @@ __global__ void __launch_bounds__(256) gram_split_kernel(Src s, GramLayout L, in
   for (int64_t g = (int64_t)blockIdx.x * nw + wave; g < ngroups; g += gstride) {
     const int64_t rbase = g * 32 + kg * 8;
     bf16x8_t h[T], l[T];
+    // unconditional loads (row clamped to m - 1, column to 0), zero selected after
+    float xv[T][8];
+#pragma unroll
+    for (int I = 0; I < T; ++I) {
+      const int col = 16 * I + c;
+      const int cc = col < L.k ? col : 0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t row = rbase + e;
+        xv[I][e] = X[(row < s.m ? row : s.m - 1) * s.ldx + cc];
+      }
+    }
 #pragma unroll
     for (int I = 0; I < T; ++I) {
       const int col = 16 * I + c;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int64_t row = rbase + e;
-        const float x = (row < s.m && col < L.k) ? X[row * s.ldx + col] : 0.f;
+        const float x = (row < s.m && col < L.k) ? xv[I][e] : 0.f;
         const __bf16 hb = (__bf16)x;
         h[I][e] = hb;
         l[I][e] = (__bf16)(x - (float)hb);

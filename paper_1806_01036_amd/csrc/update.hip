@@ -17,7 +17,7 @@
 //      (v_mfma_f64_16x16x4, operands read from LDS), accumulated per wave.
 // The waves' Gram accumulators are summed in wave order at the end and
 // written as one partial per workgroup (same tile layout as the Gram sweep).
-#include "internal.hpp"
+#include "update_impl.hpp"
 
 namespace borth {
 
@@ -32,26 +32,37 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.ky = L.ky;
   d.kyp = L.kyp;
   d.k = L.k;
-  d.Wp = L.Wp;
+  const int K = L.kp;
+  const int KYP = L.kyp == 0 ? 0 : (L.kyp <= 16 ? 16 : 64);
+  // Fused Gram of [Y | T] (Y padded to 16 columns) or of T alone.
   const bool gy = a.gram_with_y && L.kyp > 0;
-  const GramLayout G = gy ? L : make_layout(0, L.k, L.kp);
-  d.gbase = gy ? 0 : L.kyp;
-  d.gWp = G.Wp;
-  d.gT4 = G.T4;
+  GramLayout G;
+  if (gy) {
+    G = make_layout(L.ky, L.k, K);
+    G.kyp = 16;
+    G.Wp = 16 + G.kp;
+    G.T4 = G.Wp / 4;
+    G.ntiles = G.T4 * (G.T4 + 1) / 2;
+    G.E = 16 * G.ntiles;
+  } else {
+    G = make_layout(0, L.k, K);
+  }
   d.gE = G.E;
+  a.glayout = G;
   d.dense = a.dense;
+  d.zbase = 0;
   d.Q = a.Q;
   d.ldq = a.ldq;
   d.part = a.partials;
   d.npanels = (a.src.m + 63) / 64;
   if (a.partials && gy && L.kyp > 16) return hipErrorInvalidValue;
-  const int NW = (L.Wp <= 48) ? 4 : 2;
+  const int NW = upd::upd_waves(K, KYP);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   const int64_t need = (d.npanels + NW - 1) / NW;
   if (nwg > need) nwg = (int)(need > 0 ? need : 1);
   if (a.partials && (int64_t)nwg * G.E > a.partial_cap_doubles) return hipErrorInvalidValue;
   a.nwg = nwg;
-  switch (L.kp) {
+  switch (K) {
     case 4: return launch_update_k4(d, a, nwg, st);
     case 8: return launch_update_k8(d, a, nwg, st);
     case 16: return launch_update_k16(d, a, nwg, st);
@@ -59,6 +70,28 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
     case 64: return launch_update_k64(d, a, nwg, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+
+// W = -C Z for the public update entry point (C: ky x k, Z: k x k, both
+// contiguous; W: ky x kp zero padded).  One thread per entry, binary64 FMAs.
+__global__ void neg_cz_kernel(const double* __restrict__ C, const double* __restrict__ Z,
+                              double* __restrict__ W, int ky, int k, int kp) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ky * kp) return;
+  const int r = e / kp, j = e - r * kp;
+  double s = 0.0;
+  if (j < k)
+    for (int i = 0; i < k; ++i) s = __builtin_fma(C[r * k + i], Z[i * k + j], s);
+  W[e] = -s;
+}
+
+hipError_t launch_neg_cz(const double* C, const double* Z, double* W, int ky, int k, int kp,
+                         hipStream_t st) {
+  const int n = ky * kp;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(neg_cz_kernel, dim3((n + 255) / 256), dim3(256), 0, st, C, Z, W, ky, k, kp);
+  return hipGetLastError();
 }
 
 }  // namespace borth

@@ -1,21 +1,24 @@
 // Basis update sweep (TSMM), "Y = Xt Z" of Sec. 4.2 with the phase-I
-// projection folded in:  T = (S - Y C) Z  per row, S = X (first pass) or
-// Q_1 (later passes).  Optionally a second stage T = (T - Y C2) Z2 follows in
-// registers (CholQR2 with Q_1 recomputed instead of stored), and the Gram
-// matrix of [Y | T] needed by the next pass is accumulated from the values
-// just computed ("kernel fusion ... to further reduce memory accesses",
-// Sec. 4.2).
+// projection folded in:  T = (S - Y C) Z = S Z + Y W  (W = -C Z) per row,
+// S = X (first pass) or Q_1 (later passes).  Optionally a second stage
+// T = T Z_2 + Y W_2 follows (CholQR2 with Q_1 recomputed instead of stored),
+// and the Gram matrix of [Y | T] (or of T) needed by the next pass is
+// accumulated from the values just computed ("kernel fusion ... to further
+// reduce memory accesses", Sec. 4.2).
 //
-// Layout: a workgroup has NW waves; each wave owns a 64-row panel of [Y | S]
-// in LDS (row stride Wp + 2 doubles: conflict-free 16-byte row reads).
-//   1. coalesced global -> LDS load of the panel (zero-filled outside m, k, ky);
-//   2. lane r computes row r: xt = s - y C (FMAs, C and Z are wave-uniform
-//      and come through scalar loads), then t_j = sum_{i<=j} xt_i Z_ij (all i
-//      for a dense Z), written back into the row;
-//   3. coalesced LDS -> global store of T (if Q is given);
-//   4. the Gram of [Y | T] over the panel on the matrix cores
-//      (v_mfma_f64_16x16x4, operands read from LDS), accumulated per wave.
-// The waves' Gram accumulators are summed in wave order at the end and
+// The product is a dense contraction with a tiny right factor, so it runs
+// on the matrix cores (v_mfma_f64_16x16x4):
+//  * each wave streams its own 64-row panels of [Y | S] (no workgroup
+//    barrier in the loop): coalesced global loads -> LDS (row stride
+//    KYP + K + 2 doubles, compile-time, so all offsets are immediates);
+//  * Z and W live in registers as the B operands for the whole kernel
+//    (lane l holds Z[4 s + l / 16][16 J + l % 16]); the A operands
+//    (lane l: S[row l % 16][col 4 s + l / 16]) are read from LDS;
+//  * the result tile (lane l, register v: T[row l / 16 + 4 v][col 16 J +
+//    l % 16]) is stored straight to global memory, and the same registers
+//    are the operands of the fused Gram MFMA (4-row groups v), so T never
+//    goes back through LDS unless a second stage needs it as an A operand.
+// Each wave's Gram accumulators are summed in wave order at the end and
 // written as one partial per workgroup (same tile layout as the Gram sweep).
 #pragma once
 #include "dd.hpp"
@@ -27,215 +30,296 @@ namespace upd {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int tile_index_u(int ti, int tj, int T4) {
+__host__ __device__ constexpr int tile_index_u(int ti, int tj, int T4) {
   return ti * T4 - (ti * (ti - 1)) / 2 + (tj - ti);
 }
 
+// Orders this wave's LDS accesses across its lanes (LDS instructions of one
+// wave execute in order; the fences keep the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-// GR: 0 = no Gram, 1 = Gram of T (no Y), 2 = Gram of [Y | T] with ky <= 16.
-template <int K, bool TWO, int GR, typename ST>
-__global__ void __launch_bounds__(256) update_kernel(UpdDev a,
-                                                         const double* __restrict__ C1,
-                                                         const double* __restrict__ Z1,
-                                                         const double* __restrict__ C2,
-                                                         const double* __restrict__ Z2) {
+// LDS bytes of a workgroup with nw waves (one 64-row panel per wave).
+inline long upd_lds_bytes(int K, int KYP, int nw) { return 8L * nw * 64 * (KYP + K + 2); }
+
+// Waves per workgroup (1..8): the most resident waves per CU under the 160 KB
+// of LDS, at most 8 (2 per SIMD); larger workgroups preferred.
+inline int upd_waves(int K, int KYP) {
+  int best = 1, best_waves = 0;
+  for (int nw = 1; nw <= 8; nw <<= 1) {
+    const long b = upd_lds_bytes(K, KYP, nw);
+    const int wgs = (int)((160L * 1024) / b);
+    int waves = wgs * nw;
+    if (waves > 8) waves = 8;
+    if (wgs >= 1 && waves >= best_waves) {
+      best = nw;
+      best_waves = waves;
+    }
+  }
+  return best;
+}
+
+// GR: 0 = no Gram, 1 = Gram of T, 2 = Gram of [Y | T] (KYP = 16).
+template <int K, int KYP, bool TWO, int GR, typename ST>
+__global__ void __launch_bounds__(512) update_kernel(UpdDev a,
+                                                     const double* __restrict__ W1,
+                                                     const double* __restrict__ Z1,
+                                                     const double* __restrict__ W2,
+                                                     const double* __restrict__ Z2) {
   extern __shared__ double lds[];
-  constexpr bool GRAM = GR != 0;
-  constexpr int T16max = GR == 2 ? (K + 31) / 16 : (K + 15) / 16;
-  constexpr int NTLc = T16max * (T16max + 1) / 2;
+  constexpr int S = KYP + K + 2;     // LDS row stride (doubles)
+  constexpr int KC = (K + 15) / 16;  // 16-column blocks of T
+  constexpr int KV = K < 16 ? K : 16;  // valid columns per T block
+  constexpr int KS = K / 4;          // k-steps over S
+  constexpr int YS = KYP / 4;        // k-steps over Y
+  constexpr int NST = TWO ? 2 : 1;
+  constexpr int YB = GR == 2 ? 1 : 0;  // Gram blocks taken by Y
+  constexpr int GW = GR == 2 ? KYP + K : K;  // padded Gram width
+  constexpr int T16 = YB + KC;       // Gram column blocks
+  constexpr int NTL = T16 * (T16 + 1) / 2;
+  constexpr int GT4 = GW / 4;
+  constexpr int RPQ = 64 / K;        // panel rows per load step
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int NW = blockDim.x >> 6;
-  const int stride = a.Wp + 2;
-  double* pan = lds + wave * 64 * stride;
-  const int kyp = a.kyp, ky = a.ky;
-  const int T16 = (a.gWp + 15) >> 4;  // <= T16max (host checks)
-  const ST* __restrict__ X = (const ST*)a.X;
+  const int ky = a.ky;
+  const int dense = a.dense;
+  const int c16 = lane & 15, r4 = lane >> 4;
+  double* pan = lds + wave * 64 * S;
 
-  d4_t acc[NTLc];
-  if (GRAM) {
+  // B operands in registers.
+  double zb[NST][KS][KC];
+  double wb[NST][YS > 0 ? YS : 1][KC];
 #pragma unroll
-    for (int i = 0; i < NTLc; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int st = 0; st < NST; ++st) {
+    const double* __restrict__ Zg = st ? Z2 : Z1;
+    const double* __restrict__ Wg = st ? W2 : W1;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int J = 0; J < KC; ++J) {
+        const int col = 16 * J + c16;
+        zb[st][s][J] = col < K ? Zg[(4 * s + r4) * K + col] : 0.0;
+      }
+#pragma unroll
+    for (int s = 0; s < YS; ++s)
+#pragma unroll
+      for (int J = 0; J < KC; ++J) {
+        const int row = 4 * s + r4, col = 16 * J + c16;
+        wb[st][s][J] = (row < ky && col < K) ? Wg[row * K + col] : 0.0;
+      }
   }
 
-  const int64_t pstride = (int64_t)gridDim.x * NW;
-  const int64_t niter = (a.npanels - (int64_t)blockIdx.x * NW + pstride - 1) / pstride;
-  for (int64_t it = 0; it < niter; ++it) {
-    const int64_t pnl = (int64_t)blockIdx.x * NW + wave + it * pstride;
-    const bool live = pnl < a.npanels;
+  d4_t gacc[NTL];
+#pragma unroll
+  for (int i = 0; i < NTL; ++i) gacc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t wstride = (int64_t)gridDim.x * NW;
+  int64_t pnl = (int64_t)blockIdx.x * NW + wave;
+  constexpr int KY1 = KYP > 0 ? KYP : 1;
+  constexpr int RY = 64 / KY1;
+  const int ry0 = lane / KY1, cy = lane % KY1;
+  const int rx0 = lane / K, cx = lane % K;
+  const bool cyin = cy < ky, cxin = cx < a.k;
+  const int aoff = c16 * S + r4;  // A operand: row l % 16, column l / 16
+  const int doff = r4 * S + c16;  // result layout: row l / 16, column l % 16
+  while (pnl < a.npanels) {
     const int64_t row0 = pnl * 64;
-    // 1. load [Y | S] panel
-    if (live) {
-      for (int idx = lane; idx < 64 * kyp; idx += 64) {
-        const int r = idx / kyp, c = idx - r * kyp;
-        const int64_t row = row0 + r;
-        pan[r * stride + c] = (row < a.m && c < ky) ? a.Y[row * a.ldy + c] : 0.0;
-      }
+    const int nrows = (int)(a.m - row0 < 64 ? a.m - row0 : 64);
+    wave_lds_sync();  // this wave's reads of its previous panel are done
+    // 1. [Y | S] rows -> LDS (zero outside m, ky, k).  Loads are
+    // unconditional (rows clamped to m - 1, columns to 0) so that they issue
+    // back to back; out-of-range values are replaced by zero afterwards.
+    if (KYP > 0) {
+      const int cyc = cyin ? cy : 0;
 #pragma unroll
-      for (int q = 0; q < K; ++q) {
-        const int idx = lane + 64 * q;
-        const int r = idx / K, c = idx % K;
-        const int64_t row = row0 + r;
-        pan[r * stride + kyp + c] = (row < a.m && c < a.k) ? (double)X[row * a.ldx + c] : 0.0;
+      for (int q = 0; q < KYP; ++q) {
+        const int r = ry0 + q * RY;
+        const int64_t row = row0 + (r < nrows ? r : nrows - 1);
+        const double v = a.Y[row * a.ldy + cyc];
+        pan[r * S + cy] = (r < nrows && cyin) ? v : 0.0;
       }
     }
-    __syncthreads();
-    // 2. per-row transform (lane = row)
-    if (live) {
-      double* rowp = pan + lane * stride;
+    {
+      const int cxc = cxin ? cx : 0;
+      if (nrows == 64) {
+        const ST* xp = (const ST*)a.X + (row0 + rx0) * a.ldx + cxc;
+        double v[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] = (double)xp[(int64_t)q * RPQ * a.ldx];
+#pragma unroll
+        for (int q = 0; q < K; ++q) pan[(rx0 + q * RPQ) * S + KYP + cx] = cxin ? v[q] : 0.0;
+      } else {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const int r = rx0 + q * RPQ;
+          const int64_t row = row0 + (r < nrows ? r : nrows - 1);
+          const double v = (double)((const ST*)a.X)[row * a.ldx + cxc];
+          pan[r * S + KYP + cx] = (r < nrows && cxin) ? v : 0.0;
+        }
+      }
+    }
+    wave_lds_sync();
 #pragma unroll 1
-      for (int stage = 0; stage < (TWO ? 2 : 1); ++stage) {
-        const double* __restrict__ C = stage ? C2 : C1;
-        const double* __restrict__ Z = stage ? Z2 : Z1;
-        double xt[K];
+    for (int b = 0; b < 4; ++b) {  // 16-row blocks
+      double* pb = pan + 16 * b * S;
+      d4_t t[KC];
 #pragma unroll
-        for (int j = 0; j < K; j += 2) {
-          const double2 v = *(const double2*)(rowp + kyp + j);
-          xt[j] = v.x;
-          xt[j + 1] = v.y;
+      for (int st = 0; st < NST; ++st) {
+#pragma unroll
+        for (int J = 0; J < KC; ++J) t[J] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const double av = pb[aoff + KYP + 4 * s];
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+            if (dense || 4 * s <= 16 * J + 15)  // upper-triangular Z: skip zero blocks
+              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, zb[st][s][J], t[J], 0, 0, 0);
         }
-        for (int l = 0; l < ky; ++l) {
-          const double yl = rowp[l];
 #pragma unroll
-          for (int j = 0; j < K; ++j) xt[j] = __builtin_fma(-yl, C[l * K + j], xt[j]);
+        for (int s = 0; s < YS; ++s) {
+          const double av = pb[aoff + 4 * s];
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+            t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, wb[st][s][J], t[J], 0, 0, 0);
         }
-        if (a.dense) {
-#pragma unroll 1
-          for (int j = 0; j < K; ++j) {
-            double s = 0.0;
+        if (st + 1 < NST) {
+          // this stage's result is the next stage's A operand: back to LDS
+          wave_lds_sync();
 #pragma unroll
-            for (int i = 0; i < K; ++i) s = __builtin_fma(xt[i], Z[i * K + j], s);
-            rowp[kyp + j] = s;
-          }
-        } else {
+          for (int J = 0; J < KC; ++J)
 #pragma unroll
-          for (int j = 0; j < K; ++j) {
-            double s = xt[0] * Z[j];
+            for (int v = 0; v < 4; ++v)
+              if (16 * J + c16 < K) pb[doff + 4 * v * S + KYP + 16 * J] = t[J][v];
+          wave_lds_sync();
+        }
+      }
+      // store T rows 16 b + l / 16 + 4 v, columns 16 J + l % 16
+      if (a.Q) {
 #pragma unroll
-            for (int i = 1; i <= j; ++i) s = __builtin_fma(xt[i], Z[i * K + j], s);
-            rowp[kyp + j] = s;
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * b + r4 + 4 * v;
+          if (r < nrows) {
+            double* qrow = a.Q + (row0 + r) * a.ldq;
+#pragma unroll
+            for (int J = 0; J < KC; ++J)
+              if (16 * J + c16 < a.k) qrow[16 * J + c16] = t[J][v];
           }
         }
       }
-    }
-    __syncthreads();
-    // 3. store
-    if (live && a.Q) {
+      // fused Gram: the result registers are operands for the 4-row groups v
+      if (GR) {
 #pragma unroll
-      for (int q = 0; q < K; ++q) {
-        const int idx = lane + 64 * q;
-        const int r = idx / K, c = idx % K;
-        const int64_t row = row0 + r;
-        if (row < a.m && c < a.k) a.Q[row * a.ldq + c] = pan[r * stride + kyp + c];
-      }
-    }
-    // 4. Gram of [Y | T] on the matrix cores
-    if (GRAM && live) {
-      const int c = lane & 15, rs = lane >> 4;
-      for (int g = 0; g < 16; ++g) {
-        const double* rp = pan + (4 * g + rs) * stride + a.gbase;
-        double v[T16max];
+        for (int v = 0; v < 4; ++v) {
+          double op[T16];
+          if (YB) op[0] = pb[doff + 4 * v * S];  // Y block (layout of the result)
 #pragma unroll
-        for (int I = 0; I < T16max; ++I) {
-          const int col = 16 * I + c;
-          v[I] = (I < T16 && col < a.gWp) ? rp[col] : 0.0;
+          for (int J = 0; J < KC; ++J) op[YB + J] = t[J][v];
+          int idx = 0;
+#pragma unroll
+          for (int I = 0; I < T16; ++I)
+#pragma unroll
+            for (int J = I; J < T16; ++J) {
+              gacc[idx] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], gacc[idx], 0, 0, 0);
+              ++idx;
+            }
         }
-        int idx = 0;
-#pragma unroll
-        for (int I = 0; I < T16max; ++I)
-#pragma unroll
-          for (int J = I; J < T16max; ++J) {
-            if (J < T16)
-              acc[idx] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[I], v[J], acc[idx], 0, 0, 0);
-            ++idx;
-          }
       }
     }
-    __syncthreads();
+    pnl += wstride;
   }
 
-  if (!GRAM) return;
+  if (!GR) return;
   // Sum the waves' accumulators in wave order into wave 0, write the partial.
   double* red = lds;
   for (int w = 1; w < NW; ++w) {
     __syncthreads();
     if (wave == w) {
-      int idx = 0;
 #pragma unroll
-      for (int I = 0; I < T16max; ++I)
+      for (int i = 0; i < NTL; ++i)
 #pragma unroll
-        for (int J = I; J < T16max; ++J) {
-          if (J < T16)
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) red[(idx * 4 + vv) * 64 + lane] = acc[idx][vv];
-          ++idx;
-        }
+        for (int vv = 0; vv < 4; ++vv) red[(i * 4 + vv) * 64 + lane] = gacc[i][vv];
     }
     __syncthreads();
     if (wave == 0) {
-      int idx = 0;
 #pragma unroll
-      for (int I = 0; I < T16max; ++I)
+      for (int i = 0; i < NTL; ++i)
 #pragma unroll
-        for (int J = I; J < T16max; ++J) {
-          if (J < T16)
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) acc[idx][vv] += red[(idx * 4 + vv) * 64 + lane];
-          ++idx;
-        }
+        for (int vv = 0; vv < 4; ++vv) gacc[i][vv] += red[(i * 4 + vv) * 64 + lane];
     }
   }
   if (wave != 0) return;
+  // Gram block B, in-block index x -> padded Gram column (Y: 0..15, then the
+  // K columns of T); -1 for padding columns of a T block narrower than 16.
+  auto pcol = [&](int B, int x) -> int {
+    if (YB && B == 0) return x;
+    return x < KV ? YB * KYP + 16 * (B - YB) + x : -1;
+  };
   double* out = a.part + (int64_t)blockIdx.x * a.gE;
-  const int c = lane & 15, rs = lane >> 4;
   int idx = 0;
 #pragma unroll
-  for (int I = 0; I < T16max; ++I)
+  for (int I = 0; I < T16; ++I)
 #pragma unroll
-    for (int J = I; J < T16max; ++J) {
-      if (J < T16) {
+    for (int J = I; J < T16; ++J) {
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          // v_mfma_f64_16x16x4 D layout: lane l, register vv -> D[l/16 + 4 vv][l%16]
-          const int gi = 16 * I + rs + 4 * vv, gj = 16 * J + c;
-          if (gi < a.gWp && gj < a.gWp && (gi >> 2) <= (gj >> 2)) {
-            const int e = tile_index_u(gi >> 2, gj >> 2, a.gT4) * 16 + (gi & 3) * 4 + (gj & 3);
-            out[e] = acc[idx][vv];
-          }
+      for (int vv = 0; vv < 4; ++vv) {
+        // v_mfma_f64_16x16x4 D layout: lane l, register vv -> D[l/16 + 4 vv][l%16]
+        const int pi = pcol(I, r4 + 4 * vv), pj = pcol(J, c16);
+        if (pi >= 0 && pj >= 0 && (pi >> 2) <= (pj >> 2)) {
+          const int e = tile_index_u(pi >> 2, pj >> 2, GT4) * 16 + (pi & 3) * 4 + (pj & 3);
+          out[e] = gacc[idx][vv];
         }
       }
       ++idx;
     }
 }
 
-template <int K, bool TWO, int GR, typename ST>
+template <int K, int KYP, bool TWO, int GR, typename ST>
 hipError_t launch_upd_t(const UpdDev& d, const UpdateArgs& a, int nwg, hipStream_t st) {
-  const int NW = (d.Wp <= 48) ? 4 : 2;
-  const size_t panel = (size_t)NW * 64 * (d.Wp + 2);
-  constexpr int T16max = GR == 2 ? (K + 31) / 16 : (K + 15) / 16;
-  const size_t red = GR ? T16max * (T16max + 1) / 2 * 4 * 64 : 0;
-  const size_t shmem = sizeof(double) * (panel > red ? panel : red);
-  hipLaunchKernelGGL((update_kernel<K, TWO, GR, ST>), dim3(nwg), dim3(64 * NW), shmem, st, d,
-                     a.C1, a.Z1, a.C2, a.Z2);
+  const int NW = upd_waves(K, KYP);
+  constexpr int KC = (K + 15) / 16;
+  constexpr int T16 = (GR == 2 ? 1 : 0) + KC;
+  const size_t red = GR ? sizeof(double) * T16 * (T16 + 1) / 2 * 4 * 64 : 0;
+  const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW);
+  const size_t shmem = lb > red ? lb : red;
+  hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST>), dim3(nwg), dim3(64 * NW), shmem, st,
+                     d, a.W1, a.Z1, a.W2, a.Z2);
   return hipGetLastError();
 }
 
-template <int K, bool TWO, typename ST>
-hipError_t launch_upd_g(const UpdDev& d, const UpdateArgs& a, int nwg, hipStream_t st) {
-  if (!d.part) return launch_upd_t<K, TWO, 0, ST>(d, a, nwg, st);
-  if (!a.gram_with_y || d.kyp == 0) return launch_upd_t<K, TWO, 1, ST>(d, a, nwg, st);
-  if (d.kyp <= 16) return launch_upd_t<K, TWO, 2, ST>(d, a, nwg, st);
-  return hipErrorInvalidValue;
-}
-
+// Dispatch on the Y padding class, the two-stage flag and the Gram kind.
 template <int K>
 hipError_t launch_upd_k(const UpdDev& d, const UpdateArgs& a, int nwg, hipStream_t st) {
+  const bool gram = d.part != nullptr;
   if (a.src.x_f32) {
-    if (a.two_stage || d.kyp || (d.part && a.gram_with_y)) return hipErrorInvalidValue;
-    return d.part ? launch_upd_t<K, false, 1, float>(d, a, nwg, st)
-                  : launch_upd_t<K, false, 0, float>(d, a, nwg, st);
+    if (a.two_stage || d.kyp) return hipErrorInvalidValue;
+    return gram ? launch_upd_t<K, 0, false, 1, float>(d, a, nwg, st)
+                : launch_upd_t<K, 0, false, 0, float>(d, a, nwg, st);
   }
-  if (a.two_stage) return launch_upd_g<K, true, double>(d, a, nwg, st);
-  return launch_upd_g<K, false, double>(d, a, nwg, st);
+  if (d.kyp == 0) {
+    if (a.two_stage)
+      return gram ? launch_upd_t<K, 0, true, 1, double>(d, a, nwg, st)
+                  : launch_upd_t<K, 0, true, 0, double>(d, a, nwg, st);
+    return gram ? launch_upd_t<K, 0, false, 1, double>(d, a, nwg, st)
+                : launch_upd_t<K, 0, false, 0, double>(d, a, nwg, st);
+  }
+  if (d.kyp <= 16) {
+    const int gr = !gram ? 0 : (a.gram_with_y ? 2 : 1);
+    if (a.two_stage) {
+      if (gr == 2) return launch_upd_t<K, 16, true, 2, double>(d, a, nwg, st);
+      if (gr == 1) return launch_upd_t<K, 16, true, 1, double>(d, a, nwg, st);
+      return launch_upd_t<K, 16, true, 0, double>(d, a, nwg, st);
+    }
+    if (gr == 2) return launch_upd_t<K, 16, false, 2, double>(d, a, nwg, st);
+    if (gr == 1) return launch_upd_t<K, 16, false, 1, double>(d, a, nwg, st);
+    return launch_upd_t<K, 16, false, 0, double>(d, a, nwg, st);
+  }
+  // 16 < ky <= 64: single stage; a fused Gram covers T only
+  if (a.two_stage || (gram && a.gram_with_y)) return hipErrorInvalidValue;
+  return gram ? launch_upd_t<K, 64, false, 1, double>(d, a, nwg, st)
+              : launch_upd_t<K, 64, false, 0, double>(d, a, nwg, st);
 }
 
 }  // namespace upd
