@@ -80,6 +80,15 @@ __device__ __forceinline__ dd_t dd_div(dd_t a, dd_t b) {
   return dd_add(q, dd_mul(y, r));
 }
 
+// 1/sqrt(a): y1 = y0 + y0 (1 - a y0^2) / 2 from y0 = 1/sqrt(a.hi), the
+// residual 1 - a y0^2 formed in DD.
+__device__ __forceinline__ dd_t dd_rsqrt(dd_t a) {
+  const double y0 = 1.0 / sqrt(a.hi);
+  const dd_t y2 = two_prod(y0, y0);
+  const dd_t e = dd_sub(dd_from(1.0), dd_mul(a, y2));
+  return dd_add(dd_from(y0), dd_mul_d(e, 0.5 * y0));
+}
+
 // sqrt(a) = y + x0 (a - y^2)/2 with x0 ~ 1/sqrt(a.hi), y = a.hi x0.
 __device__ __forceinline__ dd_t dd_sqrt(dd_t a) {
   if (!(a.hi > 0.0)) return dd_t{a.hi == 0.0 ? 0.0 : __builtin_nan(""), 0.0};

@@ -54,6 +54,9 @@ struct Ar {
   static __device__ __forceinline__ dd_t recip(dd_t a) {
     return DD ? dd_recip(a) : dd_from(1.0 / a.hi);
   }
+  static __device__ __forceinline__ dd_t rsqrt(dd_t a) {
+    return DD ? dd_rsqrt(a) : dd_from(1.0 / sqrt(a.hi));
+  }
 };
 
 template <bool DD>
@@ -167,8 +170,10 @@ __global__ void __launch_bounds__(NTF) factor_kernel(FactorArgs a) {
       if (!(d.hi > 0.0) || !isfinite(d.hi)) {
         s_fail = j + 1;
       } else {
-        const dd_t r = A::sqrt_(d);
-        const dd_t ri = A::recip(r);
+        // 1/sqrt(d) by one Newton step from the binary64 seed, then
+        // sqrt(d) = d / sqrt(d)
+        const dd_t ri = A::rsqrt(d);
+        const dd_t r = A::mul(d, ri);
         s_rinvh[j] = ri.hi;
         s_rinvl[j] = ri.lo;
         s_rjj[0] = r.hi;
@@ -302,32 +307,46 @@ __global__ void __launch_bounds__(NTF) factor_kernel(FactorArgs a) {
 
   // Totals: X = Y C_tot + X_cur R_tot; after this pass
   //   C_tot += C_p R_tot_old,  R_tot = R_p R_tot_old   (DD, first pass: R_p, C_p).
-  // R_p goes through LDS one row block at a time.
+  // The old R_tot is staged in LDS; R_p goes through LDS one row block at a
+  // time; C_p rows go through LDS 16 at a time.
   __shared__ double s_rph[16][64], s_rpl[16][64];
+  __shared__ double s_toth[64][65], s_totl[64][65];
   Dd16 Rn;
   const bool first = (a.pass == 0);
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) Rn.v[p][q] = dd_from(0.0);
-  // C_tot update needs R_tot_old; do it before R_tot is overwritten.
-  if (ky > 0) {
-    for (int e = tid; e < ky * k; e += NTF) {
-      const int l = e / k, j = e - l * k;
-      const dd_t cp = ld_g(a.G_hi, a.G_lo, l * W + ky + j);
+  if (!first) {
+    for (int e = tid; e < k * k; e += NTF) {
+      const int i = e / k, l = e - i * k;
+      s_toth[i][l] = a.Rtot[e];
+      s_totl[i][l] = a.Rtot[k * k + e];
+    }
+  }
+  // C_tot update (needs the old R_tot).
+  for (int c0 = 0; c0 < ky; c0 += 16) {
+    __syncthreads();
+    for (int e = tid; e < 16 * 64; e += NTF) {
+      const int r = e >> 6, j = e & 63, l = c0 + r;
+      const dd_t cv = (l < ky && j < k) ? ld_g(a.G_hi, a.G_lo, l * W + ky + j) : dd_from(0.0);
+      s_ch[r][j] = cv.hi;
+      s_cl[r][j] = cv.lo;
+    }
+    __syncthreads();
+    const int rn = (ky - c0) < 16 ? (ky - c0) : 16;
+    for (int e = tid; e < rn * k; e += NTF) {
+      const int r = e / k, j = e - r * k, l = c0 + r;
       dd_t ct;
       if (first) {
-        ct = cp;
+        ct = dd_make(s_ch[r][j], s_cl[r][j]);
       } else {
-        ct = dd_make(a.Ctot[e], a.Ctot[ky * k + e]);
-        for (int q = 0; q <= j; ++q) {
-          const dd_t cq = ld_g(a.G_hi, a.G_lo, l * W + ky + q);
-          ct = A::add(ct, A::mul(cq, dd_make(a.Rtot[q * k + j], a.Rtot[k * k + q * k + j])));
-        }
+        ct = dd_make(a.Ctot[l * k + j], a.Ctot[ky * k + l * k + j]);
+        for (int q = 0; q <= j; ++q)
+          ct = A::add(ct, A::mul(dd_make(s_ch[r][q], s_cl[r][q]), dd_make(s_toth[q][j], s_totl[q][j])));
       }
-      // write after all reads of Ctot[e] by this thread (element-private)
-      a.Ctot[e] = ct.hi;
-      a.Ctot[ky * k + e] = ct.lo;
+      a.Ctot[l * k + j] = ct.hi;  // element-private
+      a.Ctot[ky * k + l * k + j] = ct.lo;
     }
   }
   for (int blk = 0; blk < 4; ++blk) {
@@ -335,32 +354,29 @@ __global__ void __launch_bounds__(NTF) factor_kernel(FactorArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ti + 16 * blk, l = tj + 16 * q;
-      if (l < 64) {
-        s_rph[ti][l] = (i < k && l < k) ? M.v[blk][q].hi : 0.0;
-        s_rpl[ti][l] = (i < k && l < k) ? M.v[blk][q].lo : 0.0;
-      }
+      s_rph[ti][l] = (i < k && l < k) ? M.v[blk][q].hi : 0.0;
+      s_rpl[ti][l] = (i < k && l < k) ? M.v[blk][q].lo : 0.0;
     }
     __syncthreads();
-    // every thread's rows in this block: i = ti + 16 * blk (p == blk)
     const int i = ti + 16 * blk;
     if (i < k) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int l = tj + 16 * q;
         if (l >= k || l < i) continue;
-        dd_t s = dd_from(0.0);
+        dd_t sacc = dd_from(0.0);
         if (first) {
-          s = dd_make(s_rph[ti][l], s_rpl[ti][l]);
+          sacc = dd_make(s_rph[ti][l], s_rpl[ti][l]);
         } else {
           for (int qq = i; qq <= l; ++qq)
-            s = A::add(s, A::mul(dd_make(s_rph[ti][qq], s_rpl[ti][qq]),
-                                 dd_make(a.Rtot[qq * k + l], a.Rtot[k * k + qq * k + l])));
+            sacc = A::add(sacc, A::mul(dd_make(s_rph[ti][qq], s_rpl[ti][qq]),
+                                       dd_make(s_toth[qq][l], s_totl[qq][l])));
         }
-        Rn.v[blk][q] = s;
+        Rn.v[blk][q] = sacc;
       }
     }
   }
-  __syncthreads();  // all reads of the old R_tot are done
+  __syncthreads();
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll

@@ -295,14 +295,28 @@ __global__ void __launch_bounds__(1024) reduce_kernel(GramLayout L, const double
   const int E = L.E;
   double h = 0.0, l = 0.0;
   if (e < E) {
-    for (int w = g; w < nwg; w += 16) {
-      if (DD) {
-        const dd_t v = dd_add(dd_make(h, l), dd_make(part[((int64_t)w * E + e) * 2],
-                                                      part[((int64_t)w * E + e) * 2 + 1]));
-        h = v.hi;
-        l = v.lo;
-      } else {
-        h += part[(int64_t)w * E + e];
+    // partials g, g + 16, ...: loaded 8 at a time so their latencies overlap,
+    // added in index order
+    constexpr int B = 8;
+    for (int w0 = g; w0 < nwg; w0 += 16 * B) {
+      double vh[B], vl[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int w = w0 + 16 * u;
+        const int64_t off = (int64_t)(w < nwg ? w : 0) * E + e;
+        vh[u] = DD ? part[2 * off] : part[off];
+        vl[u] = DD ? part[2 * off + 1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (w0 + 16 * u >= nwg) break;
+        if (DD) {
+          const dd_t v = dd_add(dd_make(h, l), dd_make(vh[u], vl[u]));
+          h = v.hi;
+          l = v.lo;
+        } else {
+          h += vh[u];
+        }
       }
     }
   }
