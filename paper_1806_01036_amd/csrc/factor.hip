@@ -4,11 +4,10 @@
 // cost negligible, even in extended precision" (Sec. 4.2) -- on the GPU they
 // are latency, so they run in one workgroup without leaving the device.
 //
-// factor_kernel (Cholesky, DD or binary64 arithmetic):
-//   256 threads; element (i, l) of a k x k matrix (k <= 64) lives in the
-//   registers of thread (i mod 16) * 16 + (l mod 16), slot (i / 16, l / 16).
-//   Right-looking Cholesky and right-looking back substitution for R^{-1}
-//   broadcast one row (and one column) per step through LDS.
+// chol_kernel (Cholesky, DD or binary64 arithmetic): one workgroup of
+//   T x T threads (T = 8, 16, 32, or 24 / 32 with 2 x 2 elements a thread);
+//   LDL^T elimination on [M | I] keeps R and R^{-1} in one array, one
+//   barrier per eliminated column (details at the kernel).
 //   Breakdown rule: unpivoted; a pivot that is not > 0 or not finite stops
 //   the factorization and reports its 1-based index (LAPACK potrf style).
 // svqb_kernel (binary64): cyclic Jacobi with parallel round-robin rotations,
@@ -23,10 +22,6 @@ namespace borth {
 namespace {
 
 constexpr int NTF = 256;
-
-struct Dd16 {
-  dd_t v[4][4];
-};
 
 __device__ __forceinline__ dd_t ld_g(const double* hi, const double* lo, int idx) {
   return dd_make(hi[idx], lo ? lo[idx] : 0.0);
@@ -59,339 +54,363 @@ struct Ar {
   }
 };
 
+// Accumulator of a dot product of DD operands, started from a DD value:
+// Dot2 on the high words plus the binary64 cross terms a.hi b.lo + a.lo b.hi.
+// Its error is O(n u^2) sum |a_i b_i|, the order of a dot product carried in
+// DD arithmetic, at a third of the instructions.  Binary64 mode: one FMA.
 template <bool DD>
-__global__ void __launch_bounds__(NTF) factor_kernel(FactorArgs a) {
+struct Acc {
+  double s, c;
+  __device__ __forceinline__ explicit Acc(dd_t v) : s(v.hi), c(DD ? v.lo : 0.0) {}
+  __device__ __forceinline__ void add(dd_t a, dd_t b) {
+    if (DD) {
+      dot2_step(s, c, a.hi, b.hi);
+      c = __builtin_fma(a.hi, b.lo, __builtin_fma(a.lo, b.hi, c));
+    } else {
+      s = __builtin_fma(a.hi, b.hi, s);
+    }
+  }
+  __device__ __forceinline__ dd_t get() const { return DD ? two_sum(s, c) : dd_from(s); }
+};
+
+// Cholesky factor of the k x k block in one workgroup of T x T threads; each
+// thread holds the NS x NS elements (i, l) = (ti + T p, tj + T q), k <= T NS.
+//
+// The factorization runs as LDL^T elimination on M augmented by the
+// identity: eliminating column j subtracts (M_ji / d_j) times row j from
+// every row i > j, on the trailing upper part of M (l >= i) and on the
+// identity's image (l <= j), which fills in as L^{-1}.  The two never
+// overlap, so both share one k x k array: element (i, l) holds U = D L^T for
+// l >= i and L^{-1} for l < i.  At the end R = D^{-1/2} U and
+// Z = R^{-1} = L^{-T} D^{-1/2}, so the inverse needs no second sweep and the
+// square roots leave the serial chain.  Each step costs one reciprocal of
+// the pivot (computed by every thread from the broadcast row) and one
+// barrier; the owners of row j + 1 publish it through a double-buffered
+// LDS row.
+template <bool DD, int T, int NS>
+__global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs a) {
   using A = Ar<DD>;
-  __shared__ double s_rowh[64], s_rowl[64], s_colh[64], s_coll[64];
-  __shared__ double s_rinvh[64], s_rinvl[64];
-  __shared__ double s_ch[16][64], s_cl[16][64], s_dh[16][64], s_dl[16][64];
-  __shared__ double s_red[NTF];
-  __shared__ double s_rjj[2];
-  __shared__ int s_fail;
+  constexpr int NT = T * T, KP = T * NS, LD = 65;
+  constexpr int ND = (64 * KP + NT - 1) / NT;  // per-thread share of a ky x k block
+  __shared__ double s_r0[2][64 * LD];  // C (DD) / R_p (DD)
+  __shared__ double s_r1[2][64 * LD];  // S, then D (DD) / Z (hi) / old R_tot (DD)
+  __shared__ double s_row[2][2][KP];   // [buffer][hi, lo][column]
+  __shared__ double s_piv[2][64];
+  __shared__ int s_flag;
 
   const int tid = threadIdx.x;
-  const int ti = tid >> 4, tj = tid & 15;
+  const int ti = tid / T, tj = tid - (tid / T) * T;
   const int k = a.k, ky = a.ky, W = a.ky + a.k, kp = a.kp;
+  const bool first = (a.pass == 0);
 
+  auto zero_out = [&]() {
+    for (int e = tid; e < kp * kp; e += NT) a.Zp[e] = 0.0;
+    for (int e = tid; e < ky * kp; e += NT) a.Wp[e] = 0.0;
+  };
   // A previous pass already failed: leave a zero transform and stop.
   if (a.status[0] != 0) {
-    for (int e = tid; e < kp * kp; e += NTF) a.Zp[e] = 0.0;
+    zero_out();
     return;
   }
 
-  // Load M = G_XX.
-  Dd16 M;
+  // Upper part of M = G_XX; the lower part starts as the identity's image (0).
+  dd_t x[NS][NS];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < NS; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ti + 16 * p, l = tj + 16 * q;
-      M.v[p][q] = (i < k && l < k) ? ld_g(a.G_hi, a.G_lo, (ky + i) * W + ky + l) : dd_from(0.0);
+    for (int q = 0; q < NS; ++q) {
+      const int i = ti + T * p, l = tj + T * q;
+      x[p][q] = (i < k && l < k && l >= i) ? ld_g(a.G_hi, a.G_lo, (ky + i) * W + ky + l) : dd_from(0.0);
     }
 
-  // Phase-I correction: M = G_XX - C^T (2C - S C), C = G_YX, S = G_YY.
-  for (int c0 = 0; c0 < ky; c0 += 16) {
+  // Projection against Y: M = G_XX - C^T D with D = 2C - S C, C = G_YX,
+  // S = G_YY; C^T D = C^T C - C^T (C - S C) expands (X - Y C)^T (X - Y C)
+  // with the Gram matrix of Y as it is (no assumption Y^T Y = I).
+  if (ky > 0) {
+    for (int e = tid; e < ky * k; e += NT) {
+      const int r = e / k, l = e - r * k;
+      const dd_t c = ld_g(a.G_hi, a.G_lo, r * W + ky + l);
+      s_r0[0][r * LD + l] = c.hi;
+      s_r0[1][r * LD + l] = c.lo;
+    }
+    for (int e = tid; e < ky * ky; e += NT) {
+      const int r = e / ky, q = e - r * ky;
+      const dd_t sv = ld_g(a.G_hi, a.G_lo, r * W + q);
+      s_r1[0][r * LD + q] = sv.hi;
+      s_r1[1][r * LD + q] = sv.lo;
+    }
     __syncthreads();
-    for (int e = tid; e < 16 * 64; e += NTF) {
-      const int r = e >> 6, j = e & 63, l = c0 + r;
-      dd_t cv = dd_from(0.0), dv = dd_from(0.0);
-      if (l < ky && j < k) {
-        cv = ld_g(a.G_hi, a.G_lo, l * W + ky + j);
-        dd_t sc = dd_from(0.0);
+    dd_t dreg[ND];
+#pragma unroll
+    for (int t = 0; t < ND; ++t) {
+      const int e = tid + NT * t;
+      dreg[t] = dd_from(0.0);
+      if (e < ky * k) {
+        const int r = e / k, l = e - r * k;
+        const dd_t c = dd_make(s_r0[0][r * LD + l], s_r0[1][r * LD + l]);
+        Acc<DD> acc(dd_make(2.0 * c.hi, 2.0 * c.lo));
         for (int q = 0; q < ky; ++q)
-          sc = A::add(sc, A::mul(ld_g(a.G_hi, a.G_lo, l * W + q), ld_g(a.G_hi, a.G_lo, q * W + ky + j)));
-        dv = A::sub(A::add(cv, cv), sc);
+          acc.add(dd_make(-s_r1[0][r * LD + q], -s_r1[1][r * LD + q]),
+                  dd_make(s_r0[0][q * LD + l], s_r0[1][q * LD + l]));
+        dreg[t] = acc.get();
       }
-      s_ch[r][j] = cv.hi; s_cl[r][j] = cv.lo;
-      s_dh[r][j] = dv.hi; s_dl[r][j] = dv.lo;
     }
     __syncthreads();
-    const int rn = (ky - c0) < 16 ? (ky - c0) : 16;
-    for (int r = 0; r < rn; ++r) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = ti + 16 * p, l = tj + 16 * q;
-          if (i < k && l < k)
-            M.v[p][q] = A::fnms(M.v[p][q], dd_make(s_ch[r][i], s_cl[r][i]), dd_make(s_dh[r][l], s_dl[r][l]));
-        }
+    for (int t = 0; t < ND; ++t) {
+      const int e = tid + NT * t;
+      if (e < ky * k) {
+        const int r = e / k, l = e - r * k;
+        s_r1[0][r * LD + l] = dreg[t].hi;
+        s_r1[1][r * LD + l] = dreg[t].lo;
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && l < k && l >= i) {
+          Acc<DD> acc(x[p][q]);
+          for (int r = 0; r < ky; ++r)
+            acc.add(dd_make(-s_r0[0][r * LD + i], -s_r0[1][r * LD + i]),
+                    dd_make(s_r1[0][r * LD + l], s_r1[1][r * LD + l]));
+          x[p][q] = acc.get();
+        }
+      }
   }
 
-  // Non-finite check and optional shift s = shift_rel * trace(M).
+  // Non-finite check; diagonal to LDS for the trace (summed in fixed order).
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
   {
-    double part = 0.0;
     int bad = 0;
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < NS; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = ti + 16 * p, l = tj + 16 * q;
-        if (i < k && l < k) {
-          if (!isfinite(M.v[p][q].hi)) bad = 1;
-          if (i == l) part += M.v[p][q].hi;
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && l < k && l >= i) {
+          if (!isfinite(x[p][q].hi) || !isfinite(x[p][q].lo)) bad = 1;
+          if (i == l) s_piv[0][i] = x[p][q].hi;
         }
       }
-    if (tid == 0) s_fail = 0;
-    __syncthreads();
-    if (bad) s_fail = 1;
-    s_red[tid] = part;
-    __syncthreads();
-    if (s_fail) {
-      if (tid == 0) {
-        a.status[0] = 5;
-        a.status[1] = a.pass + 1;
-        a.status[2] = 0;
-      }
-      for (int e = tid; e < kp * kp; e += NTF) a.Zp[e] = 0.0;
-      return;
-    }
-    if (a.shift_rel > 0.0) {
-      double tr = 0.0;
-      for (int t = 0; t < NTF; ++t) tr += s_red[t];  // fixed order
-      const double sh = a.shift_rel * tr;
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = ti + 16 * p, l = tj + 16 * q;
-          if (i < k && i == l) M.v[p][q] = A::add(M.v[p][q], dd_from(sh));
-        }
-    }
+    if (bad) s_flag = 1;
   }
-
-  // Right-looking Cholesky M = R^T R (upper R stored in place).
-  for (int j = 0; j < k; ++j) {
-    const int pj = j >> 4, jm = j & 15;
-    __syncthreads();
-    if (ti == jm && tj == jm) {
-      dd_t d = M.v[pj][pj];
-      if (!(d.hi > 0.0) || !isfinite(d.hi)) {
-        s_fail = j + 1;
-      } else {
-        // 1/sqrt(d) by one Newton step from the binary64 seed, then
-        // sqrt(d) = d / sqrt(d)
-        const dd_t ri = A::rsqrt(d);
-        const dd_t r = A::mul(d, ri);
-        s_rinvh[j] = ri.hi;
-        s_rinvl[j] = ri.lo;
-        s_rjj[0] = r.hi;
-        s_rjj[1] = r.lo;
-      }
+  __syncthreads();
+  if (s_flag) {
+    if (tid == 0) {
+      a.status[0] = 5;
+      a.status[1] = a.pass + 1;
+      a.status[2] = 0;
     }
-    __syncthreads();
-    if (s_fail) break;
-    const dd_t rjj = dd_make(s_rjj[0], s_rjj[1]);
-    const dd_t rinv = dd_make(s_rinvh[j], s_rinvl[j]);
-    __syncthreads();
-    if (ti == jm) {
+    zero_out();
+    return;
+  }
+  if (a.shift_rel > 0.0) {
+    double tr = 0.0;
+    for (int i = 0; i < k; ++i) tr += s_piv[0][i];
+    const double sh = a.shift_rel * tr;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int l = tj + 16 * q;
-        if (l < k) {
-          dd_t v;
-          if (l > j) v = A::mul(M.v[pj][q], rinv);
-          else if (l == j) v = rjj;
-          else v = dd_from(0.0);
-          M.v[pj][q] = v;
-          s_rowh[l] = v.hi;
-          s_rowl[l] = v.lo;
-        }
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && i == l) x[p][q] = A::add(x[p][q], dd_from(sh));
       }
-    }
-    __syncthreads();
+  }
+  // Publish row 0.
+  if (ti == 0) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int i = ti + 16 * p;
-      if (i <= j || i >= k) continue;
-      const dd_t ri = dd_make(s_rowh[i], s_rowl[i]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int l = tj + 16 * q;
-        if (l >= i && l < k) M.v[p][q] = A::fnms(M.v[p][q], ri, dd_make(s_rowh[l], s_rowl[l]));
-      }
+    for (int q = 0; q < NS; ++q) {
+      s_row[0][0][tj + T * q] = x[0][q].hi;
+      s_row[0][1][tj + T * q] = x[0][q].lo;
     }
   }
   __syncthreads();
-  if (s_fail) {
+
+  int fail = 0;
+  for (int j = 0; j < k; ++j) {
+    const double* rh = s_row[j & 1][0];
+    const double* rl = s_row[j & 1][1];
+    const dd_t d = dd_make(rh[j], rl[j]);
+    // unpivoted: a pivot that is not positive and finite stops here (the
+    // value is the same in every thread, so all leave together)
+    if (!(d.hi > 0.0) || !isfinite(d.hi)) {
+      fail = j + 1;
+      break;
+    }
+    const dd_t dinv = A::recip(d);
+    if (tid == 0) {
+      s_piv[0][j] = d.hi;
+      s_piv[1][j] = d.lo;
+    }
+    dd_t c[NS], v[NS];
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      const int i = ti + T * p;
+      c[p] = (i > j) ? A::mul(dd_make(rh[i], rl[i]), dinv) : dd_from(0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int l = tj + T * q;
+      v[q] = (l == j) ? dd_from(1.0) : dd_make(rh[l], rl[l]);
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i > j && (l >= i || l <= j)) x[p][q] = A::fnms(x[p][q], c[p], v[q]);
+      }
+    const int jn = j + 1;
+    if (ti == jn % T) {
+#pragma unroll
+      for (int p = 0; p < NS; ++p)
+        if (p == jn / T) {
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            s_row[jn & 1][0][tj + T * q] = x[p][q].hi;
+            s_row[jn & 1][1][tj + T * q] = x[p][q].lo;
+          }
+        }
+    }
+    __syncthreads();
+  }
+  if (fail) {
     if (tid == 0) {
       a.status[0] = 4;
       a.status[1] = a.pass + 1;
-      a.status[2] = s_fail;
+      a.status[2] = fail;
     }
-    for (int e = tid; e < kp * kp; e += NTF) a.Zp[e] = 0.0;
+    zero_out();
     return;
   }
-  // Zero the strictly lower part (it held unreduced values).
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (ti + 16 * p > tj + 16 * q) M.v[p][q] = dd_from(0.0);
 
-  // Z = R^{-1} by right-looking back substitution: T = I; for i = k-1..0:
-  // Z[i][:] = T[i][:] / R_ii, then T[i'][j] -= R[i'][i] Z[i][j] for i' < i.
-  Dd16 Z;
+  // R = D^{-1/2} U (l >= i), Z^T = D^{-1/2} L^{-1} (l <= i); x keeps R_p for
+  // l >= i and Z_li for l < i.  Z (hi words) goes to LDS for the W product,
+  // C (DD) too.
+  dd_t rs[NS];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Z.v[p][q] = dd_from((ti + 16 * p == tj + 16 * q) ? 1.0 : 0.0);
-  for (int i = k - 1; i >= 0; --i) {
-    const int pi = i >> 4, im = i & 15;
-    __syncthreads();
-    const dd_t rinv = dd_make(s_rinvh[i], s_rinvl[i]);
-    if (ti == im) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = tj + 16 * q;
-        if (j < k) {
-          const dd_t z = (j >= i) ? A::mul(Z.v[pi][q], rinv) : dd_from(0.0);
-          Z.v[pi][q] = z;
-          s_rowh[j] = z.hi;
-          s_rowl[j] = z.lo;
-        }
-      }
-    }
-    if (tj == im) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int ip = ti + 16 * p;
-        if (ip < k) {
-          s_colh[ip] = M.v[p][pi].hi;
-          s_coll[ip] = M.v[p][pi].lo;
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int ip = ti + 16 * p;
-      if (ip >= i || ip >= k) continue;
-      const dd_t r = dd_make(s_colh[ip], s_coll[ip]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = tj + 16 * q;
-        if (j >= i && j < k) Z.v[p][q] = A::fnms(Z.v[p][q], r, dd_make(s_rowh[j], s_rowl[j]));
-      }
-    }
+  for (int p = 0; p < NS; ++p) {
+    const int i = ti + T * p;
+    rs[p] = i < k ? A::rsqrt(dd_make(s_piv[0][i], s_piv[1][i])) : dd_from(0.0);
   }
-
-  // Outputs: padded Z (hi words), this pass's C (hi words), optional Z / R_p.
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < NS; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ti + 16 * p, l = tj + 16 * q;
-      if (i < kp && l < kp) a.Zp[i * kp + l] = (i < k && l < k) ? Z.v[p][q].hi : 0.0;
+    for (int q = 0; q < NS; ++q) {
+      const int i = ti + T * p, l = tj + T * q;
       if (i < k && l < k) {
-        if (a.Z_out) a.Z_out[i * k + l] = Z.v[p][q].hi;
-        if (a.Rp_out) a.Rp_out[i * k + l] = M.v[p][q].hi;
+        x[p][q] = A::mul(x[p][q], rs[p]);
+        const double z = (l < i) ? x[p][q].hi : (l == i ? rs[p].hi : 0.0);
+        s_r1[0][l * LD + i] = z;  // Z[l][i]
+        if (a.Rp_out) a.Rp_out[i * k + l] = l >= i ? x[p][q].hi : 0.0;
       }
     }
-  for (int e = tid; e < ky * kp; e += NTF) {
-    const int l = e / kp, j = e - l * kp;
-    a.Cp[e] = j < k ? a.G_hi[l * W + ky + j] + (a.G_lo ? a.G_lo[l * W + ky + j] : 0.0) : 0.0;
+  for (int e = tid; e < ky * k; e += NT) {
+    const int r = e / k, l = e - r * k;
+    const dd_t cv = ld_g(a.G_hi, a.G_lo, r * W + ky + l);
+    s_r0[0][r * LD + l] = cv.hi;
+    s_r0[1][r * LD + l] = cv.lo;
   }
-  // W = -C Z_hi (in DD, rounded): the update applies (S - Y C) Z_hi as
-  // S Z_hi + Y W.
   __syncthreads();
-  for (int e = tid; e < ky * kp; e += NTF) {
-    const int l = e / kp, j = e - l * kp;
-    dd_t w = dd_from(0.0);
-    if (j < k)
+  for (int e = tid; e < kp * kp; e += NT) {
+    const int i = e / kp, l = e - i * kp;
+    const double z = (i < k && l < k) ? s_r1[0][i * LD + l] : 0.0;
+    a.Zp[e] = z;
+    if (a.Z_out && i < k && l < k) a.Z_out[i * k + l] = z;
+  }
+  // C (rounded) and W = -C Z_hi in DD, rounded: the update applies
+  // (S - Y C) Z_hi as S Z_hi + Y W.
+  for (int e = tid; e < ky * kp; e += NT) {
+    const int r = e / kp, j = e - r * kp;
+    double w = 0.0, cr = 0.0;
+    if (j < k) {
+      cr = s_r0[0][r * LD + j] + s_r0[1][r * LD + j];
+      Acc<DD> acc(dd_from(0.0));
       for (int i = 0; i <= j; ++i)
-        w = A::add(w, A::mul(ld_g(a.G_hi, a.G_lo, l * W + ky + i), dd_from(a.Zp[i * kp + j])));
-    a.Wp[e] = -(w.hi + w.lo);
+        acc.add(dd_make(s_r0[0][r * LD + i], s_r0[1][r * LD + i]), dd_from(s_r1[0][i * LD + j]));
+      const dd_t wd = acc.get();
+      w = -(wd.hi + wd.lo);
+    }
+    a.Cp[e] = cr;
+    a.Wp[e] = w;
   }
 
-  // Totals: X = Y C_tot + X_cur R_tot; after this pass
-  //   C_tot += C_p R_tot_old,  R_tot = R_p R_tot_old   (DD, first pass: R_p, C_p).
-  // The old R_tot is staged in LDS; R_p goes through LDS one row block at a
-  // time; C_p rows go through LDS 16 at a time.
-  __shared__ double s_rph[16][64], s_rpl[16][64];
-  __shared__ double s_toth[64][65], s_totl[64][65];
-  Dd16 Rn;
-  const bool first = (a.pass == 0);
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Rn.v[p][q] = dd_from(0.0);
-  if (!first) {
-    for (int e = tid; e < k * k; e += NTF) {
-      const int i = e / k, l = e - i * k;
-      s_toth[i][l] = a.Rtot[e];
-      s_totl[i][l] = a.Rtot[k * k + e];
+  // Totals: X = Y C_tot + X_cur R_tot.  After this pass
+  //   C_tot += C_p R_tot_old,  R_tot = R_p R_tot_old   (first pass: C_p, R_p).
+  if (first) {
+    for (int e = tid; e < ky * k; e += NT) {
+      const int r = e / k, l = e - r * k;
+      const double h = s_r0[0][r * LD + l], lo = s_r0[1][r * LD + l];
+      a.Ctot[e] = h;
+      a.Ctot[ky * k + e] = DD ? lo : 0.0;
+      if (a.C_out) a.C_out[e] = h;
     }
-  }
-  // C_tot update (needs the old R_tot).
-  for (int c0 = 0; c0 < ky; c0 += 16) {
-    __syncthreads();
-    for (int e = tid; e < 16 * 64; e += NTF) {
-      const int r = e >> 6, j = e & 63, l = c0 + r;
-      const dd_t cv = (l < ky && j < k) ? ld_g(a.G_hi, a.G_lo, l * W + ky + j) : dd_from(0.0);
-      s_ch[r][j] = cv.hi;
-      s_cl[r][j] = cv.lo;
-    }
-    __syncthreads();
-    const int rn = (ky - c0) < 16 ? (ky - c0) : 16;
-    for (int e = tid; e < rn * k; e += NTF) {
-      const int r = e / k, j = e - r * k, l = c0 + r;
-      dd_t ct;
-      if (first) {
-        ct = dd_make(s_ch[r][j], s_cl[r][j]);
-      } else {
-        ct = dd_make(a.Ctot[l * k + j], a.Ctot[ky * k + l * k + j]);
-        for (int q = 0; q <= j; ++q)
-          ct = A::add(ct, A::mul(dd_make(s_ch[r][q], s_cl[r][q]), dd_make(s_toth[q][j], s_totl[q][j])));
-      }
-      a.Ctot[l * k + j] = ct.hi;  // element-private
-      a.Ctot[ky * k + l * k + j] = ct.lo;
-    }
-  }
-  for (int blk = 0; blk < 4; ++blk) {
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ti + 16 * blk, l = tj + 16 * q;
-      s_rph[ti][l] = (i < k && l < k) ? M.v[blk][q].hi : 0.0;
-      s_rpl[ti][l] = (i < k && l < k) ? M.v[blk][q].lo : 0.0;
-    }
-    __syncthreads();
-    const int i = ti + 16 * blk;
-    if (i < k) {
+    for (int p = 0; p < NS; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int l = tj + 16 * q;
-        if (l >= k || l < i) continue;
-        dd_t sacc = dd_from(0.0);
-        if (first) {
-          sacc = dd_make(s_rph[ti][l], s_rpl[ti][l]);
-        } else {
-          for (int qq = i; qq <= l; ++qq)
-            sacc = A::add(sacc, A::mul(dd_make(s_rph[ti][qq], s_rpl[ti][qq]),
-                                       dd_make(s_toth[qq][l], s_totl[qq][l])));
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && l < k) {
+          const dd_t v = l >= i ? x[p][q] : dd_from(0.0);
+          a.Rtot[i * k + l] = v.hi;
+          a.Rtot[k * k + i * k + l] = v.lo;
+          if (a.R_out) a.R_out[i * k + l] = v.hi;
         }
-        Rn.v[blk][q] = sacc;
       }
+  } else {
+    __syncthreads();  // Z in s_r1 is no longer read
+    for (int e = tid; e < k * k; e += NT) {
+      const int i = e / k, l = e - i * k;
+      s_r1[0][i * LD + l] = a.Rtot[e];
+      s_r1[1][i * LD + l] = a.Rtot[k * k + e];
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ti + 16 * p, l = tj + 16 * q;
-      if (i < k && l < k) {
-        const dd_t v = (l >= i) ? Rn.v[p][q] : dd_from(0.0);
-        a.Rtot[i * k + l] = v.hi;
-        a.Rtot[k * k + i * k + l] = v.lo;
-        if (a.R_out) a.R_out[i * k + l] = v.hi;
-      }
-    }
-  if (a.C_out) {
     __syncthreads();
-    for (int e = tid; e < ky * k; e += NTF) a.C_out[e] = a.Ctot[e];
+    for (int e = tid; e < ky * k; e += NT) {
+      const int r = e / k, j = e - r * k;
+      Acc<DD> acc(dd_make(a.Ctot[e], a.Ctot[ky * k + e]));
+      for (int q = 0; q <= j; ++q)
+        acc.add(dd_make(s_r0[0][r * LD + q], s_r0[1][r * LD + q]),
+                dd_make(s_r1[0][q * LD + j], s_r1[1][q * LD + j]));
+      const dd_t ct = acc.get();
+      a.Ctot[e] = ct.hi;  // element-private
+      a.Ctot[ky * k + e] = ct.lo;
+      if (a.C_out) a.C_out[e] = ct.hi;
+    }
+    __syncthreads();  // C in s_r0 is no longer read
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && l < k && l >= i) {
+          s_r0[0][i * LD + l] = x[p][q].hi;
+          s_r0[1][i * LD + l] = x[p][q].lo;
+        }
+      }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && l < k) {
+          dd_t v = dd_from(0.0);
+          if (l >= i) {
+            Acc<DD> acc(dd_from(0.0));
+            for (int qq = i; qq <= l; ++qq)
+              acc.add(dd_make(s_r0[0][i * LD + qq], s_r0[1][i * LD + qq]),
+                      dd_make(s_r1[0][qq * LD + l], s_r1[1][qq * LD + l]));
+            v = acc.get();
+          }
+          a.Rtot[i * k + l] = v.hi;  // element-private; the old totals are in LDS
+          a.Rtot[k * k + i * k + l] = v.lo;
+          if (a.R_out) a.R_out[i * k + l] = v.hi;
+        }
+      }
   }
   if (tid == 0) a.status[3] = a.pass + 1;
 }
@@ -608,6 +627,20 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs a) {
   if (tid == 0) a.status[3] = a.pass + 1;
 }
 
+template <bool DD>
+void launch_chol(const FactorArgs& a, hipStream_t st) {
+  if (a.k <= 8)
+    hipLaunchKernelGGL((chol_kernel<DD, 8, 1>), dim3(1), dim3(64), 0, st, a);
+  else if (a.k <= 16)
+    hipLaunchKernelGGL((chol_kernel<DD, 16, 1>), dim3(1), dim3(256), 0, st, a);
+  else if (a.k <= 32)
+    hipLaunchKernelGGL((chol_kernel<DD, 32, 1>), dim3(1), dim3(1024), 0, st, a);
+  else if (a.k <= 48)
+    hipLaunchKernelGGL((chol_kernel<DD, 24, 2>), dim3(1), dim3(576), 0, st, a);
+  else
+    hipLaunchKernelGGL((chol_kernel<DD, 32, 2>), dim3(1), dim3(1024), 0, st, a);
+}
+
 }  // namespace
 
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st) {
@@ -615,9 +648,9 @@ hipError_t launch_factor(const FactorArgs& a, hipStream_t st) {
   if (a.fact == 1) {
     hipLaunchKernelGGL(svqb_kernel, dim3(1), dim3(NTF), 0, st, a);
   } else if (a.dd) {
-    hipLaunchKernelGGL(factor_kernel<true>, dim3(1), dim3(NTF), 0, st, a);
+    launch_chol<true>(a, st);
   } else {
-    hipLaunchKernelGGL(factor_kernel<false>, dim3(1), dim3(NTF), 0, st, a);
+    launch_chol<false>(a, st);
   }
   return hipGetLastError();
 }
