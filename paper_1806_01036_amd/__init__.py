@@ -228,11 +228,15 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
     return Q, R, (C if ky else None), info
 
 
-def batch_orthonormalize(blocks, *, gram="dd", passes=2, shift=-1.0, project_once=False,
-                         sync=True, check=True, ctx=None):
-    """blocks: list of dicts with X (m x k float64), optional Y (m x ky), and
-    optional preallocated Q, R, C.  Returns the list of (Q, R, C) and the
-    list of Info (None when not synchronizing)."""
+def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0,
+                         project_once=False, graph=False, sync=True, check=True, ctx=None):
+    """Orthonormalize many independent blocks together (borth_batch_orthonormalize).
+
+    blocks: list of dicts with X (m x k float64), optional Y (m x ky, ky <= 16)
+    and optional preallocated Q (may be X itself: in place), R, C.  Every
+    phase runs as one launch over all blocks; with graph=True the launch
+    sequence is captured once and replayed.  Returns the list of (Q, R, C)
+    and the list of Info (None entries when not synchronizing)."""
     torch = _torch()
     if not blocks:
         return [], []
@@ -259,8 +263,8 @@ def batch_orthonormalize(blocks, *, gram="dd", passes=2, shift=-1.0, project_onc
         e.Q, e.ldq, e.R = Q.data_ptr(), _ld(Q), Rt.data_ptr()
         e.C = Ct.data_ptr() if ky else None
         outs.append((Q, Rt, Ct if ky else None))
-    o = _opts(gram, "chol", passes, "materialize", shift,
-              FLAG_PROJECT_ONCE if project_once else 0)
+    flags = (FLAG_PROJECT_ONCE if project_once else 0) | (FLAG_GRAPH if graph else 0)
+    o = _opts(gram, fact, passes, "materialize", shift, flags)
     infs = (_lib.borth_info * len(blocks))()
     st = ctx.lib.borth_batch_orthonormalize(ctx.h, len(blocks), arr, ctypes.byref(o),
                                             infs if sync else None)

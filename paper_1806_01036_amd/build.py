@@ -30,7 +30,7 @@ SOURCES = [
     "update_k16.hip",
     "update_k32.hip",
     "update_k64.hip",
-    "batch.hip",
+    "batch.cpp",
     "borth.cpp",
 ]
 

@@ -20,48 +20,9 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/borth.h"
-#include "internal.hpp"
+#include "ctx.hpp"
 
 using namespace borth;
-
-struct GraphKey {
-  std::vector<int64_t> v;
-  bool operator<(const GraphKey& o) const { return v < o.v; }
-};
-
-struct TimedPair {
-  hipEvent_t a, b;
-};
-
-struct borth_ctx_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  double* part = nullptr;
-  int64_t part_cap = 0;  // doubles
-  double* ws = nullptr;
-  int64_t ws_cap = 0;
-  int* status = nullptr;   // device, 4 ints (+ batch statuses)
-  int status_cap = 0;
-  int* h_status = nullptr;  // pinned host copy
-  int h_status_cap = 0;
-  std::map<GraphKey, hipGraphExec_t> graphs;
-  uint64_t ws_generation = 0;
-  // profiling
-  bool prof = false;
-  std::vector<TimedPair> ev_free;
-  std::vector<TimedPair> ev_used[2];
-  // autotune table: key (mode, kp, ky>0) -> tune
-  std::map<std::tuple<int, int, int>, TuneGram> tune_gram;
-  std::map<std::tuple<int, int, int>, TuneGram> tune_upd;
-  // batch plan cache (device descriptors)
-  void* batch_mem = nullptr;
-  int64_t batch_mem_cap = 0;
-  hipStream_t cap_stream = nullptr;  // private stream for graph capture
-  bool capturing = false;
-  hipStream_t cur = nullptr;         // stream the current enqueue targets
-};
 
 namespace {
 
@@ -72,30 +33,6 @@ const char* kStatusText[] = {"ok",
                              "Cholesky breakdown (non-positive pivot)",
                              "non-finite value in a Gram matrix",
                              "unsupported request"};
-
-borth_status fail_hip(borth_ctx c, hipError_t e, const char* where) {
-  if (c) {
-    c->err = std::string(where) + ": " + hipGetErrorString(e);
-  }
-  return BORTH_ERR_HIP;
-}
-
-borth_status fail_arg(borth_ctx c, const char* what) {
-  if (c) c->err = std::string("invalid argument: ") + what;
-  return BORTH_ERR_ARG;
-}
-
-#define HIPCHK(c, expr, where)                 \
-  do {                                         \
-    hipError_t _e = (expr);                    \
-    if (_e != hipSuccess) return fail_hip(c, _e, where); \
-  } while (0)
-
-int pow2pad(int k) {
-  int p = 4;
-  while (p < k) p <<= 1;
-  return p;
-}
 
 void invalidate_graphs(borth_ctx c) {
   for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
@@ -157,30 +94,6 @@ WsLayout ws_layout() {
   w.cu = o; o += 64 * 64;
   w.total = o;
   return w;
-}
-
-TuneGram lookup(const std::map<std::tuple<int, int, int>, TuneGram>& t, int mode, int kp, int hasy) {
-  auto it = t.find(std::make_tuple(mode, kp, hasy));
-  if (it != t.end()) return it->second;
-  return TuneGram{0, 0};
-}
-
-void prof_begin(borth_ctx c, int kind) {
-  if (!c->prof || c->capturing) return;
-  TimedPair p;
-  if (!c->ev_free.empty()) {
-    p = c->ev_free.back();
-    c->ev_free.pop_back();
-  } else {
-    hipEventCreate(&p.a);
-    hipEventCreate(&p.b);
-  }
-  hipEventRecord(p.a, c->cur);
-  c->ev_used[kind].push_back(p);
-}
-void prof_end(borth_ctx c, int kind) {
-  if (!c->prof || c->capturing) return;
-  hipEventRecord(c->ev_used[kind].back().b, c->cur);
 }
 
 // Copy a rows x k matrix into a rows x kp zero-padded one (device to device).
@@ -447,7 +360,7 @@ borth_status borth_destroy(borth_ctx c) {
   if (c->ws) hipFree(c->ws);
   if (c->status) hipFree(c->status);
   if (c->h_status) hipHostFree(c->h_status);
-  if (c->batch_mem) hipFree(c->batch_mem);
+  batch_free_all(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (auto& p : c->ev_free) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
   for (int k = 0; k < 2; ++k)
@@ -681,28 +594,6 @@ borth_status borth_kernel_time(borth_ctx c, int kind, double* avg_ms, int* count
   *avg_ms = n ? tot / n : 0.0;
   if (count) *count = n;
   return BORTH_OK;
-}
-
-borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_block* blocks,
-                                        const borth_opts* opts, borth_info* infos) {
-  (void)nblocks; (void)blocks; (void)opts; (void)infos;
-  if (!c) return BORTH_ERR_ARG;
-  c->err = "batched path not built yet";
-  return BORTH_ERR_UNSUPPORTED;
-}
-
-borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) {
-  (void)cache_path; (void)budget_ms;
-  if (!c) return BORTH_ERR_ARG;
-  c->err = "autotuner not built yet";
-  return BORTH_ERR_UNSUPPORTED;
-}
-
-borth_status borth_autotune_load(borth_ctx c, const char* cache_path) {
-  (void)cache_path;
-  if (!c) return BORTH_ERR_ARG;
-  c->err = "autotuner not built yet";
-  return BORTH_ERR_UNSUPPORTED;
 }
 
 }  // extern "C"

@@ -88,8 +88,10 @@ struct Acc {
 // barrier; the owners of row j + 1 publish it through a double-buffered
 // LDS row.
 template <bool DD, int T, int NS>
-__global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs a) {
+__global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
+                                                     const FactorArgs* __restrict__ tab) {
   using A = Ar<DD>;
+  const FactorArgs a = tab ? tab[blockIdx.x] : one;
   constexpr int NT = T * T, KP = T * NS, LD = 65;
   constexpr int ND = (64 * KP + NT - 1) / NT;  // per-thread share of a ky x k block
   __shared__ double s_r0[2][64 * LD];  // C (DD) / R_p (DD)
@@ -417,12 +419,13 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs a) {
 
 // ---------------------------------------------------------------------------
 // SVQB (binary64): M in LDS, cyclic Jacobi with round-robin parallel pairs.
-__global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs a) {
+__global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
+                                                   const FactorArgs* __restrict__ tab) {
+  const FactorArgs a = tab ? tab[blockIdx.x] : one;
   __shared__ double sM[64 * 65];
   __shared__ double sV[64 * 65];
   __shared__ double sc[32], ss[32];
   __shared__ int sp[32], sq[32];
-  __shared__ double s_red[NTF];
   __shared__ int s_flag;
   const int tid = threadIdx.x;
   const int k = a.k, ky = a.ky, W = a.ky + a.k, kp = a.kp;
@@ -465,33 +468,14 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs a) {
   // Round-robin ordering on n = k rounded up to even; index n-1 is a dummy if k odd.
   const int n = (k + 1) & ~1;
   const int npair = n / 2;
+  // Rotation rule (relative threshold of Demmel and Veselic 1992): rotate the
+  // pair (p, q) only if |a_pq| > u sqrt(|a_pp a_qq|); the sweeps stop after
+  // one with no rotation.  Off-diagonal entries at rounding level are left
+  // alone, so converged sweeps do not feed rounding noise back into V.
   for (int sweep = 0; sweep < 30; ++sweep) {
-    // convergence test: off-diagonal mass relative to the diagonal
-    double off = 0.0, dia = 0.0;
-    for (int e = tid; e < k * k; e += NTF) {
-      const int i = e / k, l = e - i * k;
-      const double v = sM[i * LD + l];
-      if (i != l) off += v * v; else dia += v * v;
-    }
-    s_red[tid] = off;
+    __syncthreads();  // every thread has read the previous sweep's flag
+    if (tid == 0) s_flag = 0;
     __syncthreads();
-    if (tid == 0) {
-      double o = 0.0;
-      for (int t = 0; t < NTF; ++t) o += s_red[t];
-      s_red[0] = o;
-    }
-    __syncthreads();
-    const double offt = s_red[0];
-    __syncthreads();
-    s_red[tid] = dia;
-    __syncthreads();
-    if (tid == 0) {
-      double d = 0.0;
-      for (int t = 0; t < NTF; ++t) d += s_red[t];
-      s_flag = (offt <= 1e-34 * d) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_flag) break;
     for (int step = 0; step < n - 1; ++step) {
       if (tid < npair) {
         // round-robin: position 0 fixed, others rotate
@@ -504,7 +488,9 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs a) {
         double c = 1.0, s = 0.0;
         if (qq < k) {
           const double apq = sM[pp * LD + qq];
-          if (apq != 0.0) {
+          const double app = sM[pp * LD + pp], aqq = sM[qq * LD + qq];
+          if (fabs(apq) > 0x1p-53 * sqrt(fabs(app * aqq))) {
+            s_flag = 1;
             const double theta = (sM[qq * LD + qq] - sM[pp * LD + pp]) / (2.0 * apq);
             const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -540,6 +526,7 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs a) {
       }
       __syncthreads();
     }
+    if (!s_flag) break;  // read after the last step's barrier, by every thread
   }
   // eigenvalues on the diagonal; lift tiny ones
   __shared__ double lam[64];
@@ -628,31 +615,35 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs a) {
 }
 
 template <bool DD>
-void launch_chol(const FactorArgs& a, hipStream_t st) {
+void launch_chol(const FactorArgs& a, const FactorArgs* tab, int n, hipStream_t st) {
   if (a.k <= 8)
-    hipLaunchKernelGGL((chol_kernel<DD, 8, 1>), dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((chol_kernel<DD, 8, 1>), dim3(n), dim3(64), 0, st, a, tab);
   else if (a.k <= 16)
-    hipLaunchKernelGGL((chol_kernel<DD, 16, 1>), dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((chol_kernel<DD, 16, 1>), dim3(n), dim3(256), 0, st, a, tab);
   else if (a.k <= 32)
-    hipLaunchKernelGGL((chol_kernel<DD, 32, 1>), dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((chol_kernel<DD, 32, 1>), dim3(n), dim3(1024), 0, st, a, tab);
   else if (a.k <= 48)
-    hipLaunchKernelGGL((chol_kernel<DD, 24, 2>), dim3(1), dim3(576), 0, st, a);
+    hipLaunchKernelGGL((chol_kernel<DD, 24, 2>), dim3(n), dim3(576), 0, st, a, tab);
   else
-    hipLaunchKernelGGL((chol_kernel<DD, 32, 2>), dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((chol_kernel<DD, 32, 2>), dim3(n), dim3(1024), 0, st, a, tab);
 }
 
 }  // namespace
 
-hipError_t launch_factor(const FactorArgs& a, hipStream_t st) {
-  if (a.k > 64 || a.ky > 64 || a.k < 1) return hipErrorInvalidValue;
+hipError_t launch_factor_table(const FactorArgs& a, const FactorArgs* tab, int n, hipStream_t st) {
+  if (a.k > 64 || a.ky > 64 || a.k < 1 || n < 1) return hipErrorInvalidValue;
   if (a.fact == 1) {
-    hipLaunchKernelGGL(svqb_kernel, dim3(1), dim3(NTF), 0, st, a);
+    hipLaunchKernelGGL(svqb_kernel, dim3(n), dim3(NTF), 0, st, a, tab);
   } else if (a.dd) {
-    launch_chol<true>(a, st);
+    launch_chol<true>(a, tab, n, st);
   } else {
-    launch_chol<false>(a, st);
+    launch_chol<false>(a, tab, n, st);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_factor(const FactorArgs& a, hipStream_t st) {
+  return launch_factor_table(a, nullptr, 1, st);
 }
 
 }  // namespace borth

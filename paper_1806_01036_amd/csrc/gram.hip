@@ -71,10 +71,16 @@ __device__ __forceinline__ double fetch(const Src& s, const GramLayout& L, int64
 constexpr int kMaxQ = 12;  // reduction entries per thread
 
 template <bool DD, int NTB>
-__global__ void __launch_bounds__(NTB) gram_tiles_kernel(Src s, GramLayout L, int P,
-                                                         int64_t npanels, int S,
-                                                         double* __restrict__ part) {
+__global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
+                                                         const GramSeg* __restrict__ tab,
+                                                         const int* __restrict__ wg2seg) {
   extern __shared__ double lds[];
+  const GramSeg g = tab ? tab[wg2seg[blockIdx.x]] : one;
+  const Src& s = g.s;
+  const GramLayout& L = g.L;
+  const int P = g.P, S = g.S;
+  const int64_t npanels = g.nunits;
+  const int wg = (int)blockIdx.x - g.wg0, nwg = g.nwg;
   const int stride = L.Wp + 2;
   const int tid = threadIdx.x, NT = blockDim.x;
   const int nt = L.ntiles;
@@ -121,15 +127,15 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(Src s, GramLayout L, in
       pf[q] = (ldr && pnl < npanels && row < s.m) ? v[q] : 0.0;
     }
   };
-  fetch_panel(blockIdx.x);
-  for (int64_t pnl = blockIdx.x; pnl < npanels; pnl += gridDim.x) {
+  fetch_panel(wg);
+  for (int64_t pnl = wg; pnl < npanels; pnl += nwg) {
     __syncthreads();
     if (lr < RS) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) lds[(lr + q * RS) * stride + lc] = pf[q];
     }
     __syncthreads();
-    fetch_panel(pnl + gridDim.x);
+    fetch_panel(pnl + nwg);
     if (active) {
       for (int r = phase; r < P; r += S) {
         const double* row = lds + r * stride;
@@ -191,7 +197,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(Src s, GramLayout L, in
     }
     __syncthreads();
   }
-  double* out = part + (int64_t)blockIdx.x * E * (DD ? 2 : 1);
+  double* out = g.part + (int64_t)wg * E * (DD ? 2 : 1);
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) {
     const int e = tid + q * NT;
@@ -211,18 +217,24 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(Src s, GramLayout L, in
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 template <int T, int U>
-__global__ void __launch_bounds__(256) gram_mfma_kernel(Src s, GramLayout L, int64_t ngroups,
-                                                        double* __restrict__ part) {
+__global__ void __launch_bounds__(256) gram_mfma_kernel(GramSeg one,
+                                                        const GramSeg* __restrict__ tab,
+                                                        const int* __restrict__ wg2seg) {
   constexpr int NTL = T * (T + 1) / 2;
   __shared__ double red[NTL * 4 * 64];
+  const GramSeg gs = tab ? tab[wg2seg[blockIdx.x]] : one;
+  const Src& s = gs.s;
+  const GramLayout& L = gs.L;
+  const int64_t ngroups = gs.nunits;
+  const int wg = (int)blockIdx.x - gs.wg0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int c = lane & 15, rsub = lane >> 4;
   d4_t acc[NTL];
 #pragma unroll
   for (int i = 0; i < NTL; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t gstride = (int64_t)gridDim.x * nw;
-  int64_t g = (int64_t)blockIdx.x * nw + wave;
+  const int64_t gstride = (int64_t)gs.nwg * nw;
+  int64_t g = (int64_t)wg * nw + wave;
   for (; g < ngroups; g += U * gstride) {
     double v[U][T];
 #pragma unroll
@@ -263,7 +275,7 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(Src s, GramLayout L, int
     }
   }
   if (wave != 0) return;
-  double* out = part + (int64_t)blockIdx.x * L.E;
+  double* out = gs.part + (int64_t)wg * L.E;
   int idx = 0;
 #pragma unroll
   for (int I = 0; I < T; ++I)
@@ -286,13 +298,19 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(Src s, GramLayout L, int
 
 // ---------------------------------------------------------------------------
 template <bool DD>
-__global__ void __launch_bounds__(1024) reduce_kernel(GramLayout L, const double* __restrict__ part,
-                                                      int nwg, double* __restrict__ Ghi,
-                                                      double* __restrict__ Glo) {
+__global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
+                                                      const ReduceSeg* __restrict__ tab) {
   __shared__ double sh[16][64], sl[16][64];
+  const ReduceSeg rs = tab ? tab[blockIdx.y] : one;
+  const GramLayout& L = rs.L;
+  const double* __restrict__ part = rs.part;
+  const int nwg = rs.nwg;
+  double* __restrict__ Ghi = rs.Ghi;
+  double* __restrict__ Glo = rs.Glo;
+  const int E = L.E;
+  if ((int)blockIdx.x * 64 >= E) return;  // batched launch: a narrower block
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + el;
-  const int E = L.E;
   double h = 0.0, l = 0.0;
   if (e < E) {
     // partials g, g + 16, ...: loaded 8 at a time so their latencies overlap,
@@ -355,64 +373,114 @@ __global__ void __launch_bounds__(1024) reduce_kernel(GramLayout L, const double
 }
 
 // ---------------------------------------------------------------------------
-static int tiles_threads(int ntiles) { return ntiles <= 40 ? 256 : 1024; }
+// Host side.  A sweep's shape: the MFMA kernel (binary64, 16 <= Wp <= 80) or
+// the VALU tile kernel (DD, or binary64 outside that range).
+
+int gram_kind(const GramLayout& L, int mode) {
+  const int W16 = (L.Wp + 15) / 16;
+  return (mode == 0 && L.Wp >= 16 && W16 <= 5) ? 0 : 1;
+}
+
+int gram_tiles_threads(const GramLayout& L) { return L.ntiles <= 40 ? 256 : 1024; }
+
+int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
+  if (gram_kind(L, mode) == 0) return (s.m + 3) / 4;
+  const int P = 8 * (NT / L.Wp);
+  return (s.m + P - 1) / P;
+}
+
+int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT) {
+  const int64_t u = gram_units(s, L, mode, NT);
+  const int64_t need = gram_kind(L, mode) == 0 ? (u + 3) / 4 : u;
+  return (int)(need < 1 ? 1 : (need > (1 << 20) ? (1 << 20) : need));
+}
+
+bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part, int wg0,
+              int nwg, GramSeg* out, size_t* shmem) {
+  GramSeg g;
+  g.s = s;
+  g.L = L;
+  g.part = part;
+  g.wg0 = wg0;
+  g.nwg = nwg;
+  g.nunits = gram_units(s, L, mode, NT);
+  g.P = 0;
+  g.S = 0;
+  *shmem = 0;
+  if (gram_kind(L, mode) == 1) {
+    g.S = NT / L.ntiles;
+    if (g.S < 1 || L.E > kMaxQ * NT || NT / L.Wp < 1) return false;
+    g.P = 8 * (NT / L.Wp);
+    const int panel = g.P * (L.Wp + 2);
+    const int redn = L.E * (mode ? 2 : 1);
+    *shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
+  }
+  *out = g;
+  return true;
+}
+
+hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int grid,
+                            const GramSeg& one, const GramSeg* tab, const int* wg2seg,
+                            hipStream_t st) {
+  if (grid < 1) return hipSuccess;
+  if (kind == 0) {
+    switch (NT_or_T) {
+      case 1: hipLaunchKernelGGL((gram_mfma_kernel<1, 4>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
+      case 2: hipLaunchKernelGGL((gram_mfma_kernel<2, 4>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
+      case 3: hipLaunchKernelGGL((gram_mfma_kernel<3, 2>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
+      case 4: hipLaunchKernelGGL((gram_mfma_kernel<4, 2>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
+      case 5: hipLaunchKernelGGL((gram_mfma_kernel<5, 2>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  if (NT_or_T == 256) {
+    if (mode == 1)
+      hipLaunchKernelGGL((gram_tiles_kernel<true, 256>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+    else
+      hipLaunchKernelGGL((gram_tiles_kernel<false, 256>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+  } else if (NT_or_T == 1024) {
+    if (mode == 1)
+      hipLaunchKernelGGL((gram_tiles_kernel<true, 1024>), dim3(grid), dim3(1024), shmem, st, one, tab, wg2seg);
+    else
+      hipLaunchKernelGGL((gram_tiles_kernel<false, 1024>), dim3(grid), dim3(1024), shmem, st, one, tab, wg2seg);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* partials,
                        int64_t cap, int* nwg_out, const TuneGram& tune, hipStream_t st) {
-  const int W16 = (L.Wp + 15) / 16;
-  const bool use_mfma = (mode == 0) && L.Wp >= 16 && W16 <= 5;
-  if (use_mfma) {
-    const int64_t ngroups = (s.m + 3) / 4;
-    int nwg = tune.nwg > 0 ? tune.nwg : 1024;
-    const int64_t need = (ngroups + 3) / 4;
-    if (nwg > need) nwg = (int)(need > 0 ? need : 1);
-    if ((int64_t)nwg * L.E > cap) return hipErrorInvalidValue;
-    GramLayout LL = L;
-    switch (W16) {
-      case 1: hipLaunchKernelGGL((gram_mfma_kernel<1, 4>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
-      case 2: hipLaunchKernelGGL((gram_mfma_kernel<2, 4>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
-      case 3: hipLaunchKernelGGL((gram_mfma_kernel<3, 2>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
-      case 4: hipLaunchKernelGGL((gram_mfma_kernel<4, 2>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
-      default: hipLaunchKernelGGL((gram_mfma_kernel<5, 2>), dim3(nwg), dim3(256), 0, st, s, LL, ngroups, partials); break;
-    }
-    *nwg_out = nwg;
-    return hipGetLastError();
-  }
-  const int NT = tiles_threads(L.ntiles);
-  const int S = NT / L.ntiles;
-  if (S < 1) return hipErrorInvalidValue;
-  if (L.E > kMaxQ * NT) return hipErrorInvalidValue;
-  const int P = 8 * (NT / L.Wp);  // rows per panel: 8 load steps of NT / Wp rows
-  const int64_t npanels = (s.m + P - 1) / P;
+  const int kind = gram_kind(L, mode);
+  const int NT = kind == 0 ? 256 : gram_tiles_threads(L);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
-  if (nwg > npanels) nwg = (int)(npanels > 0 ? npanels : 1);
+  const int mx = gram_max_wg(s, L, mode, NT);
+  if (nwg > mx) nwg = mx;
   if ((int64_t)nwg * L.E * (mode ? 2 : 1) > cap) return hipErrorInvalidValue;
-  const int panel = P * (L.Wp + 2);
-  const int redn = L.E * (mode ? 2 : 1);
-  const size_t shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
-  if (NT == 256) {
-    if (mode == 1)
-      hipLaunchKernelGGL((gram_tiles_kernel<true, 256>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
-    else
-      hipLaunchKernelGGL((gram_tiles_kernel<false, 256>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
-  } else {
-    if (mode == 1)
-      hipLaunchKernelGGL((gram_tiles_kernel<true, 1024>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
-    else
-      hipLaunchKernelGGL((gram_tiles_kernel<false, 1024>), dim3(nwg), dim3(NT), shmem, st, s, L, P, npanels, S, partials);
-  }
+  GramSeg g;
+  size_t shmem = 0;
+  if (!gram_seg(s, L, mode, NT, partials, 0, nwg, &g, &shmem)) return hipErrorInvalidValue;
+  const int arg = kind == 0 ? (L.Wp + 15) / 16 : NT;
   *nwg_out = nwg;
+  return launch_gram_segs(kind, mode, arg, shmem, nwg, g, nullptr, nullptr, st);
+}
+
+hipError_t launch_reduce_segs(int mode, int maxE, int nseg, const ReduceSeg& one,
+                              const ReduceSeg* tab, hipStream_t st) {
+  const int nb = (maxE + 63) / 64;
+  if (nb < 1 || nseg < 1) return hipSuccess;
+  if (mode == 1)
+    hipLaunchKernelGGL(reduce_kernel<true>, dim3(nb, nseg), dim3(1024), 0, st, one, tab);
+  else
+    hipLaunchKernelGGL(reduce_kernel<false>, dim3(nb, nseg), dim3(1024), 0, st, one, tab);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
                          double* G_hi, double* G_lo, hipStream_t st) {
-  const int nb = (L.E + 63) / 64;
-  if (mode == 1)
-    hipLaunchKernelGGL(reduce_kernel<true>, dim3(nb), dim3(1024), 0, st, L, partials, nwg, G_hi, G_lo);
-  else
-    hipLaunchKernelGGL(reduce_kernel<false>, dim3(nb), dim3(1024), 0, st, L, partials, nwg, G_hi, G_lo);
-  return hipGetLastError();
+  ReduceSeg r{L, partials, nwg, G_hi, G_lo};
+  return launch_reduce_segs(mode, L.E, 1, r, nullptr, st);
 }
 
 __global__ void fill_int_kernel(int* p, int n, int v) {

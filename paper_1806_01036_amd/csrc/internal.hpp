@@ -37,12 +37,38 @@ struct TuneGram {
 };
 
 // ---- launchers (all enqueue on `st`, return hipError_t) -------------------
+//
+// Every sweep kernel can cover several independent blocks in one launch:
+// block b owns workgroups [wg0, wg0 + nwg) of the grid and streams its own
+// rows with that many workgroups.  A single-block launch passes its segment
+// by value (tab == nullptr, wg0 = 0, nwg = grid size); a batched launch
+// passes a device table of segments and a workgroup -> segment map.
+
+// One block of a Gram sweep.
+struct GramSeg {
+  Src s;
+  GramLayout L;
+  double* part;    // nwg partials of E (FP64) or 2E (DD) doubles
+  int64_t nunits;  // row panels (tile kernel) or 4-row groups (MFMA kernel)
+  int P, S;        // tile kernel: rows per panel, row phases
+  int wg0, nwg;
+};
 
 // Gram sweep over [Y | X]: writes nwg partials (FP64: E doubles each, DD: 2E).
 // mode: 0 = FP64, 1 = DD.  Returns the number of partials in *nwg_out.
 hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* partials,
                        int64_t partial_cap_doubles, int* nwg_out, const TuneGram& tune,
                        hipStream_t st);
+// Pieces of launch_gram for the batched driver.
+int gram_kind(const GramLayout& L, int mode);  // 0 MFMA (binary64), 1 VALU tiles
+int gram_tiles_threads(const GramLayout& L);   // 256 or 1024
+int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT);
+bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part, int wg0,
+              int nwg, GramSeg* out, size_t* shmem);
+// kind 0: NT_or_T = column blocks (Wp / 16, rounded up); kind 1: threads.
+hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int grid,
+                            const GramSeg& one, const GramSeg* tab, const int* wg2seg,
+                            hipStream_t st);
 
 // Split-BF16 Gram of an fp32 X (k <= 64, no Y): FP64 partials (E per WG).
 hipError_t launch_gram_split(const Src& s, const GramLayout& L, double* partials,
@@ -51,8 +77,18 @@ hipError_t launch_gram_split(const Src& s, const GramLayout& L, double* partials
 
 // Reduce nwg partials (fixed order) into G_hi / G_lo, unpadded W x W with
 // W = ky + k (ld = W).  mode 1 = DD partials.
+struct ReduceSeg {
+  GramLayout L;
+  const double* part;
+  int nwg;
+  double* Ghi;
+  double* Glo;
+};
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
                          double* G_hi, double* G_lo, hipStream_t st);
+// nseg segments (grid.y), maxE = the largest L.E among them.
+hipError_t launch_reduce_segs(int mode, int maxE, int nseg, const ReduceSeg& one,
+                              const ReduceSeg* tab, hipStream_t st);
 
 // k x k factorization, one workgroup.
 struct FactorArgs {
@@ -75,6 +111,9 @@ struct FactorArgs {
   double* Rp_out;           // optional this-pass R (k x k)
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
+// One workgroup per entry of the device table `tab` (n entries, all with
+// k <= kmax and the same dd / fact); `one` describes the widest entry.
+hipError_t launch_factor_table(const FactorArgs& one, const FactorArgs* tab, int n, hipStream_t st);
 
 // Update sweep: rows of [Y | S] where S is X (pass 1) or Q_1; stage 1
 // computes T = (S - Y C1) Z1; with two_stage, T = (T - Y C2) Z2.  The
@@ -98,7 +137,7 @@ struct UpdateArgs {
 hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tune,
                          hipStream_t st);
 
-// Device-side argument block of the update kernels.
+// Device-side argument block of the update kernels (one block's segment).
 struct UpdDev {
   const double* Y;
   int64_t ldy;
@@ -113,13 +152,32 @@ struct UpdDev {
   int64_t ldq;
   double* part;
   int64_t npanels;
+  const double* W1;  // stage coefficients (K x K Z, ky x K W, zero padded)
+  const double* Z1;
+  const double* W2;
+  const double* Z2;
+  int wg0, nwg;
+};
+// Kernel class of an update launch.
+struct UpdClass {
+  int K;       // padded width 4, 8, 16, 32, 64
+  int KYP;     // Y class: 0, 16 or 64
+  int two;     // second stage
+  int gr;      // 0 no Gram, 1 Gram of T, 2 Gram of [Y | T]
+  int f32;     // X stored as fp32
 };
 // One per padded width K (separate translation units, compiled in parallel).
-hipError_t launch_update_k4(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
-hipError_t launch_update_k8(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
-hipError_t launch_update_k16(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
-hipError_t launch_update_k32(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
-hipError_t launch_update_k64(const UpdDev&, const UpdateArgs&, int nwg, hipStream_t);
+hipError_t launch_update_k4(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);
+hipError_t launch_update_k8(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);
+hipError_t launch_update_k16(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);
+hipError_t launch_update_k32(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);
+hipError_t launch_update_k64(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);
+hipError_t launch_update_class(const UpdClass&, int grid, const UpdDev& one, const UpdDev* tab,
+                               const int* wg2seg, hipStream_t st);
+int update_waves(int K, int KYP);  // waves per workgroup of a class
+// Layout of the fused Gram of an update sweep (of [Y | T] with Y padded to
+// 16 columns when with_y, else of T).
+GramLayout update_gram_layout(int ky, int k, int K, bool with_y);
 
 // W = -C Z (ky x kp, zero padded) for the public update entry point.
 hipError_t launch_neg_cz(const double* C, const double* Z, double* W, int ky, int k, int kp,
@@ -127,38 +185,5 @@ hipError_t launch_neg_cz(const double* C, const double* Z, double* W, int ky, in
 
 // Fill helper (graph-safe replacement for hipMemsetAsync).
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
-
-// Batched path (one launch per phase over all blocks).
-struct BatchDesc {
-  // per block
-  const double* X; int64_t ldx;
-  const double* Y; int64_t ldy;
-  double* Q; int64_t ldq;
-  double* R; double* C;
-  int64_t m;
-  int k, kp, ky, kyp;
-  int64_t panel0;    // first global panel index of this block
-  int64_t npanels;
-  int64_t part_off;  // offset (doubles) of this block's partial slots
-  int nslots;        // partial slots of this block
-  int64_t ws_off;    // offset (doubles) of this block's k x k workspace
-};
-struct BatchPlan {
-  BatchDesc* d_desc;  // device array
-  int nblocks;
-  int64_t total_panels;
-  int rows;           // rows per panel
-  double* partials;
-  double* ws;         // per-block small workspace
-  int* status;        // 4 ints per block
-  int gram_mode;      // 0 FP64, 1 DD for pass 1
-  int passes;
-  int project_each;
-  double shift_rel;
-};
-hipError_t launch_batch_gram(const BatchPlan& p, int pass, hipStream_t st);
-hipError_t launch_batch_factor(const BatchPlan& p, int pass, hipStream_t st);
-hipError_t launch_batch_update(const BatchPlan& p, int pass, int last, hipStream_t st);
-int64_t batch_ws_doubles_per_block();
 
 }  // namespace borth

@@ -1,25 +1,41 @@
 // Basis update sweep (TSMM), "Y = Xt Z" of Sec. 4.2 with the phase-I
-// projection folded in:  T = (S - Y C) Z  per row, S = X (first pass) or
-// Q_1 (later passes).  Optionally a second stage T = (T - Y C2) Z2 follows in
-// registers (CholQR2 with Q_1 recomputed instead of stored), and the Gram
-// matrix of [Y | T] needed by the next pass is accumulated from the values
-// just computed ("kernel fusion ... to further reduce memory accesses",
-// Sec. 4.2).
-//
-// Layout: a workgroup has NW waves; each wave owns a 64-row panel of [Y | S]
-// in LDS (row stride Wp + 2 doubles: conflict-free 16-byte row reads).
-//   1. coalesced global -> LDS load of the panel (zero-filled outside m, k, ky);
-//   2. lane r computes row r: xt = s - y C (FMAs, C and Z are wave-uniform
-//      and come through scalar loads), then t_j = sum_{i<=j} xt_i Z_ij (all i
-//      for a dense Z), written back into the row;
-//   3. coalesced LDS -> global store of T (if Q is given);
-//   4. the Gram of [Y | T] over the panel on the matrix cores
-//      (v_mfma_f64_16x16x4, operands read from LDS), accumulated per wave.
-// The waves' Gram accumulators are summed in wave order at the end and
-// written as one partial per workgroup (same tile layout as the Gram sweep).
+// projection folded in: T = (S - Y C) Z = S Z + Y W per row (W = -C Z),
+// S = X (first pass) or Q_1 (later passes); optionally a second stage and
+// the next pass's Gram matrix fused in (kernels in update_impl.hpp, one
+// translation unit per padded width K).  This file holds the host-side
+// dispatch.
 #include "update_impl.hpp"
 
 namespace borth {
+
+int update_waves(int K, int KYP) { return upd::upd_waves(K, KYP); }
+
+GramLayout update_gram_layout(int ky, int k, int K, bool with_y) {
+  GramLayout G;
+  if (with_y) {
+    G = make_layout(ky, k, K);
+    G.kyp = 16;
+    G.Wp = 16 + G.kp;
+    G.T4 = G.Wp / 4;
+    G.ntiles = G.T4 * (G.T4 + 1) / 2;
+    G.E = 16 * G.ntiles;
+  } else {
+    G = make_layout(0, k, K);
+  }
+  return G;
+}
+
+hipError_t launch_update_class(const UpdClass& c, int grid, const UpdDev& one, const UpdDev* tab,
+                               const int* wg2seg, hipStream_t st) {
+  switch (c.K) {
+    case 4: return launch_update_k4(c, grid, one, tab, wg2seg, st);
+    case 8: return launch_update_k8(c, grid, one, tab, wg2seg, st);
+    case 16: return launch_update_k16(c, grid, one, tab, wg2seg, st);
+    case 32: return launch_update_k32(c, grid, one, tab, wg2seg, st);
+    case 64: return launch_update_k64(c, grid, one, tab, wg2seg, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tune,
                          hipStream_t st) {
@@ -36,17 +52,8 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   const int KYP = L.kyp == 0 ? 0 : (L.kyp <= 16 ? 16 : 64);
   // Fused Gram of [Y | T] (Y padded to 16 columns) or of T alone.
   const bool gy = a.gram_with_y && L.kyp > 0;
-  GramLayout G;
-  if (gy) {
-    G = make_layout(L.ky, L.k, K);
-    G.kyp = 16;
-    G.Wp = 16 + G.kp;
-    G.T4 = G.Wp / 4;
-    G.ntiles = G.T4 * (G.T4 + 1) / 2;
-    G.E = 16 * G.ntiles;
-  } else {
-    G = make_layout(0, L.k, K);
-  }
+  if (a.partials && gy && L.kyp > 16) return hipErrorInvalidValue;
+  const GramLayout G = update_gram_layout(L.ky, L.k, K, gy);
   d.gE = G.E;
   a.glayout = G;
   d.dense = a.dense;
@@ -55,21 +62,25 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.ldq = a.ldq;
   d.part = a.partials;
   d.npanels = (a.src.m + 63) / 64;
-  if (a.partials && gy && L.kyp > 16) return hipErrorInvalidValue;
+  d.W1 = a.W1;
+  d.Z1 = a.Z1;
+  d.W2 = a.W2;
+  d.Z2 = a.Z2;
   const int NW = upd::upd_waves(K, KYP);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   const int64_t need = (d.npanels + NW - 1) / NW;
   if (nwg > need) nwg = (int)(need > 0 ? need : 1);
   if (a.partials && (int64_t)nwg * G.E > a.partial_cap_doubles) return hipErrorInvalidValue;
   a.nwg = nwg;
-  switch (K) {
-    case 4: return launch_update_k4(d, a, nwg, st);
-    case 8: return launch_update_k8(d, a, nwg, st);
-    case 16: return launch_update_k16(d, a, nwg, st);
-    case 32: return launch_update_k32(d, a, nwg, st);
-    case 64: return launch_update_k64(d, a, nwg, st);
-    default: return hipErrorInvalidValue;
-  }
+  d.wg0 = 0;
+  d.nwg = nwg;
+  UpdClass c;
+  c.K = K;
+  c.KYP = KYP;
+  c.two = a.two_stage ? 1 : 0;
+  c.gr = !a.partials ? 0 : (gy ? 2 : 1);
+  c.f32 = a.src.x_f32;
+  return launch_update_class(c, nwg, d, nullptr, nullptr, st);
 }
 
 

@@ -64,12 +64,11 @@ inline int upd_waves(int K, int KYP) {
 
 // GR: 0 = no Gram, 1 = Gram of T, 2 = Gram of [Y | T] (KYP = 16).
 template <int K, int KYP, bool TWO, int GR, typename ST>
-__global__ void __launch_bounds__(512) update_kernel(UpdDev a,
-                                                     const double* __restrict__ W1,
-                                                     const double* __restrict__ Z1,
-                                                     const double* __restrict__ W2,
-                                                     const double* __restrict__ Z2) {
+__global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* __restrict__ tab,
+                                                     const int* __restrict__ wg2seg) {
   extern __shared__ double lds[];
+  const UpdDev a = tab ? tab[wg2seg[blockIdx.x]] : one;
+  const int wg = (int)blockIdx.x - a.wg0;
   constexpr int S = KYP + K + 2;     // LDS row stride (doubles)
   constexpr int KC = (K + 15) / 16;  // 16-column blocks of T
   constexpr int KV = K < 16 ? K : 16;  // valid columns per T block
@@ -94,8 +93,8 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev a,
   double wb[NST][YS > 0 ? YS : 1][KC];
 #pragma unroll
   for (int st = 0; st < NST; ++st) {
-    const double* __restrict__ Zg = st ? Z2 : Z1;
-    const double* __restrict__ Wg = st ? W2 : W1;
+    const double* __restrict__ Zg = st ? a.Z2 : a.Z1;
+    const double* __restrict__ Wg = st ? a.W2 : a.W1;
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
@@ -116,8 +115,8 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev a,
 #pragma unroll
   for (int i = 0; i < NTL; ++i) gacc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t wstride = (int64_t)gridDim.x * NW;
-  int64_t pnl = (int64_t)blockIdx.x * NW + wave;
+  const int64_t wstride = (int64_t)a.nwg * NW;
+  int64_t pnl = (int64_t)wg * NW + wave;
   constexpr int KY1 = KYP > 0 ? KYP : 1;
   constexpr int RY = 64 / KY1;
   const int ry0 = lane / KY1, cy = lane % KY1;
@@ -257,7 +256,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev a,
     if (YB && B == 0) return x;
     return x < KV ? YB * KYP + 16 * (B - YB) + x : -1;
   };
-  double* out = a.part + (int64_t)blockIdx.x * a.gE;
+  double* out = a.part + (int64_t)wg * a.gE;
   int idx = 0;
 #pragma unroll
   for (int I = 0; I < T16; ++I)
@@ -277,49 +276,51 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev a,
 }
 
 template <int K, int KYP, bool TWO, int GR, typename ST>
-hipError_t launch_upd_t(const UpdDev& d, const UpdateArgs& a, int nwg, hipStream_t st) {
+hipError_t launch_upd_t(int grid, const UpdDev& one, const UpdDev* tab, const int* map,
+                        hipStream_t st) {
   const int NW = upd_waves(K, KYP);
   constexpr int KC = (K + 15) / 16;
   constexpr int T16 = (GR == 2 ? 1 : 0) + KC;
   const size_t red = GR ? sizeof(double) * T16 * (T16 + 1) / 2 * 4 * 64 : 0;
   const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW);
   const size_t shmem = lb > red ? lb : red;
-  hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST>), dim3(nwg), dim3(64 * NW), shmem, st,
-                     d, a.W1, a.Z1, a.W2, a.Z2);
+  hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST>), dim3(grid), dim3(64 * NW), shmem, st,
+                     one, tab, map);
   return hipGetLastError();
 }
 
 // Dispatch on the Y padding class, the two-stage flag and the Gram kind.
 template <int K>
-hipError_t launch_upd_k(const UpdDev& d, const UpdateArgs& a, int nwg, hipStream_t st) {
-  const bool gram = d.part != nullptr;
-  if (a.src.x_f32) {
-    if (a.two_stage || d.kyp) return hipErrorInvalidValue;
-    return gram ? launch_upd_t<K, 0, false, 1, float>(d, a, nwg, st)
-                : launch_upd_t<K, 0, false, 0, float>(d, a, nwg, st);
+hipError_t launch_upd_k(const UpdClass& c, int grid, const UpdDev& one, const UpdDev* tab,
+                        const int* map, hipStream_t st) {
+  if (grid < 1) return hipSuccess;
+  if (c.f32) {
+    if (c.two || c.KYP || c.gr == 2) return hipErrorInvalidValue;
+    return c.gr ? launch_upd_t<K, 0, false, 1, float>(grid, one, tab, map, st)
+                : launch_upd_t<K, 0, false, 0, float>(grid, one, tab, map, st);
   }
-  if (d.kyp == 0) {
-    if (a.two_stage)
-      return gram ? launch_upd_t<K, 0, true, 1, double>(d, a, nwg, st)
-                  : launch_upd_t<K, 0, true, 0, double>(d, a, nwg, st);
-    return gram ? launch_upd_t<K, 0, false, 1, double>(d, a, nwg, st)
-                : launch_upd_t<K, 0, false, 0, double>(d, a, nwg, st);
+  if (c.KYP == 0) {
+    if (c.gr == 2) return hipErrorInvalidValue;
+    if (c.two)
+      return c.gr ? launch_upd_t<K, 0, true, 1, double>(grid, one, tab, map, st)
+                  : launch_upd_t<K, 0, true, 0, double>(grid, one, tab, map, st);
+    return c.gr ? launch_upd_t<K, 0, false, 1, double>(grid, one, tab, map, st)
+                : launch_upd_t<K, 0, false, 0, double>(grid, one, tab, map, st);
   }
-  if (d.kyp <= 16) {
-    const int gr = !gram ? 0 : (a.gram_with_y ? 2 : 1);
-    if (a.two_stage) {
-      if (gr == 2) return launch_upd_t<K, 16, true, 2, double>(d, a, nwg, st);
-      if (gr == 1) return launch_upd_t<K, 16, true, 1, double>(d, a, nwg, st);
-      return launch_upd_t<K, 16, true, 0, double>(d, a, nwg, st);
+  if (c.KYP == 16) {
+    if (c.two) {
+      if (c.gr == 2) return launch_upd_t<K, 16, true, 2, double>(grid, one, tab, map, st);
+      if (c.gr == 1) return launch_upd_t<K, 16, true, 1, double>(grid, one, tab, map, st);
+      return launch_upd_t<K, 16, true, 0, double>(grid, one, tab, map, st);
     }
-    if (gr == 2) return launch_upd_t<K, 16, false, 2, double>(d, a, nwg, st);
-    if (gr == 1) return launch_upd_t<K, 16, false, 1, double>(d, a, nwg, st);
-    return launch_upd_t<K, 16, false, 0, double>(d, a, nwg, st);
+    if (c.gr == 2) return launch_upd_t<K, 16, false, 2, double>(grid, one, tab, map, st);
+    if (c.gr == 1) return launch_upd_t<K, 16, false, 1, double>(grid, one, tab, map, st);
+    return launch_upd_t<K, 16, false, 0, double>(grid, one, tab, map, st);
   }
   // 16 < ky <= 64: single stage; a fused Gram covers T only
-  if (a.two_stage || (gram && a.gram_with_y)) return hipErrorInvalidValue;
-  return gram ? launch_upd_t<K, 64, false, 1, double>(d, a, nwg, st)
-              : launch_upd_t<K, 64, false, 0, double>(d, a, nwg, st);
+  if (c.KYP != 64 || c.two || c.gr == 2) return hipErrorInvalidValue;
+  return c.gr ? launch_upd_t<K, 64, false, 1, double>(grid, one, tab, map, st)
+              : launch_upd_t<K, 64, false, 0, double>(grid, one, tab, map, st);
 }
 
 }  // namespace upd

@@ -2,7 +2,8 @@
 #include "update_impl.hpp"
 
 namespace borth {
-hipError_t launch_update_k64(const UpdDev& d, const UpdateArgs& a, int nwg, hipStream_t st) {
-  return upd::launch_upd_k<64>(d, a, nwg, st);
+hipError_t launch_update_k64(const UpdClass& c, int grid, const UpdDev& one, const UpdDev* tab,
+                              const int* map, hipStream_t st) {
+  return upd::launch_upd_k<64>(c, grid, one, tab, map, st);
 }
 }  // namespace borth

@@ -14,6 +14,12 @@ condition number but does not say how they are built.  The recipe used here:
 * X = U diag(sigma) V^T, formed in float64 (optionally rounded to float32).
 * The locked basis Y is another Haar matrix, drawn independently.
 
+For the full-size benchmark blocks (tens of GB) the same recipe runs on the
+GPU with torch's seeded Philox generator (``svd_matrix_device``): same
+distribution, different random stream from the numpy one, so those inputs are
+checked through properties (orthogonality, residual) rather than against the
+oracle element by element.
+
 Exact families (Sylvester-Hadamard columns) are provided for bitwise tests:
 with m = 4**j rows, column c of the normalized Hadamard matrix has entries
 (-1)**popcount(i & c) * 2**-j, which are exactly orthonormal in binary64.
@@ -32,6 +38,8 @@ __all__ = [
     "hadamard_near_parallel",
     "batch_table",
     "projected_pair",
+    "svd_matrix_device",
+    "locked_basis_device",
 ]
 
 
@@ -152,3 +160,35 @@ def batch_table(nblocks: int = 256, seed: int = 5000, m_lo: int = 10_000,
     kap = np.power(10.0, rng.uniform(log_kappa[0], log_kappa[1], size=nblocks))
     return [dict(m=int(ms[b]), k=int(ks[b]), kappa=float(kap[b]),
                  seed=int(seed + 1 + b)) for b in range(nblocks)]
+
+
+def _haar_device(torch, gen, m: int, k: int, device):
+    g = torch.randn((m, k), generator=gen, dtype=torch.float64, device=device)
+    q, r = torch.linalg.qr(g, mode="reduced")
+    s = torch.sign(torch.diagonal(r))
+    s[s == 0] = 1.0
+    return (q * s[None, :]).contiguous()
+
+
+def svd_matrix_device(m: int, k: int, kappa: float, seed: int, device="cuda", dtype=None):
+    """X = U diag(sigma) V^T drawn on the device (torch Philox stream seeded
+    with ``seed``; U first, then V).  Same recipe as ``svd_matrix``."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    u = _haar_device(torch, gen, m, k, device)
+    v = _haar_device(torch, gen, k, k, device)
+    sig = torch.from_numpy(sigma_logspace(k, kappa)).to(device)
+    x = (u * sig[None, :]) @ v.t().contiguous()
+    del u
+    if dtype is not None:
+        x = x.to(dtype)
+    return x.contiguous()
+
+
+def locked_basis_device(m: int, ky: int, seed: int, device="cuda"):
+    """Haar m x ky locked basis drawn on the device (seeded Philox stream)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    return _haar_device(torch, gen, m, ky, device)

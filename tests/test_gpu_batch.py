@@ -1,0 +1,217 @@
+"""GPU tests of the batched path (many independent blocks per launch).
+
+Every block of a batch must satisfy what the single-block method guarantees
+(oracle metrics: rho, omega, omega_Y <= 1e-14 for DD CholQR2 with the
+projection repeated, Sec. 4.2), results must not depend on the other blocks
+(a breakdown stays in its block), graph replays and in-place runs are
+bitwise identical to the eager run, and the autotune table round-trips.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import U64, dev, host, lib, note, rel_fro, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _blocks(specs):
+    """specs: (m, k, ky, kappa, seed) -> host arrays and device blocks."""
+    hostb, devb = [], []
+    for (m, k, ky, kappa, seed) in specs:
+        X = synth.svd_matrix(m, k, kappa, seed)
+        Y = synth.locked_basis(m, ky, seed + 7777) if ky else None
+        hostb.append((X, Y))
+        d = {"X": dev(X)}
+        if ky:
+            d["Y"] = dev(Y)
+        devb.append(d)
+    return hostb, devb
+
+
+MIXED = [(3001, 8, 16, 1e3, 11), (12007, 32, 16, 1e9, 12), (2500, 64, 16, 1e5, 13),
+         (7003, 16, 0, 1e10, 14), (20011, 13, 5, 1e7, 15), (4099, 1, 0, 1.0, 16),
+         (9001, 40, 16, 1e8, 17), (15013, 64, 0, 1e6, 18), (5000, 20, 3, 1e4, 19),
+         (6007, 3, 16, 1e2, 20)]
+
+
+def test_batch_dd_cholqr2_vs_oracle():
+    """DD-Gram CholQR2 with the projection repeated (P,C,P,C) on ten blocks
+    of uneven height, width and conditioning (kappa up to 1e10)."""
+    borth = lib()
+    hostb, devb = _blocks(MIXED)
+    outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2)
+    for (X, Y), (Q, R, C), inf, spec in zip(hostb, outs, infos, MIXED):
+        note("block", spec, inf)
+        assert inf.status == 0 and inf.passes_run == 2
+        met = oracle.metrics(host(Q), X, host(R), Y, host(C) if C is not None else None)
+        note("  ", met)
+        assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+        if Y is not None:
+            assert met["omega_y"] <= 1e-14
+            o1 = oracle.qr_q(X, Y)
+            assert np.max(np.abs(host(C) - o1["C"])) <= 1e-13
+        Rh = host(R)
+        assert np.all(np.tril(Rh, -1) == 0) and np.all(np.diag(Rh) > 0)
+
+
+def test_batch_matches_single_block_path():
+    """The batched sweeps split each block over a different number of
+    workgroups than the single-block call, so results agree to rounding:
+    both R factors within 1e3 kappa u of each other, both Q orthonormal."""
+    borth = lib()
+    specs = MIXED[:5]
+    hostb, devb = _blocks(specs)
+    outs, _ = borth.batch_orthonormalize(devb, gram="dd", passes=2)
+    for (X, Y), d, (Qb, Rb, Cb), spec in zip(hostb, devb, outs, specs):
+        Qs, Rs, Cs, info = borth.orthonormalize(d["X"], d.get("Y"), gram="dd", passes=2)
+        assert info.status == 0
+        kappa = max(spec[3], 1.0)
+        assert rel_fro(host(Rb), host(Rs)) <= 1e3 * kappa * U64
+        assert rel_fro(host(Qb), host(Qs)) <= 1e3 * kappa * U64
+
+
+def test_batch_graph_replay_and_in_place():
+    borth = lib()
+    torch = torch_gpu()
+    specs = MIXED[:6]
+    hostb, devb = _blocks(specs)
+    ref, _ = borth.batch_orthonormalize(devb, gram="dd", passes=2)
+    ref = [(Q.clone(), R.clone()) for (Q, R, _) in ref]
+    # graph: captured once, replayed; outputs preallocated
+    for d, (Q, R) in zip(devb, ref):
+        d["Q"] = torch.empty_like(Q)
+        d["R"] = torch.empty_like(R)
+    for rep in range(3):
+        for d in devb:
+            d["Q"].fill_(0.0)
+        outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2, graph=True)
+        torch.cuda.synchronize()
+        junk = torch.randn(512, 512, device="cuda", dtype=torch.float64).sum()  # eager work
+        torch.cuda.synchronize()
+        del junk
+        for (Q, R, _), (Qr, Rr), inf in zip(outs, ref, infos):
+            assert inf.status == 0
+            assert torch.equal(Q, Qr) and torch.equal(R, Rr), rep
+    # in place: Q = X
+    for d in devb:
+        d["X"] = d["X"].clone()
+        d["Q"] = d["X"]
+    outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2)
+    for (Q, R, _), (Qr, Rr), inf in zip(outs, ref, infos):
+        assert inf.status == 0
+        assert torch.equal(Q, Qr) and torch.equal(R, Rr)
+
+
+def test_batch_breakdown_stays_in_its_block():
+    """A rank-deficient block (exact Hadamard duplicate column: pivot 5 is 0
+    in every precision) reports its own breakdown; its neighbours finish."""
+    borth = lib()
+    Xbad = synth.hadamard_columns(6, [1, 2, 3, 4, 2, 5])
+    good = [synth.svd_matrix(5000, 8, 1e6, 31), synth.svd_matrix(7000, 24, 1e4, 32)]
+    devb = [{"X": dev(good[0])}, {"X": dev(Xbad)}, {"X": dev(good[1])}]
+    for gram in ("f64", "dd"):
+        outs, infos = borth.batch_orthonormalize(devb, gram=gram, passes=2, check=False)
+        assert infos[1].status == 4 and infos[1].failed_pass == 1 and infos[1].failed_pivot == 5
+        for i in (0, 2):
+            assert infos[i].status == 0
+            X = good[0] if i == 0 else good[1]
+            met = oracle.metrics(host(outs[i][0]), X, host(outs[i][1]))
+            assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+
+
+@pytest.mark.parametrize("gram,fact,passes,project_once", [
+    ("f64", "chol", 2, False), ("f64", "chol", 1, False), ("dd", "chol", 3, False),
+    ("dd", "chol", 2, True), ("f64", "svqb", 2, False)])
+def test_batch_options(gram, fact, passes, project_once):
+    borth = lib()
+    specs = [(4001, 8, 16, 1e3, 41), (9001, 32, 0, 1e5, 42), (3003, 17, 16, 1e4, 43),
+             (6001, 64, 16, 1e2, 44)]
+    hostb, devb = _blocks(specs)
+    outs, infos = borth.batch_orthonormalize(devb, gram=gram, fact=fact, passes=passes,
+                                             project_once=project_once)
+    for (X, Y), (Q, R, C), inf, spec in zip(hostb, outs, infos, specs):
+        assert inf.status == 0 and inf.passes_run == passes
+        met = oracle.metrics(host(Q), X, host(R), Y, host(C) if C is not None else None)
+        note(gram, fact, passes, project_once, spec, met)
+        kappa, k = spec[3], spec[1]
+        if fact == "svqb":
+            # binary64 SVQB: the dense symmetric Z is applied as a product, so
+            # the residual carries k kappa u (CholQR's triangular structure
+            # keeps its residual O(u)), and omega is the orthogonality level
+            # of the Jacobi eigenvectors, O(k u).  The single-block path lands
+            # at the same levels on the same input.
+            Qs, Rs, Cs, _ = borth.orthonormalize(devb[specs.index(spec)]["X"],
+                                                 devb[specs.index(spec)].get("Y"),
+                                                 gram=gram, fact=fact, passes=passes)
+            ms = oracle.metrics(host(Qs), X, host(Rs), Y, host(Cs) if Cs is not None else None)
+            note("  single block:", ms)
+            assert met["rho"] <= max(1e-14, k * kappa * U64)
+            assert met["rho"] <= 4 * ms["rho"] + 1e-15
+            assert met["omega"] <= 20 * k * U64
+            assert met["omega"] <= 4 * ms["omega"] + 1e-15
+            continue
+        assert met["rho"] <= 1e-14
+        if passes == 1:
+            # one plain pass: omega ~ c kappa^2 u (binary64 Gram)
+            assert met["omega"] <= 10 * spec[1] * kappa ** 2 * U64
+        else:
+            assert met["omega"] <= 1e-14
+        if Y is not None and not project_once and passes >= 2:
+            assert met["omega_y"] <= 1e-14
+
+
+def test_batch_c5_shape_reduced():
+    """The batched workload's recipe (rows uniform, widths {8,16,32,64},
+    kappa log-uniform in [1e3, 1e10], a 16-column locked basis per block) at
+    reduced heights: 24 blocks, per-block omega / rho / omega_Y <= 1e-14."""
+    borth = lib()
+    table = synth.batch_table(24, seed=5000, m_lo=10_000, m_hi=60_000)
+    specs = [(t["m"], t["k"], 16, t["kappa"], t["seed"]) for t in table]
+    hostb, devb = _blocks(specs)
+    outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2, graph=True)
+    for (X, Y), (Q, R, C), inf, spec in zip(hostb, outs, infos, specs):
+        assert inf.status == 0
+        met = oracle.metrics(host(Q), X, host(R), Y, host(C))
+        assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14 and met["omega_y"] <= 1e-14, (spec, met)
+
+
+def test_batch_argument_errors():
+    borth = lib()
+    X = dev(np.zeros((100, 8)))
+    with pytest.raises(borth.BorthError):
+        borth.batch_orthonormalize([{"X": dev(np.zeros((5, 8)))}])  # m < k
+    with pytest.raises(borth.BorthError):
+        borth.batch_orthonormalize([{"X": X, "Y": dev(np.zeros((100, 20)))}])  # ky > 16
+    with pytest.raises(borth.BorthError):
+        borth.batch_orthonormalize([{"X": dev(np.zeros((100, 8), np.float32))}], gram="split")
+
+
+def test_autotune_roundtrip(tmp_path):
+    borth = lib()
+    ctx = borth.Context(0)
+    try:
+        path = tmp_path / "tune.json"
+        ctx.autotune(path, budget_ms=1500)
+        txt = path.read_text()
+        assert '"op": "gram"' in txt
+        ctx.autotune_load(path)
+        bad = tmp_path / "bad.json"
+        bad.write_text("{}\n")
+        with pytest.raises(borth.BorthError):
+            ctx.autotune_load(bad)
+        # the tuned shapes still give correct results (single and batched)
+        X = synth.svd_matrix(30000, 32, 1e10, 77)
+        Q, R, _, info = borth.orthonormalize(dev(X), gram="dd", ctx=ctx)
+        assert info.status == 0
+        met = oracle.metrics(host(Q), X, host(R))
+        assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+        hostb, devb = _blocks(MIXED[:3])
+        outs, infos = borth.batch_orthonormalize(devb, gram="dd", ctx=ctx)
+        for (Xh, Yh), (Qb, Rb, Cb), inf in zip(hostb, outs, infos):
+            assert inf.status == 0
+            met = oracle.metrics(host(Qb), Xh, host(Rb), Yh, host(Cb) if Cb is not None else None)
+            assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+    finally:
+        ctx.close()

@@ -162,6 +162,25 @@ def test_factor_svqb_vs_oracle():
     assert np.allclose(host(Z), host(Z).T, rtol=0, atol=1e-12 * np.abs(zex).max())
 
 
+def test_factor_svqb_near_identity_k64():
+    """Second-pass shape: M = Q_1^T Q_1 with ||M - I|| ~ 1e-10 at k = 64
+    (2016 rotations per sweep).  Z must stay within O(k u) of the exact
+    M^{-1/2} (binary128 Jacobi of the oracle): sweeps over off-diagonal
+    entries at rounding level must not keep rotating and feed noise into V."""
+    borth = lib()
+    rng = np.random.default_rng(64)
+    X = synth.svd_matrix(20000, 64, 1.0, 65) + 1e-10 * rng.standard_normal((20000, 64))
+    ghi, glo = oracle.gram_q(X)
+    M = ghi + glo
+    Z, _, _, info = borth.factor(dev(M), None, fact="svqb")
+    assert info.status == 0
+    zex, lam, _ = oracle.svqb_q(ghi, glo)
+    Zh = host(Z)
+    note(" svqb k=64 near identity:", rel_fro(Zh, zex))
+    assert rel_fro(Zh, zex) <= 10 * 64 * U64
+    assert np.linalg.norm(Zh.T @ M @ Zh - np.eye(64)) <= 20 * 64 * U64
+
+
 # ---------------------------------------------------------------------------
 # a4: update sweep
 
