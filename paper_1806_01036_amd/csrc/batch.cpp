@@ -92,20 +92,25 @@ struct TableBuf {
 
 int chol_class(int k) { return k <= 8 ? 0 : k <= 16 ? 1 : k <= 32 ? 2 : k <= 48 ? 3 : 4; }
 
-// Workgroups of each block of a group: proportional to its rows, at least
-// one, at most what the block can use; `target` for the whole group.
-std::vector<int> share_wgs(const std::vector<int64_t>& rows, const std::vector<int>& cap, int target) {
-  int64_t tot = 0;
-  for (int64_t r : rows) tot += r;
+// Workgroups of each block of a group: one per `rows_per_wg` rows (the
+// share a workgroup gets in a single-block sweep, so per-workgroup
+// accumulation chains are as long as there), at least one, at most what the
+// block can use.
+constexpr int64_t kTuneRows = 1 << 21;  // rows of the autotuner's synthetic block
+std::vector<int> share_wgs(const std::vector<int64_t>& rows, const std::vector<int>& cap,
+                           int64_t rows_per_wg) {
   std::vector<int> n(rows.size());
   for (size_t i = 0; i < rows.size(); ++i) {
-    const double f = tot > 0 ? (double)rows[i] / (double)tot : 1.0;
-    int w = (int)std::llround(f * target);
+    int64_t w = (rows[i] + rows_per_wg - 1) / rows_per_wg;
     if (w < 1) w = 1;
     if (w > cap[i]) w = cap[i];
-    n[i] = w;
+    n[i] = (int)w;
   }
   return n;
+}
+int64_t rows_per_wg(const borth::TuneGram& t) {
+  const int64_t r = t.nwg > 0 ? kTuneRows / t.nwg : 4096;
+  return r < 256 ? 256 : r;
 }
 
 struct BlkWs {
@@ -187,9 +192,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       kpmax = std::max(kpmax, W[b].kp);
       hasy |= B[b].ky > 0;
     }
-    int target = lookup(c->tune_gram, gmode, kpmax, hasy).nwg;
-    if (target <= 0) target = 2048;
-    const std::vector<int> n = share_wgs(rows, cap, target);
+    const std::vector<int> n = share_wgs(rows, cap, rows_per_wg(lookup(c->tune_gram, gmode, kpmax, hasy)));
     for (size_t i = 0; i < kv.second.size(); ++i) {
       const int b = kv.second[i];
       nwg_g[b] = n[i];
@@ -225,14 +228,12 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       std::vector<int> cap;
       int hasy = 0;
       for (int b : kv.second) {
-        const int64_t np = (B[b].m + 63) / 64;
+        const int64_t np = (B[b].m + update_rows(K) - 1) / update_rows(K);
         rows.push_back(B[b].m);
         cap.push_back((int)std::max<int64_t>(1, std::min<int64_t>((np + NW - 1) / NW, 1 << 20)));
         hasy |= B[b].ky > 0;
       }
-      int target = lookup(c->tune_upd, gr ? 1 : 0, K, hasy).nwg;
-      if (target <= 0) target = 2048;
-      const std::vector<int> n = share_wgs(rows, cap, target);
+      const std::vector<int> n = share_wgs(rows, cap, rows_per_wg(lookup(c->tune_upd, gr ? 1 : 0, K, hasy)));
       for (size_t i = 0; i < kv.second.size(); ++i) {
         const int b = kv.second[i];
         nwg_u[p][b] = n[i];
@@ -387,7 +388,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         d.Q = B[b].Q;
         d.ldq = B[b].ldq;
         d.part = uc.gr ? part + W[b].part : nullptr;
-        d.npanels = (B[b].m + 63) / 64;
+        d.npanels = (B[b].m + update_rows(uc.K) - 1) / update_rows(uc.K);
         d.W1 = ws + W[b].wp[p - 1];
         d.Z1 = ws + W[b].zp[p - 1];
         d.wg0 = (int)map.size();
@@ -773,6 +774,12 @@ borth_status borth_autotune_load(borth_ctx c, const char* cache_path) {
   if (n == 0) {
     c->err = "no autotune entries found";
     return BORTH_ERR_ARG;
+  }
+  for (const TuneEntry& t : got) {
+    if (t.nwg > kMaxSweepWG) {
+      c->err = "autotune entry above the workgroup limit";
+      return BORTH_ERR_ARG;
+    }
   }
   for (const TuneEntry& t : got) {
     auto& tab = t.op == "gram" ? c->tune_gram : c->tune_upd;

@@ -294,7 +294,7 @@ int64_t partial_need(int ky, int k, int gmode) {
   GramLayout Lu = make_layout(ky <= 16 && ky > 0 ? 16 : ky, k, kp);
   int64_t e = (int64_t)L1.E * (gmode == BORTH_GRAM_DD ? 2 : 1);
   if (Lu.E > e) e = Lu.E;
-  return 1024 * e;
+  return kMaxSweepWG * e;
 }
 
 borth_status read_status(borth_ctx c, borth_info* info) {
@@ -407,7 +407,7 @@ borth_status borth_gram(borth_ctx c, int64_t m, int ka, const double* A, int64_t
     return BORTH_OK;
   }
   GramLayout L = make_layout(ka, kb, 4);
-  borth_status r = ensure(c, &c->part, &c->part_cap, 1024 * (int64_t)L.E * 2);
+  borth_status r = ensure(c, &c->part, &c->part_cap, kMaxSweepWG * (int64_t)L.E * 2);
   if (r) return r;
   int nwg = 0;
   const int kp = pow2pad(kb);

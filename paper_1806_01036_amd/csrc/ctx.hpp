@@ -66,6 +66,10 @@ inline borth_status fail_arg(borth_ctx c, const char* what) {
     if (_e != hipSuccess) return fail_hip(c, _e, where); \
   } while (0)
 
+// Largest workgroup count of a single-block sweep (default 1024; the
+// autotuner may pick up to this many); partial buffers are sized for it.
+constexpr int64_t kMaxSweepWG = 4096;
+
 inline int pow2pad(int k) {
   int p = 4;
   while (p < k) p <<= 1;

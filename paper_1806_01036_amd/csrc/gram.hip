@@ -68,7 +68,7 @@ __device__ __forceinline__ double fetch(const Src& s, const GramLayout& L, int64
 
 // ---------------------------------------------------------------------------
 // VALU tile kernel (binary64 or DD).
-constexpr int kMaxQ = 12;  // reduction entries per thread
+constexpr int kMaxQ = 12;  // reduction entries per thread (row phases > 1)
 
 template <bool DD, int NTB>
 __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
@@ -158,10 +158,26 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
     }
   }
 
+  const int E = L.E;
+  if (S == 1) {
+    // one row phase: each thread's tile is its part of the partial
+    if (!active) return;
+    double* out = g.part + (int64_t)wg * E * (DD ? 2 : 1);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      if (DD) {
+        const dd_t v = dot2_finish(acs[e], acc[e]);
+        out[2 * (t * 16 + e)] = v.hi;
+        out[2 * (t * 16 + e) + 1] = v.lo;
+      } else {
+        out[t * 16 + e] = acs[e];
+      }
+    }
+    return;
+  }
   // Combine the row phases in phase order, then write this WG's partial.
   __syncthreads();
   double* red = lds;
-  const int E = L.E;
   double sh[kMaxQ], sl[kMaxQ];
 #pragma unroll
   for (int q = 0; q < kMaxQ; ++q) {
@@ -381,7 +397,9 @@ int gram_kind(const GramLayout& L, int mode) {
   return (mode == 0 && L.Wp >= 16 && W16 <= 5) ? 0 : 1;
 }
 
-int gram_tiles_threads(const GramLayout& L) { return L.ntiles <= 40 ? 256 : 1024; }
+// 256 threads (one 4x4 tile each; row phases when there are fewer than 128
+// tiles) up to 256 tiles (Wp <= 88); wider blocks take 1024 threads.
+int gram_tiles_threads(const GramLayout& L) { return L.ntiles <= 256 ? 256 : 1024; }
 
 int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
   if (gram_kind(L, mode) == 0) return (s.m + 3) / 4;
@@ -409,10 +427,10 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
   *shmem = 0;
   if (gram_kind(L, mode) == 1) {
     g.S = NT / L.ntiles;
-    if (g.S < 1 || L.E > kMaxQ * NT || NT / L.Wp < 1) return false;
+    if (g.S < 1 || (g.S > 1 && L.E > kMaxQ * NT) || NT / L.Wp < 1) return false;
     g.P = 8 * (NT / L.Wp);
     const int panel = g.P * (L.Wp + 2);
-    const int redn = L.E * (mode ? 2 : 1);
+    const int redn = g.S > 1 ? L.E * (mode ? 2 : 1) : 0;  // one phase: no LDS reduction
     *shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
   }
   *out = g;

@@ -9,6 +9,7 @@
 namespace borth {
 
 int update_waves(int K, int KYP) { return upd::upd_waves(K, KYP); }
+int update_rows(int K) { return upd::upd_rows(K); }
 
 GramLayout update_gram_layout(int ky, int k, int K, bool with_y) {
   GramLayout G;
@@ -61,12 +62,13 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.Q = a.Q;
   d.ldq = a.ldq;
   d.part = a.partials;
-  d.npanels = (a.src.m + 63) / 64;
+  const int PR = upd::upd_rows(K);
+  d.npanels = (a.src.m + PR - 1) / PR;
   d.W1 = a.W1;
   d.Z1 = a.Z1;
   d.W2 = a.W2;
   d.Z2 = a.Z2;
-  const int NW = upd::upd_waves(K, KYP);
+  const int NW = upd::upd_waves(K, KYP, a.two_stage ? 2 : 1);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   const int64_t need = (d.npanels + NW - 1) / NW;
   if (nwg > need) nwg = (int)(need > 0 ? need : 1);

@@ -42,15 +42,27 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// LDS bytes of a workgroup with nw waves (one 64-row panel per wave).
-inline long upd_lds_bytes(int K, int KYP, int nw) { return 8L * nw * 64 * (KYP + K + 2); }
+// Widths K >= 64 keep the B operands (Z, W) in LDS, shared by the
+// workgroup's waves, and stream 16-row panels: their operands would not fit
+// the register file next to the fused Gram accumulators, and 64-row panels
+// of [Y | X] would leave fewer than one wave per SIMD under the LDS budget.
+__host__ __device__ constexpr bool upd_zl(int K) { return K >= 64; }
+__host__ __device__ constexpr int upd_rows(int K) { return upd_zl(K) ? 16 : 64; }
+__host__ __device__ constexpr int upd_zs(int K) { return K + 2; }  // LDS row stride of Z / W
+
+// LDS bytes of a workgroup with nw waves (one panel per wave, plus the
+// shared Z / W operands of each stage when they live in LDS).
+inline long upd_lds_bytes(int K, int KYP, int nw, int nst = 1) {
+  const long zreg = upd_zl(K) ? (long)nst * (K + KYP) * upd_zs(K) : 0;
+  return 8L * (zreg + (long)nw * upd_rows(K) * (KYP + K + 2));
+}
 
 // Waves per workgroup (1..8): the most resident waves per CU under the 160 KB
 // of LDS, at most 8 (2 per SIMD); larger workgroups preferred.
-inline int upd_waves(int K, int KYP) {
+inline int upd_waves(int K, int KYP, int nst = 1) {
   int best = 1, best_waves = 0;
   for (int nw = 1; nw <= 8; nw <<= 1) {
-    const long b = upd_lds_bytes(K, KYP, nw);
+    const long b = upd_lds_bytes(K, KYP, nw, nst);
     const int wgs = (int)((160L * 1024) / b);
     int waves = wgs * nw;
     if (waves > 8) waves = 8;
@@ -81,35 +93,60 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   constexpr int NTL = T16 * (T16 + 1) / 2;
   constexpr int GT4 = GW / 4;
   constexpr int RPQ = 64 / K;        // panel rows per load step
+  constexpr bool ZL = upd_zl(K);     // B operands in LDS
+  constexpr int PR = upd_rows(K);    // rows per wave panel
+  constexpr int NLQ = PR * K / 64;   // X load steps per panel
+  constexpr int NLY = PR * KYP / 64; // Y load steps per panel
+  constexpr int ZS = upd_zs(K);
+  constexpr int ZST = (K + KYP) * ZS;  // LDS doubles of one stage's Z / W
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int NW = blockDim.x >> 6;
   const int ky = a.ky;
   const int dense = a.dense;
   const int c16 = lane & 15, r4 = lane >> 4;
-  double* pan = lds + wave * 64 * S;
+  double* zl = lds;
+  double* pan = lds + (ZL ? NST * ZST : 0) + wave * PR * S;
 
-  // B operands in registers.
-  double zb[NST][KS][KC];
-  double wb[NST][YS > 0 ? YS : 1][KC];
+  // B operands: in registers (lane l holds Z[4 s + l / 16][16 J + l % 16]),
+  // or for ZL rows of Z then rows of W in LDS, read at the same positions.
+  double zb[ZL ? 1 : NST][ZL ? 1 : KS][ZL ? 1 : KC];
+  double wb[ZL ? 1 : NST][(ZL || YS == 0) ? 1 : YS][ZL ? 1 : KC];
+  if (ZL) {
+    for (int e = threadIdx.x; e < NST * (K + KYP) * K; e += blockDim.x) {
+      const int st = e / ((K + KYP) * K);
+      const int r = (e / K) % (K + KYP), c = e % K;
+      const double* __restrict__ Zg = st ? a.Z2 : a.Z1;
+      const double* __restrict__ Wg = st ? a.W2 : a.W1;
+      zl[st * ZST + r * ZS + c] = r < K ? Zg[r * K + c] : ((r - K) < ky ? Wg[(r - K) * K + c] : 0.0);
+    }
+    __syncthreads();
+  } else {
 #pragma unroll
-  for (int st = 0; st < NST; ++st) {
-    const double* __restrict__ Zg = st ? a.Z2 : a.Z1;
-    const double* __restrict__ Wg = st ? a.W2 : a.W1;
+    for (int st = 0; st < NST; ++st) {
+      const double* __restrict__ Zg = st ? a.Z2 : a.Z1;
+      const double* __restrict__ Wg = st ? a.W2 : a.W1;
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+      for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int J = 0; J < KC; ++J) {
-        const int col = 16 * J + c16;
-        zb[st][s][J] = col < K ? Zg[(4 * s + r4) * K + col] : 0.0;
-      }
+        for (int J = 0; J < KC; ++J) {
+          const int col = 16 * J + c16;
+          zb[ZL ? 0 : st][ZL ? 0 : s][ZL ? 0 : J] = col < K ? Zg[(4 * s + r4) * K + col] : 0.0;
+        }
 #pragma unroll
-    for (int s = 0; s < YS; ++s)
+      for (int s = 0; s < YS; ++s)
 #pragma unroll
-      for (int J = 0; J < KC; ++J) {
-        const int row = 4 * s + r4, col = 16 * J + c16;
-        wb[st][s][J] = (row < ky && col < K) ? Wg[row * K + col] : 0.0;
-      }
+        for (int J = 0; J < KC; ++J) {
+          const int row = 4 * s + r4, col = 16 * J + c16;
+          wb[ZL ? 0 : st][ZL ? 0 : s][ZL ? 0 : J] = (row < ky && col < K) ? Wg[row * K + col] : 0.0;
+        }
+    }
   }
+  auto bz = [&](int st, int s, int J) -> double {
+    return ZL ? zl[st * ZST + (4 * s + r4) * ZS + 16 * J + c16] : zb[ZL ? 0 : st][ZL ? 0 : s][ZL ? 0 : J];
+  };
+  auto bw = [&](int st, int s, int J) -> double {
+    return ZL ? zl[st * ZST + (K + 4 * s + r4) * ZS + 16 * J + c16] : wb[ZL ? 0 : st][ZL ? 0 : s][ZL ? 0 : J];
+  };
 
   d4_t gacc[NTL];
 #pragma unroll
@@ -124,9 +161,10 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   const bool cyin = cy < ky, cxin = cx < a.k;
   const int aoff = c16 * S + r4;  // A operand: row l % 16, column l / 16
   const int doff = r4 * S + c16;  // result layout: row l / 16, column l % 16
-  while (pnl < a.npanels) {
-    const int64_t row0 = pnl * 64;
-    const int nrows = (int)(a.m - row0 < 64 ? a.m - row0 : 64);
+  const int64_t npanels = (a.m + PR - 1) / PR;
+  while (pnl < npanels) {
+    const int64_t row0 = pnl * PR;
+    const int nrows = (int)(a.m - row0 < PR ? a.m - row0 : PR);
     wave_lds_sync();  // this wave's reads of its previous panel are done
     // 1. [Y | S] rows -> LDS (zero outside m, ky, k).  Loads are
     // unconditional (rows clamped to m - 1, columns to 0) so that they issue
@@ -134,7 +172,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
     if (KYP > 0) {
       const int cyc = cyin ? cy : 0;
 #pragma unroll
-      for (int q = 0; q < KYP; ++q) {
+      for (int q = 0; q < NLY; ++q) {
         const int r = ry0 + q * RY;
         const int64_t row = row0 + (r < nrows ? r : nrows - 1);
         const double v = a.Y[row * a.ldy + cyc];
@@ -143,16 +181,16 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
     }
     {
       const int cxc = cxin ? cx : 0;
-      if (nrows == 64) {
+      if (nrows == PR) {
         const ST* xp = (const ST*)a.X + (row0 + rx0) * a.ldx + cxc;
-        double v[K];
+        double v[NLQ];
 #pragma unroll
-        for (int q = 0; q < K; ++q) v[q] = (double)xp[(int64_t)q * RPQ * a.ldx];
+        for (int q = 0; q < NLQ; ++q) v[q] = (double)xp[(int64_t)q * RPQ * a.ldx];
 #pragma unroll
-        for (int q = 0; q < K; ++q) pan[(rx0 + q * RPQ) * S + KYP + cx] = cxin ? v[q] : 0.0;
+        for (int q = 0; q < NLQ; ++q) pan[(rx0 + q * RPQ) * S + KYP + cx] = cxin ? v[q] : 0.0;
       } else {
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
+        for (int q = 0; q < NLQ; ++q) {
           const int r = rx0 + q * RPQ;
           const int64_t row = row0 + (r < nrows ? r : nrows - 1);
           const double v = (double)((const ST*)a.X)[row * a.ldx + cxc];
@@ -162,27 +200,29 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
     }
     wave_lds_sync();
 #pragma unroll 1
-    for (int b = 0; b < 4; ++b) {  // 16-row blocks
+    for (int b = 0; b < PR / 16; ++b) {  // 16-row blocks
       double* pb = pan + 16 * b * S;
       d4_t t[KC];
 #pragma unroll
       for (int st = 0; st < NST; ++st) {
 #pragma unroll
         for (int J = 0; J < KC; ++J) t[J] = d4_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
+        // with the B operands in LDS, a partly unrolled k loop bounds the
+        // operand loads in flight (the registers are needed by the Gram)
+#pragma unroll(ZL ? 2 : KS)
         for (int s = 0; s < KS; ++s) {
           const double av = pb[aoff + KYP + 4 * s];
 #pragma unroll
           for (int J = 0; J < KC; ++J)
             if (dense || 4 * s <= 16 * J + 15)  // upper-triangular Z: skip zero blocks
-              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, zb[st][s][J], t[J], 0, 0, 0);
+              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bz(st, s, J), t[J], 0, 0, 0);
         }
 #pragma unroll
         for (int s = 0; s < YS; ++s) {
           const double av = pb[aoff + 4 * s];
 #pragma unroll
           for (int J = 0; J < KC; ++J)
-            t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, wb[st][s][J], t[J], 0, 0, 0);
+            t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw(st, s, J), t[J], 0, 0, 0);
         }
         if (st + 1 < NST) {
           // this stage's result is the next stage's A operand: back to LDS
@@ -231,7 +271,9 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   }
 
   if (!GR) return;
-  // Sum the waves' accumulators in wave order into wave 0, write the partial.
+  // Sum the waves' accumulators in wave order into wave 0, write the partial
+  // (the buffer overlays the panels and Z / W: the first barrier below
+  // orders it after every wave's last panel).
   double* red = lds;
   for (int w = 1; w < NW; ++w) {
     __syncthreads();
@@ -278,11 +320,11 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
 template <int K, int KYP, bool TWO, int GR, typename ST>
 hipError_t launch_upd_t(int grid, const UpdDev& one, const UpdDev* tab, const int* map,
                         hipStream_t st) {
-  const int NW = upd_waves(K, KYP);
+  const int NW = upd_waves(K, KYP, TWO ? 2 : 1);
   constexpr int KC = (K + 15) / 16;
   constexpr int T16 = (GR == 2 ? 1 : 0) + KC;
   const size_t red = GR ? sizeof(double) * T16 * (T16 + 1) / 2 * 4 * 64 : 0;
-  const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW);
+  const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW, TWO ? 2 : 1);
   const size_t shmem = lb > red ? lb : red;
   hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST>), dim3(grid), dim3(64 * NW), shmem, st,
                      one, tab, map);

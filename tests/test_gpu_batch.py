@@ -207,6 +207,13 @@ def test_autotune_roundtrip(tmp_path):
         assert info.status == 0
         met = oracle.metrics(host(Q), X, host(R))
         assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+        # tuned grids may exceed the default workgroup count: the partial
+        # buffers must still fit (widest DD Gram: [Y | X] with 16 + 64 columns)
+        Xw = synth.svd_matrix(50000, 64, 1e3, 78)
+        Yw = synth.locked_basis(50000, 16, 79)
+        ghi, glo = borth.gram(dev(Xw), A=dev(Yw), prec="dd", ctx=ctx)
+        ehi, elo = oracle.gram_q(np.hstack([Yw, Xw]))
+        assert rel_fro(host(ghi) + host(glo), ehi + elo) <= 1e-28
         hostb, devb = _blocks(MIXED[:3])
         outs, infos = borth.batch_orthonormalize(devb, gram="dd", ctx=ctx)
         for (Xh, Yh), (Qb, Rb, Cb), inf in zip(hostb, outs, infos):
