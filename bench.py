@@ -91,6 +91,13 @@ def run_c3(args, torch, borth, synth):
     Q = torch.empty_like(Xd)
     R = torch.empty((k, k), dtype=torch.float64, device="cuda")
     ctx = borth.default_context()
+    if args.copy_probe:
+        # plain device copy of known size (8 m k bytes read and written):
+        # calibrates the HBM byte counters of a profiling run
+        for _ in range(3):
+            Q.copy_(Xd)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {8 * m * k} bytes")
 
     def step():
         borth.orthonormalize(Xd, gram="dd", passes=2, out=Q, R=R, sync=False, ctx=ctx)
@@ -332,6 +339,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--blocks", type=int, default=256)
     ap.add_argument("--tune-ms", type=int, default=3000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain copy of X before timing (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the block orthonormalization path is "

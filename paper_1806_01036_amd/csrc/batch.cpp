@@ -96,7 +96,12 @@ int chol_class(int k) { return k <= 8 ? 0 : k <= 16 ? 1 : k <= 32 ? 2 : k <= 48 
 // share a workgroup gets in a single-block sweep, so per-workgroup
 // accumulation chains are as long as there), at least one, at most what the
 // block can use.
-constexpr int64_t kTuneRows = 1 << 21;  // rows of the autotuner's synthetic block
+// Rows per workgroup of the batched sweeps (measured defaults; an autotune
+// entry's "rows" field overrides them).  The update sweeps accumulate the
+// next pass's binary64 Gram, so their workgroups keep a single-block sweep's
+// share (~4k rows) and the accumulation chains stay as short.
+constexpr int64_t kBatchRowsUpd = 4096;
+constexpr int64_t kBatchRowsGram = 4096;
 std::vector<int> share_wgs(const std::vector<int64_t>& rows, const std::vector<int>& cap,
                            int64_t rows_per_wg) {
   std::vector<int> n(rows.size());
@@ -108,9 +113,9 @@ std::vector<int> share_wgs(const std::vector<int64_t>& rows, const std::vector<i
   }
   return n;
 }
-int64_t rows_per_wg(const borth::TuneGram& t) {
-  const int64_t r = t.nwg > 0 ? kTuneRows / t.nwg : 4096;
-  return r < 256 ? 256 : r;
+// Rows per workgroup from the autotune table's "rows" field (0: default).
+int64_t rows_per_wg(const borth::TuneGram& t, int64_t dflt) {
+  return t.rows > 0 ? t.rows : dflt;
 }
 
 struct BlkWs {
@@ -192,7 +197,8 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       kpmax = std::max(kpmax, W[b].kp);
       hasy |= B[b].ky > 0;
     }
-    const std::vector<int> n = share_wgs(rows, cap, rows_per_wg(lookup(c->tune_gram, gmode, kpmax, hasy)));
+    const std::vector<int> n =
+        share_wgs(rows, cap, rows_per_wg(lookup(c->tune_gram, gmode, kpmax, hasy), kBatchRowsGram));
     for (size_t i = 0; i < kv.second.size(); ++i) {
       const int b = kv.second[i];
       nwg_g[b] = n[i];
@@ -233,7 +239,8 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         cap.push_back((int)std::max<int64_t>(1, std::min<int64_t>((np + NW - 1) / NW, 1 << 20)));
         hasy |= B[b].ky > 0;
       }
-      const std::vector<int> n = share_wgs(rows, cap, rows_per_wg(lookup(c->tune_upd, gr ? 1 : 0, K, hasy)));
+      const std::vector<int> n =
+          share_wgs(rows, cap, rows_per_wg(lookup(c->tune_upd, gr ? 1 : 0, K, hasy), kBatchRowsUpd));
       for (size_t i = 0; i < kv.second.size(); ++i) {
         const int b = kv.second[i];
         nwg_u[p][b] = n[i];
@@ -610,6 +617,7 @@ struct TuneEntry {
   int mode;        // gram: 0 binary64, 1 DD; update: 0 plain, 1 with fused Gram
   int kp, hasy, nwg;
   double ms;
+  int rows = 0;    // rows per workgroup of batched sweeps (0: default)
 };
 
 double median(std::vector<float> v) {
@@ -757,9 +765,16 @@ borth_status borth_autotune_load(borth_ctx c, const char* cache_path) {
   while (std::fgets(line, sizeof(line), f)) {
     char op[16] = {0};
     TuneEntry t;
+    t.rows = 0;
     if (std::sscanf(line, " {\"op\": \"%15[a-z]\", \"mode\": %d, \"kp\": %d, \"hasy\": %d, \"nwg\": %d, \"ms\": %lf",
                     op, &t.mode, &t.kp, &t.hasy, &t.nwg, &t.ms) == 6) {
       t.op = op;
+      const char* rp = std::strstr(line, "\"rows\":");
+      if (rp && (std::sscanf(rp, "\"rows\": %d", &t.rows) != 1 || t.rows < 0)) {
+        std::fclose(f);
+        c->err = "malformed autotune entry";
+        return BORTH_ERR_ARG;
+      }
       if ((t.op != "gram" && t.op != "update") || t.mode < 0 || t.mode > 1 || t.nwg < 1 ||
           t.nwg > (1 << 20)) {
         std::fclose(f);
@@ -783,7 +798,7 @@ borth_status borth_autotune_load(borth_ctx c, const char* cache_path) {
   }
   for (const TuneEntry& t : got) {
     auto& tab = t.op == "gram" ? c->tune_gram : c->tune_upd;
-    tab[std::make_tuple(t.mode, t.kp, t.hasy)] = TuneGram{t.nwg, 0};
+    tab[std::make_tuple(t.mode, t.kp, t.hasy)] = TuneGram{t.nwg, t.rows};
   }
   ++c->tune_generation;
   ++c->ws_generation;

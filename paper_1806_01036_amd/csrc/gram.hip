@@ -60,22 +60,21 @@ __device__ __forceinline__ double fetch(const Src& s, const GramLayout& L, int64
   const int j = c - L.kyp;
   const bool ok = row < s.m && (isy ? c < L.ky : j < L.k);
   const int64_t rc = row < s.m ? row : s.m - 1;
-  const double* p = isy ? s.Y + rc * s.ldy + (c < L.ky ? c : 0)
-                        : (const double*)s.X + rc * s.ldx + (j < L.k ? j : 0);
+  const double BORTH_GLOBAL* p = isy ? gmem(s.Y) + rc * s.ldy + (c < L.ky ? c : 0)
+                                     : gmem((const double*)s.X) + rc * s.ldx + (j < L.k ? j : 0);
   const double v = *p;
   return ok ? v : 0.0;
 }
 
 // ---------------------------------------------------------------------------
 // VALU tile kernel (binary64 or DD).
-constexpr int kMaxQ = 12;  // reduction entries per thread (row phases > 1)
 
-template <bool DD, int NTB>
+template <bool DD, int NTB, bool BATCH>
 __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
                                                          const GramSeg* __restrict__ tab,
                                                          const int* __restrict__ wg2seg) {
   extern __shared__ double lds[];
-  const GramSeg g = tab ? tab[wg2seg[blockIdx.x]] : one;
+  const GramSeg g = BATCH ? tab[wg2seg[blockIdx.x]] : one;
   const Src& s = g.s;
   const GramLayout& L = g.L;
   const int P = g.P, S = g.S;
@@ -98,45 +97,48 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   }
 
   // Panel loads: thread t owns column lc = t % Wp and rows lr + q RS
-  // (RS = NT / Wp rows per step, P = NQ RS rows per panel), so one pointer and
+  // (RS = NT / Wp rows per step, P = nq RS rows per panel, nq <= 8 chosen
+  // on the host so that the S row phases split P evenly), so one pointer and
   // one stride per thread address all its loads.  The next panel's loads are
   // issued into registers before the current panel is processed, so HBM
   // latency overlaps the arithmetic.
   constexpr int NQ = 8;
+  const int nq = P / (NT / L.Wp);
   const int RS = NT / L.Wp;
   const int lc = tid % L.Wp, lr = tid / L.Wp;
   const bool isy = lc < L.kyp;
   const bool ldr = lr < RS && (isy ? lc < L.ky : lc - L.kyp < L.k);
   const int64_t ld = isy ? s.ldy : s.ldx;
   // column clamped to a valid one; loads below are unconditional
-  const double* bd = isy ? s.Y + (lc < L.ky ? lc : 0)
-                         : (const double*)s.X + (lc - L.kyp < L.k ? lc - L.kyp : 0);
+  const double BORTH_GLOBAL* bd = isy ? gmem(s.Y) + (lc < L.ky ? lc : 0)
+                                      : gmem((const double*)s.X) + (lc - L.kyp < L.k ? lc - L.kyp : 0);
+  // The raw loaded values stay in pf until the panel is stored to LDS (the
+  // zero for rows beyond m and padding columns is selected there), so the
+  // wait for the loads falls after the arithmetic of the current panel.
   double pf[NQ];
   auto fetch_panel = [&](int64_t pnl) {
     const int64_t row0 = pnl * P + lr;
     const int64_t mlast = s.m - 1;
-    double v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int64_t row = row0 + q * RS;
-      v[q] = bd[(row < s.m ? row : mlast) * ld];
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int64_t row = row0 + q * RS;
-      pf[q] = (ldr && pnl < npanels && row < s.m) ? v[q] : 0.0;
+      // load steps beyond nq re-read the first row (a cache hit) and are dropped
+      const int64_t row = row0 + (q < nq ? q : 0) * RS;
+      pf[q] = bd[(row < s.m ? row : mlast) * ld];
     }
   };
   fetch_panel(wg);
   for (int64_t pnl = wg; pnl < npanels; pnl += nwg) {
     __syncthreads();
     if (lr < RS) {
+      const int64_t row0 = pnl * P + lr;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) lds[(lr + q * RS) * stride + lc] = pf[q];
+      for (int q = 0; q < NQ; ++q)
+        if (q < nq) lds[(lr + q * RS) * stride + lc] = (ldr && row0 + q * RS < s.m) ? pf[q] : 0.0;
     }
     __syncthreads();
     fetch_panel(pnl + nwg);
     if (active) {
+#pragma unroll 2
       for (int r = phase; r < P; r += S) {
         const double* row = lds + r * stride;
         double a[4], b[4];
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   if (S == 1) {
     // one row phase: each thread's tile is its part of the partial
     if (!active) return;
-    double* out = g.part + (int64_t)wg * E * (DD ? 2 : 1);
+    double BORTH_GLOBAL* out = gmem(g.part) + (int64_t)wg * E * (DD ? 2 : 1);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       if (DD) {
@@ -175,70 +177,43 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
     }
     return;
   }
-  // Combine the row phases in phase order, then write this WG's partial.
+  // Combine the row phases in phase order in LDS (the threads of phase ph add
+  // their tiles to the running sum, one phase per barrier), then write this
+  // WG's partial.
   __syncthreads();
   double* red = lds;
-  double sh[kMaxQ], sl[kMaxQ];
-#pragma unroll
-  for (int q = 0; q < kMaxQ; ++q) {
-    sh[q] = 0.0;
-    sl[q] = 0.0;
-  }
   for (int ph = 0; ph < S; ++ph) {
     if (active && phase == ph) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
+        const int x = t * 16 + e;
         if (DD) {
-          const dd_t v = dot2_finish(acs[e], acc[e]);
-          red[2 * (t * 16 + e)] = v.hi;
-          red[2 * (t * 16 + e) + 1] = v.lo;
+          dd_t v = dot2_finish(acs[e], acc[e]);
+          if (ph > 0) v = dd_add(dd_make(red[2 * x], red[2 * x + 1]), v);
+          red[2 * x] = v.hi;
+          red[2 * x + 1] = v.lo;
         } else {
-          red[t * 16 + e] = acs[e];
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kMaxQ; ++q) {
-      const int e = tid + q * NT;
-      if (e < E) {
-        if (DD) {
-          const dd_t v = dd_add(dd_make(sh[q], sl[q]), dd_make(red[2 * e], red[2 * e + 1]));
-          sh[q] = v.hi;
-          sl[q] = v.lo;
-        } else {
-          sh[q] += red[e];
+          red[x] = ph > 0 ? red[x] + acs[e] : acs[e];
         }
       }
     }
     __syncthreads();
   }
-  double* out = g.part + (int64_t)wg * E * (DD ? 2 : 1);
-#pragma unroll
-  for (int q = 0; q < kMaxQ; ++q) {
-    const int e = tid + q * NT;
-    if (e < E) {
-      if (DD) {
-        out[2 * e] = sh[q];
-        out[2 * e + 1] = sl[q];
-      } else {
-        out[e] = sh[q];
-      }
-    }
-  }
+  double BORTH_GLOBAL* out = gmem(g.part) + (int64_t)wg * E * (DD ? 2 : 1);
+  for (int x = tid; x < E * (DD ? 2 : 1); x += NT) out[x] = red[x];
 }
 
 // ---------------------------------------------------------------------------
 // binary64 MFMA kernel: T = padded width / 16 column blocks.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-template <int T, int U>
+template <int T, int U, bool BATCH>
 __global__ void __launch_bounds__(256) gram_mfma_kernel(GramSeg one,
                                                         const GramSeg* __restrict__ tab,
                                                         const int* __restrict__ wg2seg) {
   constexpr int NTL = T * (T + 1) / 2;
   __shared__ double red[NTL * 4 * 64];
-  const GramSeg gs = tab ? tab[wg2seg[blockIdx.x]] : one;
+  const GramSeg gs = BATCH ? tab[wg2seg[blockIdx.x]] : one;
   const Src& s = gs.s;
   const GramLayout& L = gs.L;
   const int64_t ngroups = gs.nunits;
@@ -291,7 +266,7 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(GramSeg one,
     }
   }
   if (wave != 0) return;
-  double* out = gs.part + (int64_t)wg * L.E;
+  double BORTH_GLOBAL* out = gmem(gs.part) + (int64_t)wg * L.E;
   int idx = 0;
 #pragma unroll
   for (int I = 0; I < T; ++I)
@@ -319,10 +294,10 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
   __shared__ double sh[16][64], sl[16][64];
   const ReduceSeg rs = tab ? tab[blockIdx.y] : one;
   const GramLayout& L = rs.L;
-  const double* __restrict__ part = rs.part;
+  const double BORTH_GLOBAL* __restrict__ part = gmem(rs.part);
   const int nwg = rs.nwg;
-  double* __restrict__ Ghi = rs.Ghi;
-  double* __restrict__ Glo = rs.Glo;
+  double BORTH_GLOBAL* __restrict__ Ghi = gmem(rs.Ghi);
+  double BORTH_GLOBAL* __restrict__ Glo = rs.Glo ? gmem(rs.Glo) : nullptr;
   const int E = L.E;
   if ((int)blockIdx.x * 64 >= E) return;  // batched launch: a narrower block
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -401,9 +376,29 @@ int gram_kind(const GramLayout& L, int mode) {
 // tiles) up to 256 tiles (Wp <= 88); wider blocks take 1024 threads.
 int gram_tiles_threads(const GramLayout& L) { return L.ntiles <= 256 ? 256 : 1024; }
 
+// Rows per panel of the tile kernel: nq load steps of NT / Wp rows, nq in
+// 5..8 chosen so that the S = NT / ntiles row phases get equal shares (the
+// fewest idle rows per panel row).
+static int gram_tiles_rows(const GramLayout& L, int NT) {
+  const int RS = NT / L.Wp, S = NT / L.ntiles;
+  if (RS < 1 || S < 1) return 8 * (RS > 0 ? RS : 1);
+  int best = 8;
+  double best_w = 1e9;
+  for (int nq = 8; nq >= 5; --nq) {
+    const int P = nq * RS;
+    const int per = (P + S - 1) / S;
+    const double w = (double)(per * S - P) / P;
+    if (w < best_w - 1e-12) {
+      best_w = w;
+      best = nq;
+    }
+  }
+  return best * RS;
+}
+
 int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
   if (gram_kind(L, mode) == 0) return (s.m + 3) / 4;
-  const int P = 8 * (NT / L.Wp);
+  const int P = gram_tiles_rows(L, NT);
   return (s.m + P - 1) / P;
 }
 
@@ -427,8 +422,9 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
   *shmem = 0;
   if (gram_kind(L, mode) == 1) {
     g.S = NT / L.ntiles;
-    if (g.S < 1 || (g.S > 1 && L.E > kMaxQ * NT) || NT / L.Wp < 1) return false;
-    g.P = 8 * (NT / L.Wp);
+    if (g.S < 1 || NT / L.Wp < 1) return false;
+    g.P = gram_tiles_rows(L, NT);
+    g.nunits = (s.m + g.P - 1) / g.P;
     const int panel = g.P * (L.Wp + 2);
     const int redn = g.S > 1 ? L.E * (mode ? 2 : 1) : 0;  // one phase: no LDS reduction
     *shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
@@ -441,30 +437,41 @@ hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int g
                             const GramSeg& one, const GramSeg* tab, const int* wg2seg,
                             hipStream_t st) {
   if (grid < 1) return hipSuccess;
+  const bool b = tab != nullptr;
+#define BORTH_MFMA(T, U)                                                                       \
+  do {                                                                                         \
+    if (b)                                                                                     \
+      hipLaunchKernelGGL((gram_mfma_kernel<T, U, true>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); \
+    else                                                                                       \
+      hipLaunchKernelGGL((gram_mfma_kernel<T, U, false>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); \
+  } while (0)
+#define BORTH_TILES(D, N)                                                                      \
+  do {                                                                                         \
+    if (b)                                                                                     \
+      hipLaunchKernelGGL((gram_tiles_kernel<D, N, true>), dim3(grid), dim3(N), shmem, st, one, tab, wg2seg); \
+    else                                                                                       \
+      hipLaunchKernelGGL((gram_tiles_kernel<D, N, false>), dim3(grid), dim3(N), shmem, st, one, tab, wg2seg); \
+  } while (0)
   if (kind == 0) {
     switch (NT_or_T) {
-      case 1: hipLaunchKernelGGL((gram_mfma_kernel<1, 4>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
-      case 2: hipLaunchKernelGGL((gram_mfma_kernel<2, 4>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
-      case 3: hipLaunchKernelGGL((gram_mfma_kernel<3, 2>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
-      case 4: hipLaunchKernelGGL((gram_mfma_kernel<4, 2>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
-      case 5: hipLaunchKernelGGL((gram_mfma_kernel<5, 2>), dim3(grid), dim3(256), 0, st, one, tab, wg2seg); break;
+      case 1: BORTH_MFMA(1, 4); break;
+      case 2: BORTH_MFMA(2, 4); break;
+      case 3: BORTH_MFMA(3, 2); break;
+      case 4: BORTH_MFMA(4, 2); break;
+      case 5: BORTH_MFMA(5, 2); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
   if (NT_or_T == 256) {
-    if (mode == 1)
-      hipLaunchKernelGGL((gram_tiles_kernel<true, 256>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
-    else
-      hipLaunchKernelGGL((gram_tiles_kernel<false, 256>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+    if (mode == 1) BORTH_TILES(true, 256); else BORTH_TILES(false, 256);
   } else if (NT_or_T == 1024) {
-    if (mode == 1)
-      hipLaunchKernelGGL((gram_tiles_kernel<true, 1024>), dim3(grid), dim3(1024), shmem, st, one, tab, wg2seg);
-    else
-      hipLaunchKernelGGL((gram_tiles_kernel<false, 1024>), dim3(grid), dim3(1024), shmem, st, one, tab, wg2seg);
+    if (mode == 1) BORTH_TILES(true, 1024); else BORTH_TILES(false, 1024);
   } else {
     return hipErrorInvalidValue;
   }
+#undef BORTH_MFMA
+#undef BORTH_TILES
   return hipGetLastError();
 }
 

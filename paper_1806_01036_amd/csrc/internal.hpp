@@ -5,6 +5,16 @@
 
 namespace borth {
 
+// Global-memory view of a pointer.  Kernel segments are read from tables in
+// device memory, so the compiler cannot infer the address space of the
+// pointers they hold; without this cast their loads become flat accesses,
+// which share the LDS wait counter and serialize prefetches with LDS traffic.
+#define BORTH_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T BORTH_GLOBAL* gmem(T* p) {
+  return (T BORTH_GLOBAL*)p;
+}
+
 // Layout of a per-workgroup partial Gram: the upper triangle of the padded
 // Wp x Wp matrix (Wp = kyp + kp, a multiple of 4) split into 4x4 tiles
 // (ti <= tj) enumerated row by row; entry e = tile * 16 + a * 4 + b holds

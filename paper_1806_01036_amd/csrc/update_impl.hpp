@@ -75,11 +75,11 @@ inline int upd_waves(int K, int KYP, int nst = 1) {
 }
 
 // GR: 0 = no Gram, 1 = Gram of T, 2 = Gram of [Y | T] (KYP = 16).
-template <int K, int KYP, bool TWO, int GR, typename ST>
+template <int K, int KYP, bool TWO, int GR, typename ST, bool BATCH>
 __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* __restrict__ tab,
                                                      const int* __restrict__ wg2seg) {
   extern __shared__ double lds[];
-  const UpdDev a = tab ? tab[wg2seg[blockIdx.x]] : one;
+  const UpdDev a = BATCH ? tab[wg2seg[blockIdx.x]] : one;
   const int wg = (int)blockIdx.x - a.wg0;
   constexpr int S = KYP + K + 2;     // LDS row stride (doubles)
   constexpr int KC = (K + 15) / 16;  // 16-column blocks of T
@@ -115,16 +115,16 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
     for (int e = threadIdx.x; e < NST * (K + KYP) * K; e += blockDim.x) {
       const int st = e / ((K + KYP) * K);
       const int r = (e / K) % (K + KYP), c = e % K;
-      const double* __restrict__ Zg = st ? a.Z2 : a.Z1;
-      const double* __restrict__ Wg = st ? a.W2 : a.W1;
+      const double BORTH_GLOBAL* __restrict__ Zg = gmem(st ? a.Z2 : a.Z1);
+      const double BORTH_GLOBAL* __restrict__ Wg = gmem(st ? a.W2 : a.W1);
       zl[st * ZST + r * ZS + c] = r < K ? Zg[r * K + c] : ((r - K) < ky ? Wg[(r - K) * K + c] : 0.0);
     }
     __syncthreads();
   } else {
 #pragma unroll
     for (int st = 0; st < NST; ++st) {
-      const double* __restrict__ Zg = st ? a.Z2 : a.Z1;
-      const double* __restrict__ Wg = st ? a.W2 : a.W1;
+      const double BORTH_GLOBAL* __restrict__ Zg = gmem(st ? a.Z2 : a.Z1);
+      const double BORTH_GLOBAL* __restrict__ Wg = gmem(st ? a.W2 : a.W1);
 #pragma unroll
       for (int s = 0; s < KS; ++s)
 #pragma unroll
@@ -175,14 +175,14 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
       for (int q = 0; q < NLY; ++q) {
         const int r = ry0 + q * RY;
         const int64_t row = row0 + (r < nrows ? r : nrows - 1);
-        const double v = a.Y[row * a.ldy + cyc];
+        const double v = gmem(a.Y)[row * a.ldy + cyc];
         pan[r * S + cy] = (r < nrows && cyin) ? v : 0.0;
       }
     }
     {
       const int cxc = cxin ? cx : 0;
       if (nrows == PR) {
-        const ST* xp = (const ST*)a.X + (row0 + rx0) * a.ldx + cxc;
+        const ST BORTH_GLOBAL* xp = gmem((const ST*)a.X) + (row0 + rx0) * a.ldx + cxc;
         double v[NLQ];
 #pragma unroll
         for (int q = 0; q < NLQ; ++q) v[q] = (double)xp[(int64_t)q * RPQ * a.ldx];
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
         for (int q = 0; q < NLQ; ++q) {
           const int r = rx0 + q * RPQ;
           const int64_t row = row0 + (r < nrows ? r : nrows - 1);
-          const double v = (double)((const ST*)a.X)[row * a.ldx + cxc];
+          const double v = (double)gmem((const ST*)a.X)[row * a.ldx + cxc];
           pan[r * S + KYP + cx] = (r < nrows && cxin) ? v : 0.0;
         }
       }
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
         for (int v = 0; v < 4; ++v) {
           const int r = 16 * b + r4 + 4 * v;
           if (r < nrows) {
-            double* qrow = a.Q + (row0 + r) * a.ldq;
+            double BORTH_GLOBAL* qrow = gmem(a.Q) + (row0 + r) * a.ldq;
 #pragma unroll
             for (int J = 0; J < KC; ++J)
               if (16 * J + c16 < a.k) qrow[16 * J + c16] = t[J][v];
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
     if (YB && B == 0) return x;
     return x < KV ? YB * KYP + 16 * (B - YB) + x : -1;
   };
-  double* out = a.part + (int64_t)wg * a.gE;
+  double BORTH_GLOBAL* out = gmem(a.part) + (int64_t)wg * a.gE;
   int idx = 0;
 #pragma unroll
   for (int I = 0; I < T16; ++I)
@@ -326,8 +326,12 @@ hipError_t launch_upd_t(int grid, const UpdDev& one, const UpdDev* tab, const in
   const size_t red = GR ? sizeof(double) * T16 * (T16 + 1) / 2 * 4 * 64 : 0;
   const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW, TWO ? 2 : 1);
   const size_t shmem = lb > red ? lb : red;
-  hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST>), dim3(grid), dim3(64 * NW), shmem, st,
-                     one, tab, map);
+  if (tab)
+    hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, true>), dim3(grid), dim3(64 * NW), shmem,
+                       st, one, tab, map);
+  else
+    hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, false>), dim3(grid), dim3(64 * NW), shmem,
+                       st, one, tab, map);
   return hipGetLastError();
 }
 

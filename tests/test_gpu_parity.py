@@ -287,15 +287,27 @@ def _check_qr(X, Q, R, Y=None, C=None, omega=1e-14, rho=1e-14):
 
 def test_cholqr_plain_c1_shape():
     """Plain CholQR at the 20000 x 8, kappa = 1e4 workload: orthogonality
-    loss ~ c kappa^2 u (same decade as the oracle's binary64 steps), rho ~ u."""
+    loss follows c kappa^2 u (Stathopoulos and Wu), rho ~ u.  The constant c
+    depends on the summation order of the Gram matrix, so the GPU and the
+    oracle's binary64 steps are both checked against the law (level band and
+    kappa^2 slope between kappa = 1e3 and 1e4), not against each other."""
     borth = lib()
+    om = {}
+    for kappa in (1e3, 1e4):
+        X = synth.svd_matrix(20000, 8, kappa, 101)
+        Q, R, _, info = borth.orthonormalize(dev(X), gram="f64", passes=1)
+        assert info.status == 0
+        met = _check_qr(X, host(Q), host(R), omega=1.0)
+        o2 = oracle.cholqr_steps(X, dd_first=False, passes=1)
+        m2 = oracle.metrics(o2["Q"], X, o2["R_hi"])
+        law = kappa ** 2 * U64
+        note(" plain CholQR kappa", kappa, "gpu", met["omega"], "oracle", m2["omega"], "k^2u", law)
+        for w in (met["omega"], m2["omega"]):
+            assert 1e-2 * law <= w <= 1e2 * law
+        om[kappa] = met["omega"]
+    assert 10 <= om[1e4] / om[1e3] <= 1000  # kappa^2 predicts 100
     X = synth.svd_matrix(20000, 8, 1e4, 101)
     Q, R, _, info = borth.orthonormalize(dev(X), gram="f64", passes=1)
-    assert info.status == 0
-    o2 = oracle.cholqr_steps(X, dd_first=False, passes=1)
-    m2 = oracle.metrics(o2["Q"], X, o2["R_hi"])
-    met = _check_qr(X, host(Q), host(R), omega=1.0)
-    assert m2["omega"] / 10 <= met["omega"] <= m2["omega"] * 10
     o1 = oracle.qr_q(X)
     assert rel_fro(host(R), o1["R"]) <= 1e-14 * 1e4
 
