@@ -34,6 +34,23 @@ sys.path.insert(0, str(ROOT))
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP64 lane-ops per second (39.3 T)
 
+# HBM bytes per dispatch of the dominant kernel of the default workload, from
+# two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; calibrated on a plain
+# device copy of known size, see profiles/dd_cholqr2_4Mx32_hbm_counters.md).
+# Valid only for the kernel sources they were taken on: reported as null once
+# those sources change.
+DD_GRAM_TRAFFIC = {"bytes": 1.0337e9,
+                   "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
+                   "sha256": "b8a0b90527cbea22b15bb964c30c18d75ca2360171870fb12fc9b0a1a601e1b5"}
+
+
+def measured_traffic(rec):
+    import hashlib
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update((ROOT / "paper_1806_01036_amd" / "csrc" / f).read_bytes())
+    return rec["bytes"] if h.hexdigest() == rec["sha256"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -162,7 +179,9 @@ def run_c3(args, torch, borth, synth):
         "fp64_cholqr2_ms_per_step": round(tf2 * 1e3, 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_TOPS,
                      "unit": "Tops/s (FP64 VALU lane-ops)", "frac": round(achieved / FP64_VALU_TOPS, 4),
-                     "traffic": None, "kernel": "gram_tiles_kernel<DD>",
+                     "traffic": measured_traffic(DD_GRAM_TRAFFIC),
+                     "traffic_unit": "bytes per launch (algorithmic 8 m k = %d)" % (8 * m * k),
+                     "kernel": "gram_tiles_kernel<DD>",
                      "kernel_ms": round(gram_ms, 4)},
     }
     if not args.no_cpu:
