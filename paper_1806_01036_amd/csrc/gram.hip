@@ -19,6 +19,10 @@
 //  reduce_kernel      sums the partials in workgroup order (DD additions in DD
 //                     mode) -- no floating-point atomics, so every result is
 //                     bitwise reproducible.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "dd.hpp"
 #include "internal.hpp"
 
@@ -475,11 +479,50 @@ hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int g
   return hipGetLastError();
 }
 
+// Workgroups of the tile kernel resident on the device at once, from the
+// occupancy of the kernel instance (cached per device and shape).
+int gram_tiles_resident(int mode, int NT, size_t shmem) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, size_t>, int> cache;
+  const auto key = std::make_tuple(dev, mode, NT, shmem);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e;
+  if (NT == 256)
+    e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 256, false>, 256, shmem)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 256, false>, 256, shmem);
+  else
+    e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 1024, false>, 1024, shmem)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 1024, false>, 1024, shmem);
+  if (e != hipSuccess || per < 1) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = per * cus;
+  return per * cus;
+}
+
 hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* partials,
                        int64_t cap, int* nwg_out, const TuneGram& tune, hipStream_t st) {
   const int kind = gram_kind(L, mode);
   const int NT = kind == 0 ? 256 : gram_tiles_threads(L);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
+  if (tune.nwg <= 0 && kind == 1) {
+    // ALU-bound tile kernel: two full rounds of resident workgroups (measured
+    // best on the 4M x 32 DD Gram: 1536 against 1024 or 2048)
+    GramSeg g0;
+    size_t sh0 = 0;
+    if (gram_seg(s, L, mode, NT, partials, 0, 1, &g0, &sh0)) {
+      const int r = gram_tiles_resident(mode, NT, sh0);
+      if (r > 0) nwg = 2 * r;
+    }
+    const int64_t fit = cap / ((int64_t)L.E * (mode ? 2 : 1));  // partial slots available
+    if (nwg > fit) nwg = (int)(fit > 0 ? fit : 1);
+  }
   const int mx = gram_max_wg(s, L, mode, NT);
   if (nwg > mx) nwg = mx;
   if ((int64_t)nwg * L.E * (mode ? 2 : 1) > cap) return hipErrorInvalidValue;
