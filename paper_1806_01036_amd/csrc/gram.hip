@@ -120,14 +120,22 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   // zero for rows beyond m and padding columns is selected there), so the
   // wait for the loads falls after the arithmetic of the current panel.
   double pf[NQ];
+  const int64_t step = (int64_t)RS * ld;
   auto fetch_panel = [&](int64_t pnl) {
     const int64_t row0 = pnl * P + lr;
-    const int64_t mlast = s.m - 1;
+    if ((pnl + 1) * P <= s.m) {
+      // full panel (uniform branch): rows in range, pointer steps of RS rows
+      const double BORTH_GLOBAL* p = bd + row0 * ld;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      // load steps beyond nq re-read the first row (a cache hit) and are dropped
-      const int64_t row = row0 + (q < nq ? q : 0) * RS;
-      pf[q] = bd[(row < s.m ? row : mlast) * ld];
+      for (int q = 0; q < NQ; ++q) pf[q] = p[(q < nq ? q : 0) * step];
+    } else {
+      const int64_t mlast = s.m - 1;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        // load steps beyond nq re-read the first row (a cache hit) and are dropped
+        const int64_t row = row0 + (q < nq ? q : 0) * RS;
+        pf[q] = bd[(row < s.m ? row : mlast) * ld];
+      }
     }
   };
   fetch_panel(wg);
