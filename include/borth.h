@@ -12,11 +12,11 @@
  *     Cholesky (CholQR):  M = R^T R,  Z = R^{-1};
  *     SVQB:               M = U L U^T, Z = U L^{-1/2} U^T  (symmetric form);
  *     Q = Xt Z.
- * "Iterating this process, alternating between the two phases" (Sec. 4.2)
- * is offered as `passes` repetitions (passes = 2 is CholQR2).  The Gram
- * matrix of the first pass can be accumulated in binary64, in double-double
- * (DD, hi + lo; Sec. 4.2 "extended precision ... including the computation
- * and decomposition of the Gram matrix"), or as BF16 hi/lo split products on
+ * Repeating the two phases (Sec. 4.2) is offered as `passes` repetitions
+ * (passes = 2 is CholQR2).  The Gram matrix of the first pass can be
+ * accumulated in binary64, in double-double (DD, hi + lo; Sec. 4.2 carries
+ * the Gram matrix and its factorization in extended precision), or as BF16
+ * hi/lo split products on
  * the matrix cores (FP32 accumulation) followed by a shifted factorization;
  * later passes are binary64.  On success
  *     X = Y C + Q R,   Q^T Q = I,   Y^T Q = 0   (to working accuracy).
@@ -125,8 +125,8 @@ borth_status borth_gram(borth_ctx ctx, int64_t m, int ka, const double* A, int64
                         int kb, borth_dtype dt_b, const void* B, int64_t ldb, int prec,
                         double* G_hi, double* G_lo);
 
-/* Small factorization (Sec. 4.2 phase II, "determining a suitable matrix Z
- * such that Z^T M Z = I"): from the Gram matrix G of [Y | X] (W x W,
+/* Small factorization (Sec. 4.2 phase II: a k x k transform Z with
+ * Z^T M Z = I): from the Gram matrix G of [Y | X] (W x W,
  * W = ky + k, hi and optional lo words), form
  *     C = G_YX,  M = G_XX - 2 C^T C + C^T G_YY C  (= Xt^T Xt exactly),
  * add shift * trace(M) to the diagonal if shift > 0, and factor M in DD

@@ -20,9 +20,9 @@
  *        the stored input for every condition number below ~1e17.
  *
  *  O2 -- the paper's algorithm taken step by step in the working precision:
- *        binary64 (plain CholQR / CholQR2) or double-double (DD) "throughout the
- *        orthogonalization, including the orthogonalization against W and the
- *        computation and decomposition of the Gram matrix" (Sec. 4.2).  DD uses
+ *        binary64 (plain CholQR / CholQR2) or double-double (DD) in the first
+ *        pass -- the projection against W, the Gram matrix and its
+ *        factorization all in DD, as Sec. 4.2 describes its DD variant.  DD uses
  *        Dekker's splitting for the exact product (no FMA, so it does not share
  *        the GPU's FMA route) and Knuth's TwoSum; DD division and square root
  *        are Newton-Raphson iterations seeded by binary64, as the paper states.

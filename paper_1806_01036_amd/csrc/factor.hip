@@ -1,8 +1,9 @@
 // Small k x k step of phase II (Sec. 4.2): from the Gram matrix of [Y | X]
 // form the projected Gram matrix M = Xt^T Xt, factor it and build the
-// transform Z with Z^T M Z = I.  "Operations on small n_b x n_b matrices are
-// cost negligible, even in extended precision" (Sec. 4.2) -- on the GPU they
-// are latency, so they run in one workgroup without leaving the device.
+// transform Z with Z^T M Z = I.  Sec. 4.2 counts the work on these small
+// matrices as negligible next to the sweeps, also in extended precision; on
+// the GPU their cost is latency, so they run in one workgroup per block
+// without leaving the device.
 //
 // chol_kernel (Cholesky, DD or binary64 arithmetic): one workgroup of
 //   T x T threads (T = 8, 16, 32, or 24 / 32 with 2 x 2 elements a thread);

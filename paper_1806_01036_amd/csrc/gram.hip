@@ -1,6 +1,6 @@
 // Gram sweeps (TSMTTSM): G = V^T V for the tall-skinny V = [Y | X].
 //
-// The Gram matrix is "the bulk of computation" of the orthogonalization
+// The Gram matrix is where Sec. 4.2 places most of the orthogonalization's work
 // (Sec. 4.2); for a few columns it is bound by the HBM stream.  Three
 // kernels, all writing per-workgroup partials in one shared layout (4x4
 // tiles of the upper triangle, see GramLayout) that a fixed-order reduction

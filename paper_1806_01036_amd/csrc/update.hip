@@ -1,4 +1,5 @@
-// Basis update sweep (TSMM), "Y = Xt Z" of Sec. 4.2 with the phase-I
+// Basis update sweep (TSMM), the product of the projected block with Z
+// (Sec. 4.2), with the phase-I
 // projection folded in: T = (S - Y C) Z = S Z + Y W per row (W = -C Z),
 // S = X (first pass) or Q_1 (later passes); optionally a second stage and
 // the next pass's Gram matrix fused in (kernels in update_impl.hpp, one

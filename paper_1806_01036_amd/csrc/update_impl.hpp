@@ -1,19 +1,24 @@
-// Basis update sweep (TSMM), "Y = Xt Z" of Sec. 4.2 with the phase-I
+// Basis update sweep (TSMM), the product of the projected block with Z
+// (Sec. 4.2), with the phase-I
 // projection folded in:  T = (S - Y C) Z = S Z + Y W  (W = -C Z) per row,
 // S = X (first pass) or Q_1 (later passes).  Optionally a second stage
 // T = T Z_2 + Y W_2 follows (CholQR2 with Q_1 recomputed instead of stored),
 // and the Gram matrix of [Y | T] (or of T) needed by the next pass is
-// accumulated from the values just computed ("kernel fusion ... to further
-// reduce memory accesses", Sec. 4.2).
+// accumulated from the values just computed (the fusion of operations that
+// Sec. 4.2 uses to save memory traffic).
 //
 // The product is a dense contraction with a tiny right factor, so it runs
 // on the matrix cores (v_mfma_f64_16x16x4):
-//  * each wave streams its own 64-row panels of [Y | S] (no workgroup
-//    barrier in the loop): coalesced global loads -> LDS (row stride
-//    KYP + K + 2 doubles, compile-time, so all offsets are immediates);
-//  * Z and W live in registers as the B operands for the whole kernel
-//    (lane l holds Z[4 s + l / 16][16 J + l % 16]); the A operands
-//    (lane l: S[row l % 16][col 4 s + l / 16]) are read from LDS;
+//  * each wave streams its own panels of [Y | S] (64 rows; 16 for K = 64),
+//    with no workgroup barrier in the loop: coalesced global loads -> LDS
+//    (row stride KYP + K + 2 doubles, compile-time, so all offsets are
+//    immediates);
+//  * Z and W are the B operands (lane l holds Z[4 s + l / 16][16 J + l % 16]):
+//    in registers for the whole kernel for K <= 32, in LDS shared by the
+//    workgroup for K = 64; the A operands (lane l: S[row l % 16][col 4 s +
+//    l / 16]) are read from LDS;
+//  * a workgroup streams the rows of one block; a batched launch covers many
+//    blocks, each owning a range of the grid's workgroups (UpdDev table);
 //  * the result tile (lane l, register v: T[row l / 16 + 4 v][col 16 J +
 //    l % 16]) is stored straight to global memory, and the same registers
 //    are the operands of the fused Gram MFMA (4-row groups v), so T never
