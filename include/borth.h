@@ -159,6 +159,36 @@ borth_status borth_orthonormalize(borth_ctx ctx, int64_t m, int k, borth_dtype d
                                   int ky, double* Q, int64_t ldq, double* R, double* C,
                                   const borth_opts* opts, borth_info* info);
 
+/* Outcome of the iterated scheme (borth_orthonormalize_iter). */
+typedef struct {
+  int converged;  /* 1 if the stop test held after passes_run passes */
+  int passes_run;
+  double c_norm;  /* ||C_j||_F of the last pass (its projection coefficients) */
+  double r_dev;   /* ||R_j - I||_F of the last pass */
+} borth_iter_info;
+
+/* Iterated two-phase scheme (Sec. 4.2: phase I and phase II alternated until
+ * the block no longer changes): pass j projects the current block S_j (X,
+ * then Q) against Y and orthonormalizes it, S_{j+1} = (S_j - Y C_j) Z_j, and
+ * the iteration stops once a pass changes nothing measurable,
+ *     ||C_j||_F <= eps  and  ||R_j - I||_F <= eps,
+ * or after max_iter passes.  Every pass's Gram matrix is taken in
+ * opts->gram precision (BORTH_GRAM_F64 or BORTH_GRAM_DD; DD also for the
+ * factorization), opts->fact selects Cholesky or SVQB (binary64 only);
+ * opts->passes, sched and PROJECT_ONCE are ignored.  Each pass is a Gram
+ * sweep over [Y | S_j] and an update sweep writing Q (Q may alias X as in
+ * borth_orthonormalize); ky <= 64.  The call synchronizes after every pass
+ * to evaluate the stop test.  On return X = Y C + Q R with R, C the products
+ * of all passes (device, may be NULL); *it (host, required) reports the
+ * passes run and the last pass's norms; info (host, may be NULL) the
+ * numerical status.  Returns BORTH_OK whether or not the test was met
+ * (it->converged tells), or the breakdown status. */
+borth_status borth_orthonormalize_iter(borth_ctx ctx, int64_t m, int k, const double* X,
+                                       int64_t ldx, const double* Y, int64_t ldy, int ky,
+                                       double* Q, int64_t ldq, double* R, double* C,
+                                       const borth_opts* opts, double eps, int max_iter,
+                                       borth_iter_info* it, borth_info* info);
+
 /* One block of a batch (all pointers device, as in borth_orthonormalize;
  * X binary64). */
 typedef struct {

@@ -19,7 +19,8 @@ from . import _lib
 
 __all__ = [
     "BorthError", "Breakdown", "Context", "Info", "default_context", "gram", "factor",
-    "update", "orthonormalize", "batch_orthonormalize", "GRAM", "FACT", "SCHED",
+    "update", "orthonormalize", "orthonormalize_iter", "batch_orthonormalize", "GRAM", "FACT",
+    "SCHED",
 ]
 
 GRAM = {"f64": 0, "dd": 1, "split": 2}
@@ -226,6 +227,42 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)
     return Q, R, (C if ky else None), info
+
+
+@dataclass
+class IterInfo:
+    converged: bool
+    passes_run: int
+    c_norm: float
+    r_dev: float
+
+
+def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5, out=None,
+                        R=None, C=None, check=True, ctx=None):
+    """Iterated two-phase scheme: passes of projection against Y and
+    orthonormalization until ||C_j||_F <= eps and ||R_j - I||_F <= eps (or
+    max_iter passes).  Returns (Q, R, C, IterInfo, Info)."""
+    torch = _torch()
+    ctx = ctx or default_context(X.device.index)
+    m, k = X.shape
+    ky = 0 if Y is None else Y.shape[1]
+    dev = X.device
+    Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
+    R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
+    if ky and C is None:
+        C = torch.empty((ky, k), dtype=torch.float64, device=dev)
+    o = _opts(gram, fact, 1, "materialize", 0.0, 0)
+    it = _lib.borth_iter_info()
+    inf = _lib.borth_info()
+    st = ctx.lib.borth_orthonormalize_iter(
+        ctx.h, m, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y) if ky else 0, ky, _ptr(Q), _ld(Q), _ptr(R),
+        _ptr(C) if ky else None, ctypes.byref(o), float(eps), int(max_iter), ctypes.byref(it),
+        ctypes.byref(inf))
+    if check or st not in (BREAKDOWN, NONFINITE):
+        ctx.check(st)
+    return (Q, R, (C if ky else None),
+            IterInfo(bool(it.converged), it.passes_run, it.c_norm, it.r_dev),
+            Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run))
 
 
 def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0,

@@ -35,6 +35,10 @@ class borth_block(ctypes.Structure):
                 ("C", _vp)]
 
 
+class borth_iter_info(ctypes.Structure):
+    _fields_ = [("converged", _int), ("passes_run", _int), ("c_norm", _dbl), ("r_dev", _dbl)]
+
+
 EXPORTS = {
     "borth_default_opts": ([ctypes.POINTER(borth_opts)], None),
     "borth_create": ([ctypes.POINTER(_vp), _int, _vp], _int),
@@ -51,6 +55,10 @@ EXPORTS = {
     "borth_orthonormalize": ([_vp, _i64, _int, _int, _vp, _i64, _vp, _i64, _int, _vp, _i64,
                               _vp, _vp, ctypes.POINTER(borth_opts),
                               ctypes.POINTER(borth_info)], _int),
+    "borth_orthonormalize_iter": ([_vp, _i64, _int, _vp, _i64, _vp, _i64, _int, _vp, _i64,
+                                   _vp, _vp, ctypes.POINTER(borth_opts), _dbl, _int,
+                                   ctypes.POINTER(borth_iter_info), ctypes.POINTER(borth_info)],
+                                  _int),
     "borth_batch_orthonormalize": ([_vp, _int, ctypes.POINTER(borth_block),
                                     ctypes.POINTER(borth_opts), ctypes.POINTER(borth_info)],
                                    _int),

@@ -119,7 +119,7 @@ int64_t rows_per_wg(const borth::TuneGram& t, int64_t dflt) {
 }
 
 struct BlkWs {
-  int64_t ghi, glo, zp[3], cp[3], wp[3], rtot, ctot;
+  int64_t ghi, glo, zp[3], cp[3], rtot, ctot;
   int64_t part;        // offset of this block's partial region (doubles)
   int64_t part_need;   // its size
   int kp;
@@ -150,7 +150,6 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
     for (int p = 0; p < 3; ++p) {
       x.zp[p] = p < passes ? take((int64_t)kp * kp) : -1;
       x.cp[p] = p < passes ? take((int64_t)ky1 * kp) : -1;
-      x.wp[p] = p < passes ? take((int64_t)ky1 * kp) : -1;
     }
     x.rtot = take(2 * (int64_t)k * k);
     x.ctot = take(2 * (int64_t)ky1 * k);
@@ -345,7 +344,6 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         f.pass = p;
         f.Zp = ws + W[b].zp[p];
         f.Cp = ws + W[b].cp[p];
-        f.Wp = ws + W[b].wp[p];
         f.Rtot = ws + W[b].rtot;
         f.Ctot = ws + W[b].ctot;
         f.status = P->status + 4 * b;
@@ -396,7 +394,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         d.ldq = B[b].ldq;
         d.part = uc.gr ? part + W[b].part : nullptr;
         d.npanels = (B[b].m + update_rows(uc.K) - 1) / update_rows(uc.K);
-        d.W1 = ws + W[b].wp[p - 1];
+        d.C1 = ws + W[b].cp[p - 1];
         d.Z1 = ws + W[b].zp[p - 1];
         d.wg0 = (int)map.size();
         d.nwg = nwg_u[p][b];
@@ -687,7 +685,7 @@ borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) 
                   UpdateArgs u;
                   std::memset(&u, 0, sizeof(u));
                   u.src = Src{hasy ? Y : nullptr, 16, X, 64, 0, m};
-                  u.W1 = zw;
+                  u.C1 = zw;
                   u.Z1 = zw;
                   u.gram_with_y = mode && hasy;
                   u.Q = Q;

@@ -78,7 +78,7 @@ borth_status ensure_status(borth_ctx c, int n) {
 
 // Small-matrix workspace layout (doubles), for W = ky + k <= 128, kp <= 64.
 struct WsLayout {
-  int64_t g_hi, g_lo, zp[3], cp[3], wp[3], rtot, ctot, zu, cu, total;
+  int64_t g_hi, g_lo, zp[3], cp[3], rtot, ctot, zu, cu, total;
 };
 WsLayout ws_layout() {
   WsLayout w;
@@ -87,7 +87,6 @@ WsLayout ws_layout() {
   w.g_lo = o; o += 128 * 128;
   for (int i = 0; i < 3; ++i) { w.zp[i] = o; o += 64 * 64; }
   for (int i = 0; i < 3; ++i) { w.cp[i] = o; o += 64 * 64; }
-  for (int i = 0; i < 3; ++i) { w.wp[i] = o; o += 64 * 64; }
   w.rtot = o; o += 2 * 64 * 64;
   w.ctot = o; o += 2 * 64 * 64;
   w.zu = o; o += 64 * 64;
@@ -177,7 +176,6 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     f.pass = pass;
     f.Zp = ws + W.zp[pass];
     f.Cp = ws + W.cp[pass];
-    f.Wp = ws + W.wp[pass];
     f.Rtot = ws + W.rtot;
     f.Ctot = ws + W.ctot;
     f.status = c->status;
@@ -201,7 +199,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     UpdateArgs u;
     memset(&u, 0, sizeof(u));
     u.src = s1;
-    u.W1 = ws + W.wp[0];
+    u.C1 = ws + W.cp[0];
     u.Z1 = ws + W.zp[0];
     u.dense = a.o.fact == BORTH_SVQB;
     u.Q = a.Q;
@@ -217,7 +215,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     UpdateArgs u;
     memset(&u, 0, sizeof(u));
     u.src = s1;
-    u.W1 = ws + W.wp[0];
+    u.C1 = ws + W.cp[0];
     u.Z1 = ws + W.zp[0];
     u.dense = a.o.fact == BORTH_SVQB;
     u.gram_with_y = later_proj ? 1 : 0;
@@ -233,9 +231,9 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     UpdateArgs u3;
     memset(&u3, 0, sizeof(u3));
     u3.src = s1;
-    u3.W1 = ws + W.wp[0];
+    u3.C1 = ws + W.cp[0];
     u3.Z1 = ws + W.zp[0];
-    u3.W2 = ws + W.wp[1];
+    u3.C2 = ws + W.cp[1];
     u3.Z2 = ws + W.zp[1];
     u3.two_stage = 1;
     u3.dense = a.o.fact == BORTH_SVQB;
@@ -243,7 +241,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     u3.ldq = a.ldq;
     if (!later_proj) {
       // pass 2 did not project: its C is zero
-      HIPCHK(c, launch_fill_int((int*)(ws + W.wp[1]), 2 * 64 * 64, 0, st), "zero W2");
+      HIPCHK(c, launch_fill_int((int*)(ws + W.cp[1]), 2 * 64 * 64, 0, st), "zero C2");
     }
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u3, Lu, lookup(c->tune_upd, 2, kp, hasy), st), "update3");
@@ -257,7 +255,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     UpdateArgs u;
     memset(&u, 0, sizeof(u));
     u.src = cur;
-    u.W1 = ws + W.wp[p - 1];
+    u.C1 = ws + W.cp[p - 1];
     u.Z1 = ws + W.zp[p - 1];
     u.dense = a.o.fact == BORTH_SVQB;
     u.Q = a.Q;
@@ -272,12 +270,12 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     r = factor(p, later_proj ? a.ky : 0, ws + W.g_hi, nullptr, false, 0.0, p == passes - 1);
     if (r) return r;
     cur = Src{a.Y, a.ldy, a.Q, a.ldq, 0, a.m};
-    if (!later_proj) HIPCHK(c, launch_fill_int((int*)(ws + W.wp[p]), 2 * 64 * 64, 0, st), "zero W");
+    if (!later_proj) HIPCHK(c, launch_fill_int((int*)(ws + W.cp[p]), 2 * 64 * 64, 0, st), "zero C");
   }
   UpdateArgs u;
   memset(&u, 0, sizeof(u));
   u.src = cur;
-  u.W1 = ws + W.wp[passes - 1];
+  u.C1 = ws + W.cp[passes - 1];
   u.Z1 = ws + W.zp[passes - 1];
   u.dense = a.o.fact == BORTH_SVQB;
   u.Q = a.Q;
@@ -452,7 +450,6 @@ borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const 
   f.pass = 0;
   f.Zp = c->ws + W.zp[0];
   f.Cp = c->ws + W.cp[0];
-  f.Wp = c->ws + W.wp[0];
   f.Rtot = c->ws + W.rtot;
   f.Ctot = c->ws + W.ctot;
   f.status = c->status;
@@ -483,11 +480,14 @@ borth_status borth_update(borth_ctx c, int64_t m, int k, borth_dtype dt, const v
   HIPCHK(c, launch_fill_int((int*)cp, 2 * 64 * 64, 0, c->stream), "zero C");
   borth_status r = pad_copy(c, zp, kp, Z, k, k);
   if (r) return r;
-  if (ky > 0) HIPCHK(c, launch_neg_cz(C, Z, cp, ky, k, kp, c->stream), "neg_cz");
+  if (ky > 0) {
+    r = pad_copy(c, cp, kp, C, k, ky);
+    if (r) return r;
+  }
   UpdateArgs u;
   memset(&u, 0, sizeof(u));
   u.src = Src{Y, ldy, X, ldx, dt == BORTH_F32 ? 1 : 0, m};
-  u.W1 = cp;
+  u.C1 = cp;
   u.Z1 = zp;
   u.dense = z_dense ? 1 : 0;
   u.Q = Q;
@@ -566,6 +566,112 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
   }
   if (info || (o.flags & BORTH_FLAG_SYNC)) return read_status(c, info);
   return BORTH_OK;
+}
+
+borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const double* X,
+                                       int64_t ldx, const double* Y, int64_t ldy, int ky,
+                                       double* Q, int64_t ldq, double* R, double* C,
+                                       const borth_opts* opts, double eps, int max_iter,
+                                       borth_iter_info* it, borth_info* info) {
+  if (!c) return BORTH_ERR_ARG;
+  borth_opts o;
+  if (opts) o = *opts; else borth_default_opts(&o);
+  if (!it) return fail_arg(c, "iteration report (it) is required");
+  if (k < 1 || k > 64 || ky < 0 || ky > 64 || m < (int64_t)k + ky) return fail_arg(c, "shape");
+  if (!X || !Q || ldx < k || ldq < k) return fail_arg(c, "X/Q");
+  if (ky > 0 && (!Y || ldy < ky)) return fail_arg(c, "Y");
+  if ((const void*)Q == (const void*)X && ldq != ldx) return fail_arg(c, "aliasing");
+  if (!(eps >= 0.0) || max_iter < 1 || max_iter > 64) return fail_arg(c, "eps / max_iter");
+  if (o.gram != BORTH_GRAM_F64 && o.gram != BORTH_GRAM_DD) return fail_arg(c, "opts.gram");
+  if (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB) return fail_arg(c, "opts.fact");
+  if (o.fact == BORTH_SVQB && o.gram == BORTH_GRAM_DD) {
+    c->err = "SVQB runs in binary64 in this build";
+    return BORTH_ERR_UNSUPPORTED;
+  }
+  hipSetDevice(c->device);
+  c->cur = c->stream;
+  const bool dd = o.gram == BORTH_GRAM_DD;
+  GramLayout L = make_layout(ky, k, 4);
+  borth_status r = ensure(c, &c->part, &c->part_cap, kMaxSweepWG * (int64_t)L.E * 2);
+  if (r) return r;
+  const WsLayout W = ws_layout();
+  double* ws = c->ws;
+  const int kp = pow2pad(k);
+  double* conv = ws + W.cu;  // two doubles of the spare k x k area
+  HIPCHK(c, launch_fill_int(c->status, 4, 0, c->stream), "fill");
+  it->converged = 0;
+  it->passes_run = 0;
+  it->c_norm = it->r_dev = 0.0;
+  for (int p = 0; p < max_iter; ++p) {
+    const double* S = p == 0 ? X : Q;
+    const int64_t lds_ = p == 0 ? ldx : ldq;
+    Src src{Y, ldy, S, lds_, 0, m};
+    int nwg = 0;
+    prof_begin(c, 0);
+    HIPCHK(c, launch_gram(src, L, dd ? 1 : 0, c->part, c->part_cap, &nwg,
+                          lookup(c->tune_gram, dd ? 1 : 0, kp, ky > 0), c->stream),
+           "gram");
+    prof_end(c, 0);
+    HIPCHK(c, launch_reduce(L, dd ? 1 : 0, c->part, nwg, ws + W.g_hi, dd ? ws + W.g_lo : nullptr,
+                            c->stream),
+           "reduce");
+    FactorArgs f;
+    memset(&f, 0, sizeof(f));
+    f.ky = ky;
+    f.k = k;
+    f.kp = kp;
+    f.G_hi = ws + W.g_hi;
+    f.G_lo = dd ? ws + W.g_lo : nullptr;
+    f.dd = dd ? 1 : 0;
+    f.fact = o.fact;
+    f.shift_rel = 0.0;
+    f.pass = p;
+    f.Zp = ws + W.zp[0];
+    f.Cp = ws + W.cp[0];
+    f.Rtot = ws + W.rtot;
+    f.Ctot = ws + W.ctot;
+    f.status = c->status;
+    f.conv = conv;
+    HIPCHK(c, launch_factor(f, c->stream), "factor");
+    UpdateArgs u;
+    memset(&u, 0, sizeof(u));
+    u.src = src;
+    u.C1 = ws + W.cp[0];
+    u.Z1 = ws + W.zp[0];
+    u.dense = o.fact == BORTH_SVQB;
+    u.Q = Q;
+    u.ldq = ldq;
+    prof_begin(c, 1);
+    HIPCHK(c, launch_update(u, make_layout(ky, k, kp), lookup(c->tune_upd, 0, kp, ky > 0),
+                            c->stream),
+           "update");
+    prof_end(c, 1);
+    // stop test: status and the two norms of this pass
+    HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 4, hipMemcpyDeviceToHost,
+                             c->stream),
+           "status readback");
+    double hn[2] = {0.0, 0.0};
+    HIPCHK(c, hipMemcpyAsync(hn, conv, sizeof(hn), hipMemcpyDeviceToHost, c->stream), "norms");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    it->passes_run = p + 1;
+    it->c_norm = hn[0];
+    it->r_dev = hn[1];
+    if (c->h_status[0] != 0) break;
+    if (hn[0] <= eps && hn[1] <= eps) {
+      it->converged = 1;
+      break;
+    }
+  }
+  // totals: R = R_j ... R_1 and C (hi words of the DD totals)
+  if (R)
+    HIPCHK(c, hipMemcpyAsync(R, ws + W.rtot, sizeof(double) * k * k, hipMemcpyDeviceToDevice,
+                             c->stream),
+           "copy R");
+  if (C && ky > 0)
+    HIPCHK(c, hipMemcpyAsync(C, ws + W.ctot, sizeof(double) * ky * k, hipMemcpyDeviceToDevice,
+                             c->stream),
+           "copy C");
+  return read_status(c, info);
 }
 
 borth_status borth_set_profiling(borth_ctx c, int on) {

@@ -108,7 +108,6 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
 
   auto zero_out = [&]() {
     for (int e = tid; e < kp * kp; e += NT) a.Zp[e] = 0.0;
-    for (int e = tid; e < ky * kp; e += NT) a.Wp[e] = 0.0;
   };
   // A previous pass already failed: leave a zero transform and stop.
   if (a.status[0] != 0) {
@@ -325,21 +324,10 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
     a.Zp[e] = z;
     if (a.Z_out && i < k && l < k) a.Z_out[i * k + l] = z;
   }
-  // C (rounded) and W = -C Z_hi in DD, rounded: the update applies
-  // (S - Y C) Z_hi as S Z_hi + Y W.
+  // C of this pass, rounded, for the update (S - Y C) Z
   for (int e = tid; e < ky * kp; e += NT) {
     const int r = e / kp, j = e - r * kp;
-    double w = 0.0, cr = 0.0;
-    if (j < k) {
-      cr = s_r0[0][r * LD + j] + s_r0[1][r * LD + j];
-      Acc<DD> acc(dd_from(0.0));
-      for (int i = 0; i <= j; ++i)
-        acc.add(dd_make(s_r0[0][r * LD + i], s_r0[1][r * LD + i]), dd_from(s_r1[0][i * LD + j]));
-      const dd_t wd = acc.get();
-      w = -(wd.hi + wd.lo);
-    }
-    a.Cp[e] = cr;
-    a.Wp[e] = w;
+    a.Cp[e] = j < k ? s_r0[0][r * LD + j] + s_r0[1][r * LD + j] : 0.0;
   }
 
   // Totals: X = Y C_tot + X_cur R_tot.  After this pass
@@ -414,6 +402,39 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
           if (a.R_out) a.R_out[i * k + l] = v.hi;
         }
       }
+  }
+  if (a.conv) {
+    // stop test of the iterated scheme: ||C_p||_F (this pass's projection
+    // coefficients) and ||R_p - I||_F, summed in a fixed order
+    double rr = 0.0;
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && l < k && l >= i) {
+          const double d = x[p][q].hi - (i == l ? 1.0 : 0.0);
+          rr = __builtin_fma(d, d, rr);
+        }
+      }
+    double cc = 0.0;
+    for (int e = tid; e < ky * k; e += NT) {
+      const double v = a.G_hi[(e / k) * W + ky + e % k];
+      cc = __builtin_fma(v, v, cc);
+    }
+    __syncthreads();
+    s_r1[0][tid] = rr;
+    s_r1[1][tid] = cc;
+    __syncthreads();
+    if (tid == 0) {
+      double sr = 0.0, sc = 0.0;
+      for (int t = 0; t < NT; ++t) {
+        sr += s_r1[0][t];
+        sc += s_r1[1][t];
+      }
+      a.conv[0] = sqrt(sc);
+      a.conv[1] = sqrt(sr);
+    }
   }
   if (tid == 0) a.status[3] = a.pass + 1;
 }
@@ -561,15 +582,6 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     a.Cp[e] = j < k ? a.G_hi[l * W + ky + j] + (a.G_lo ? a.G_lo[l * W + ky + j] : 0.0) : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < ky * kp; e += NTF) {
-    const int l = e / kp, j = e - l * kp;
-    double w = 0.0;
-    if (j < k)
-      for (int i = 0; i < k; ++i)
-        w = __builtin_fma(a.G_hi[l * W + ky + i] + (a.G_lo ? a.G_lo[l * W + ky + i] : 0.0), a.Zp[i * kp + j], w);
-    a.Wp[e] = -w;
-  }
-  __syncthreads();
   // totals in binary64 (R_p dense): C_tot += C_p R_tot_old; R_tot = R_p R_tot_old
   const bool first = (a.pass == 0);
   // R_p into sM (reuse), computed from V and lam
@@ -611,6 +623,33 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     a.Rtot[e] = rnew[cnt];
     a.Rtot[k * k + e] = 0.0;
     if (a.R_out) a.R_out[e] = rnew[cnt];
+  }
+  if (a.conv) {
+    // stop test of the iterated scheme: ||C_p||_F and ||R_p - I||_F (R_p is
+    // in sM), summed in a fixed order
+    double rr = 0.0, cc = 0.0;
+    for (int e = tid; e < k * k; e += NTF) {
+      const int i = e / k, j = e - i * k;
+      const double d = sM[i * LD + j] - (i == j ? 1.0 : 0.0);
+      rr = __builtin_fma(d, d, rr);
+    }
+    for (int e = tid; e < ky * k; e += NTF) {
+      const double v = a.G_hi[(e / k) * W + ky + e % k];
+      cc = __builtin_fma(v, v, cc);
+    }
+    __syncthreads();
+    sV[tid] = rr;
+    sV[NTF + tid] = cc;
+    __syncthreads();
+    if (tid == 0) {
+      double sr = 0.0, sc = 0.0;
+      for (int t = 0; t < NTF; ++t) {
+        sr += sV[t];
+        sc += sV[NTF + t];
+      }
+      a.conv[0] = sqrt(sc);
+      a.conv[1] = sqrt(sr);
+    }
   }
   if (tid == 0) a.status[3] = a.pass + 1;
 }

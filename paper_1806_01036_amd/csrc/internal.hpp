@@ -110,8 +110,7 @@ struct FactorArgs {
   double shift_rel;         // > 0: add shift_rel * trace(M)
   int pass;                 // 0-based; pass 0 initializes the totals
   double* Zp;               // kp x kp (zero padded), binary64 hi words
-  double* Cp;               // ky x kp  (hi words of this pass's C)
-  double* Wp;               // ky x kp  W = -C Z (the update's Y coefficients)
+  double* Cp;               // ky x kp  (this pass's C, rounded, zero padded)
   double* Rtot;             // 2 * k * k  (DD totals, hi then lo)
   double* Ctot;             // 2 * ky * k
   int* status;              // [code, pass, pivot, passes_run]
@@ -119,6 +118,7 @@ struct FactorArgs {
   double* C_out;
   double* Z_out;            // optional unpadded Z (k x k)
   double* Rp_out;           // optional this-pass R (k x k)
+  double* conv;             // optional: ||C_p||_F and ||R_p - I||_F of this pass
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 // One workgroup per entry of the device table `tab` (n entries, all with
@@ -133,10 +133,10 @@ hipError_t launch_factor_table(const FactorArgs& one, const FactorArgs* tab, int
 struct UpdateArgs {
   int gram_with_y;
   Src src;
-  // Stage s computes T = S Z_s + Y W_s with W_s = -C_s Z_s (== (S - Y C_s) Z_s):
-  // Z_s kp x kp, W_s ky x kp (row-major, zero padded beyond k).
-  const double* W1; const double* Z1;
-  const double* W2; const double* Z2;
+  // Stage s computes T = (S - Y C_s) Z_s: Z_s kp x kp, C_s ky x kp
+  // (row-major, zero padded beyond k).
+  const double* C1; const double* Z1;
+  const double* C2; const double* Z2;
   int two_stage;
   int dense;                           // Z dense (SVQB)
   double* Q; int64_t ldq;
@@ -162,9 +162,9 @@ struct UpdDev {
   int64_t ldq;
   double* part;
   int64_t npanels;
-  const double* W1;  // stage coefficients (K x K Z, ky x K W, zero padded)
+  const double* C1;  // stage coefficients (ky x K C, K x K Z, zero padded)
   const double* Z1;
-  const double* W2;
+  const double* C2;
   const double* Z2;
   int wg0, nwg;
 };
@@ -189,10 +189,6 @@ int update_rows(int K);            // rows per wave panel
 // Layout of the fused Gram of an update sweep (of [Y | T] with Y padded to
 // 16 columns when with_y, else of T).
 GramLayout update_gram_layout(int ky, int k, int K, bool with_y);
-
-// W = -C Z (ky x kp, zero padded) for the public update entry point.
-hipError_t launch_neg_cz(const double* C, const double* Z, double* W, int ky, int k, int kp,
-                         hipStream_t st);
 
 // Fill helper (graph-safe replacement for hipMemsetAsync).
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);

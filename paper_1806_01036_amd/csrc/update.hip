@@ -65,9 +65,9 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.part = a.partials;
   const int PR = upd::upd_rows(K);
   d.npanels = (a.src.m + PR - 1) / PR;
-  d.W1 = a.W1;
+  d.C1 = a.C1;
   d.Z1 = a.Z1;
-  d.W2 = a.W2;
+  d.C2 = a.C2;
   d.Z2 = a.Z2;
   const int NW = upd::upd_waves(K, KYP, a.two_stage ? 2 : 1);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
@@ -86,26 +86,5 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   return launch_update_class(c, nwg, d, nullptr, nullptr, st);
 }
 
-
-// W = -C Z for the public update entry point (C: ky x k, Z: k x k, both
-// contiguous; W: ky x kp zero padded).  One thread per entry, binary64 FMAs.
-__global__ void neg_cz_kernel(const double* __restrict__ C, const double* __restrict__ Z,
-                              double* __restrict__ W, int ky, int k, int kp) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ky * kp) return;
-  const int r = e / kp, j = e - r * kp;
-  double s = 0.0;
-  if (j < k)
-    for (int i = 0; i < k; ++i) s = __builtin_fma(C[r * k + i], Z[i * k + j], s);
-  W[e] = -s;
-}
-
-hipError_t launch_neg_cz(const double* C, const double* Z, double* W, int ky, int k, int kp,
-                         hipStream_t st) {
-  const int n = ky * kp;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(neg_cz_kernel, dim3((n + 255) / 256), dim3(256), 0, st, C, Z, W, ky, k, kp);
-  return hipGetLastError();
-}
 
 }  // namespace borth

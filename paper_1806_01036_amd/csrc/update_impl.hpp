@@ -1,8 +1,9 @@
 // Basis update sweep (TSMM), the product of the projected block with Z
-// (Sec. 4.2), with the phase-I
-// projection folded in:  T = (S - Y C) Z = S Z + Y W  (W = -C Z) per row,
-// S = X (first pass) or Q_1 (later passes).  Optionally a second stage
-// T = T Z_2 + Y W_2 follows (CholQR2 with Q_1 recomputed instead of stored),
+// (Sec. 4.2), with the phase-I projection folded in:  T = (S - Y C) Z per
+// row, S = X (first pass) or Q_1 (later passes), the subtraction first (as
+// the paper orders it: when S lies close to span(Y), S Z and Y C Z are much
+// larger than T and would cancel).  Optionally a second stage
+// T = (T - Y C_2) Z_2 follows (CholQR2 with Q_1 recomputed instead of stored),
 // and the Gram matrix of [Y | T] (or of T) needed by the next pass is
 // accumulated from the values just computed (the fusion of operations that
 // Sec. 4.2 uses to save memory traffic).
@@ -13,7 +14,7 @@
 //    with no workgroup barrier in the loop: coalesced global loads -> LDS
 //    (row stride KYP + K + 2 doubles, compile-time, so all offsets are
 //    immediates);
-//  * Z and W are the B operands (lane l holds Z[4 s + l / 16][16 J + l % 16]):
+//  * Z and -C are the B operands (lane l holds Z[4 s + l / 16][16 J + l % 16]):
 //    in registers for the whole kernel for K <= 32, in LDS shared by the
 //    workgroup for K = 64; the A operands (lane l: S[row l % 16][col 4 s +
 //    l / 16]) are read from LDS;
@@ -112,8 +113,9 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   double* zl = lds;
   double* pan = lds + (ZL ? NST * ZST : 0) + wave * PR * S;
 
-  // B operands: in registers (lane l holds Z[4 s + l / 16][16 J + l % 16]),
-  // or for ZL rows of Z then rows of W in LDS, read at the same positions.
+  // B operands: in registers (lane l holds Z[4 s + l / 16][16 J + l % 16] and
+  // -C[4 s + l / 16][16 J + l % 16]), or for ZL rows of Z then rows of -C in
+  // LDS, read at the same positions.
   double zb[ZL ? 1 : NST][ZL ? 1 : KS][ZL ? 1 : KC];
   double wb[ZL ? 1 : NST][(ZL || YS == 0) ? 1 : YS][ZL ? 1 : KC];
   if (ZL) {
@@ -121,15 +123,15 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
       const int st = e / ((K + KYP) * K);
       const int r = (e / K) % (K + KYP), c = e % K;
       const double BORTH_GLOBAL* __restrict__ Zg = gmem(st ? a.Z2 : a.Z1);
-      const double BORTH_GLOBAL* __restrict__ Wg = gmem(st ? a.W2 : a.W1);
-      zl[st * ZST + r * ZS + c] = r < K ? Zg[r * K + c] : ((r - K) < ky ? Wg[(r - K) * K + c] : 0.0);
+      const double BORTH_GLOBAL* __restrict__ Cg = gmem(st ? a.C2 : a.C1);
+      zl[st * ZST + r * ZS + c] = r < K ? Zg[r * K + c] : ((r - K) < ky ? -Cg[(r - K) * K + c] : 0.0);
     }
     __syncthreads();
   } else {
 #pragma unroll
     for (int st = 0; st < NST; ++st) {
       const double BORTH_GLOBAL* __restrict__ Zg = gmem(st ? a.Z2 : a.Z1);
-      const double BORTH_GLOBAL* __restrict__ Wg = gmem(st ? a.W2 : a.W1);
+      const double BORTH_GLOBAL* __restrict__ Cg = gmem(st ? a.C2 : a.C1);
 #pragma unroll
       for (int s = 0; s < KS; ++s)
 #pragma unroll
@@ -142,7 +144,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
 #pragma unroll
         for (int J = 0; J < KC; ++J) {
           const int row = 4 * s + r4, col = 16 * J + c16;
-          wb[ZL ? 0 : st][ZL ? 0 : s][ZL ? 0 : J] = (row < ky && col < K) ? Wg[row * K + col] : 0.0;
+          wb[ZL ? 0 : st][ZL ? 0 : s][ZL ? 0 : J] = (row < ky && col < K) ? -Cg[row * K + col] : 0.0;
         }
     }
   }
@@ -210,6 +212,36 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
       d4_t t[KC];
 #pragma unroll
       for (int st = 0; st < NST; ++st) {
+        // 1. projection in the paper's order: Xt = S_st - Y C_st, accumulated
+        //    on the matrix cores into S_st itself (result layout: lane l,
+        //    register v holds row l / 16 + 4 v, column 16 J + l % 16), so the
+        //    subtraction is one rounding per product term on top of S; then
+        //    Xt goes back to LDS as the A operand of the product with Z.
+        //    S_0 is the panel, S_1 the previous stage's result (registers).
+        if (YS > 0) {
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (st == 0) t[J][v] = pb[doff + 4 * v * S + KYP + 16 * J];
+#pragma unroll
+          for (int s = 0; s < YS; ++s) {
+            const double av = pb[aoff + 4 * s];
+#pragma unroll
+            for (int J = 0; J < KC; ++J)
+              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw(st, s, J), t[J], 0, 0, 0);
+          }
+        }
+        if (YS > 0 || st > 0) {
+          wave_lds_sync();
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (16 * J + c16 < K) pb[doff + 4 * v * S + KYP + 16 * J] = t[J][v];
+          wave_lds_sync();
+        }
+        // 2. T = Xt Z_st
 #pragma unroll
         for (int J = 0; J < KC; ++J) t[J] = d4_t{0.0, 0.0, 0.0, 0.0};
         // with the B operands in LDS, a partly unrolled k loop bounds the
@@ -221,23 +253,6 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
           for (int J = 0; J < KC; ++J)
             if (dense || 4 * s <= 16 * J + 15)  // upper-triangular Z: skip zero blocks
               t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bz(st, s, J), t[J], 0, 0, 0);
-        }
-#pragma unroll
-        for (int s = 0; s < YS; ++s) {
-          const double av = pb[aoff + 4 * s];
-#pragma unroll
-          for (int J = 0; J < KC; ++J)
-            t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw(st, s, J), t[J], 0, 0, 0);
-        }
-        if (st + 1 < NST) {
-          // this stage's result is the next stage's A operand: back to LDS
-          wave_lds_sync();
-#pragma unroll
-          for (int J = 0; J < KC; ++J)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              if (16 * J + c16 < K) pb[doff + 4 * v * S + KYP + 16 * J] = t[J][v];
-          wave_lds_sync();
         }
       }
       // store T rows 16 b + l / 16 + 4 v, columns 16 J + l % 16

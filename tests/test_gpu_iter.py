@@ -1,0 +1,75 @@
+"""GPU tests of the iterated two-phase scheme (projection against Y and
+orthonormalization alternated until a pass changes nothing, Sec. 4.2), on
+the shape of the paper's runtime experiment (Fig. 8: few columns, a locked
+basis of 10-40 vectors, kappa(X) = 1e6, X within 1e-12 of span(Y))."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import U64, dev, host, lib, note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("k,ky", [(1, 10), (2, 20), (4, 40)])
+@pytest.mark.parametrize("gram,fact,kxy", [("f64", "svqb", 1e12), ("dd", "chol", 1e12),
+                                           ("f64", "chol", 1e4)])
+def test_iterated_scheme_converges(k, ky, gram, fact, kxy):
+    """binary64 Cholesky is run at kappa(X, Y) = 1e4 only: at 1e12 the
+    projected Gram matrix (smallest eigenvalue ~1e-24 against an absolute
+    binary64 error ~1e-16) is not positive definite and an unshifted
+    Cholesky must break down -- the paper's binary64 variant uses SVQB."""
+    borth = lib()
+    m = 100_000
+    X, Y = synth.projected_pair(m, k, ky, 1e6, kxy, 800 + 10 * k + ky)
+    Q, R, C, it, info = borth.orthonormalize_iter(dev(X), dev(Y), gram=gram, fact=fact,
+                                                  eps=1e-10, max_iter=8)
+    note("iter", k, ky, gram, fact, it)
+    assert info.status == 0 and it.converged and it.c_norm <= 1e-10 and it.r_dev <= 1e-10
+    met = oracle.metrics(host(Q), X, host(R), Y, host(C))
+    note("  metrics", met)
+    assert met["rho"] <= 1e-14
+    assert met["omega"] <= (20 * k * U64 if fact == "svqb" else 1e-14)
+    assert met["omega_y"] <= 1e-14
+    o1 = oracle.qr_q(X, Y)
+    assert np.max(np.abs(host(C) - o1["C"])) <= 1e-13
+    # the oracle's steps over the same number of passes reach the same levels
+    o2 = oracle.cholqr_steps(X, Y, dd_first=(gram == "dd"), passes=it.passes_run,
+                             project_each_pass=True)
+    assert o2["info"] == 0
+    m2 = oracle.metrics(o2["Q"], X, o2["R_hi"] + o2["R_lo"], Y, o2["C_hi"] + o2["C_lo"])
+    assert m2["omega_y"] <= 1e-14 and m2["omega"] <= 1e-14
+
+
+def test_iterated_scheme_dd_needs_fewer_passes():
+    """The point of the paper's DD variant: the DD projection resolves X's
+    tiny component outside span(Y) in one pass, so the scheme converges in
+    fewer passes than in binary64."""
+    borth = lib()
+    X, Y = synth.projected_pair(100_000, 4, 20, 1e6, 1e12, 901)
+    *_, it64, _ = borth.orthonormalize_iter(dev(X), dev(Y), gram="f64", fact="svqb", eps=1e-10,
+                                            max_iter=10)
+    *_, itdd, _ = borth.orthonormalize_iter(dev(X), dev(Y), gram="dd", fact="chol", eps=1e-10,
+                                            max_iter=10)
+    note("passes binary64", it64.passes_run, "DD", itdd.passes_run)
+    assert it64.converged and itdd.converged
+    assert itdd.passes_run < it64.passes_run
+
+
+def test_iterated_scheme_limits_and_errors():
+    borth = lib()
+    X, Y = synth.projected_pair(50_000, 2, 10, 1e6, 1e12, 902)
+    # one pass only, unreachable tolerance: reported as not converged
+    Q, R, C, it, info = borth.orthonormalize_iter(dev(X), dev(Y), gram="dd", eps=0.0, max_iter=1)
+    assert info.status == 0 and not it.converged and it.passes_run == 1
+    # in place
+    Xd = dev(X)
+    Q, R, C, it, info = borth.orthonormalize_iter(Xd, dev(Y), gram="dd", out=Xd, max_iter=6)
+    assert it.converged
+    met = oracle.metrics(host(Xd), X, host(R), Y, host(C))
+    assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14 and met["omega_y"] <= 1e-14
+    with pytest.raises(borth.BorthError):
+        borth.orthonormalize_iter(dev(X), dev(Y), gram="split")
+    with pytest.raises(borth.BorthError):
+        borth.orthonormalize_iter(dev(X), dev(Y), max_iter=0)
