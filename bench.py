@@ -348,12 +348,64 @@ def run_c5(args, torch, borth, synth):
     return out
 
 
+# Runtime per block vector of the paper's iterated project / SVQB experiment
+# (Fig. 8, an Intel Haswell workstation; n = 8e6 rows, kappa(X) = 1e6,
+# kappa(X, W) = 1e12), read off the figure: (k_y, n_b) -> seconds, for the
+# binary64 variant and the fused DD variant.  Context only (other hardware).
+FIG8_PAPER = {"f64": {(10, 1): 0.0164, (10, 2): 0.0216, (10, 4): 0.0195, (20, 1): 0.0324,
+                      (20, 2): 0.0425, (20, 4): 0.0382, (40, 1): 0.0805, (40, 2): 0.0901,
+                      (40, 4): 0.0644},
+              "dd": {(10, 1): 0.0152, (10, 2): 0.0127, (10, 4): 0.0117, (20, 1): 0.0309,
+                     (20, 2): 0.0256, (20, 4): 0.0205, (40, 1): 0.0783, (40, 2): 0.0611,
+                     (40, 4): 0.0410}}
+
+
+def run_fig8(args, torch, borth, synth):
+    """Iterated two-phase scheme to convergence (eps 1e-10) on the shapes of
+    the paper's runtime experiment: n = 8e6 rows, k_y in {10, 20, 40} locked
+    vectors, n_b in {1, 2, 4} new ones, kappa(X) = 1e6, kappa(X, Y) = 1e12.
+    Variants: binary64 Gram with SVQB, DD Gram with DD Cholesky."""
+    n = 8_000_000
+    rows = []
+    for ky in (10, 20, 40):
+        for k in (1, 2, 4):
+            X, Y = synth.projected_pair_device(n, k, ky, 1e6, 1e12, 7000 + 10 * ky + k)
+            Q = torch.empty_like(X)
+            for var, gram, fact in (("f64", "f64", "svqb"), ("dd", "dd", "chol")):
+                res = borth.orthonormalize_iter(X, Y, gram=gram, fact=fact, eps=1e-10, max_iter=10,
+                                                out=Q)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(max(1, args.steps)):
+                    t0 = time.perf_counter()
+                    res = borth.orthonormalize_iter(X, Y, gram=gram, fact=fact, eps=1e-10,
+                                                    max_iter=10, out=Q)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                t = sorted(ts)[len(ts) // 2]
+                it = res[3]
+                ghi, glo = borth.gram(Q, A=Y, prec="dd")
+                g = ghi.cpu().numpy()
+                lo = glo.cpu().numpy()
+                om = float(np.linalg.norm((g[ky:, ky:] - np.eye(k)) + lo[ky:, ky:]))
+                omy = float(np.linalg.norm(g[:ky, ky:] + lo[:ky, ky:]))
+                r = dict(ky=ky, nb=k, variant=var, passes=it.passes_run, converged=it.converged,
+                         s_per_vector=t / k, omega=om, omega_y=omy,
+                         paper_haswell_s_per_vector=FIG8_PAPER[var][(ky, k)])
+                log(r)
+                rows.append(r)
+            del X, Y, Q
+    return {"workload": "iterated project / orthonormalize to convergence, n = 8e6, "
+                        "kappa(X) = 1e6, kappa(X, Y) = 1e12 (the paper's runtime experiment)",
+            "data": "synthetic", "n_gpus": 1, "results": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "fig8"])
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--blocks", type=int, default=256)
@@ -373,7 +425,7 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    fn = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5}.get(args.workload)
+    fn = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fig8": run_fig8}.get(args.workload)
     if fn is None:
         raise SystemExit(f"workload {args.workload} not available")
     out = fn(args, torch, borth, synth)

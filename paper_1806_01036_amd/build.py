@@ -30,6 +30,8 @@ SOURCES = [
     "update_k16.hip",
     "update_k32.hip",
     "update_k64.hip",
+    "update_narrow.hip",
+    "update_narrow_gram.hip",
     "batch.cpp",
     "borth.cpp",
 ]

@@ -41,7 +41,7 @@ struct BatchStep {
   int gkind = 0, gmode = 0, garg = 0;
   size_t shmem = 0;
   // REDUCE
-  int maxE = 0;
+  int red_nb = 0;  // blocks of the reduction launch
   // FACTOR
   FactorArgs fone;
   // UPDATE
@@ -304,18 +304,18 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
 
   auto add_reduce = [&](int sweep, int mode) {
     std::vector<ReduceSeg> segs(nb);
-    int maxE = 0;
+    int red_nb = 0;
     for (int b = 0; b < nb; ++b) {
       const GramLayout& L = sweep == 0 ? L1[b] : Lu[sweep][b];
       const int n = sweep == 0 ? nwg_g[b] : nwg_u[sweep][b];
       segs[b] = ReduceSeg{L, part + W[b].part, n, ws + W[b].ghi,
                           (sweep == 0 && dd) ? ws + W[b].glo : nullptr};
-      maxE = std::max(maxE, L.E);
+      red_nb = std::max(red_nb, reduce_blocks(L.E));
     }
     BatchStep s;
     s.kind = BatchStep::REDUCE;
     s.gmode = mode;
-    s.maxE = maxE;
+    s.red_nb = red_nb;
     s.grid = nb;
     s.tab_off = tb.add(segs);
     steps.push_back(s);
@@ -455,7 +455,7 @@ borth_status run_plan(borth_ctx c, BatchPlan* P, hipStream_t st) {
         const ReduceSeg* tab = (const ReduceSeg*)(P->dtab + s.tab_off);
         ReduceSeg none;
         std::memset(&none, 0, sizeof(none));
-        HIPCHK(c, launch_reduce_segs(s.gmode, s.maxE, s.grid, none, tab, st), "batch reduce");
+        HIPCHK(c, launch_reduce_segs(s.gmode, s.red_nb, s.grid, none, tab, st), "batch reduce");
         break;
       }
       case BatchStep::FACTOR: {

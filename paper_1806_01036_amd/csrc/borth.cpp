@@ -592,6 +592,7 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
   c->cur = c->stream;
   const bool dd = o.gram == BORTH_GRAM_DD;
   GramLayout L = make_layout(ky, k, 4);
+  const GramLayout Lx = make_layout_xcols(ky, k, 4);
   borth_status r = ensure(c, &c->part, &c->part_cap, kMaxSweepWG * (int64_t)L.E * 2);
   if (r) return r;
   const WsLayout W = ws_layout();
@@ -602,19 +603,31 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
   it->converged = 0;
   it->passes_run = 0;
   it->c_norm = it->r_dev = 0.0;
+  // Narrow blocks: each update also accumulates the next pass's Gram columns
+  // (the fused operations of Sec. 4.2), so after the first pass no separate
+  // sweep over the block is made.
+  const bool fuse = k <= 8 && ky + k <= 64 &&
+                    (ky == 0 || (ky % 2 == 0 && ldy == ky && ((uintptr_t)Y & 15) == 0));
+  bool have_gram = false;  // the Gram of this pass's input is already reduced
   for (int p = 0; p < max_iter; ++p) {
     const double* S = p == 0 ? X : Q;
     const int64_t lds_ = p == 0 ? ldx : ldq;
     Src src{Y, ldy, S, lds_, 0, m};
-    int nwg = 0;
-    prof_begin(c, 0);
-    HIPCHK(c, launch_gram(src, L, dd ? 1 : 0, c->part, c->part_cap, &nwg,
-                          lookup(c->tune_gram, dd ? 1 : 0, kp, ky > 0), c->stream),
-           "gram");
-    prof_end(c, 0);
-    HIPCHK(c, launch_reduce(L, dd ? 1 : 0, c->part, nwg, ws + W.g_hi, dd ? ws + W.g_lo : nullptr,
+    if (!have_gram) {
+      int nwg = 0;
+      // Y does not change between passes: after the first, only the columns
+      // [Y | S]^T S are swept and Y^T Y stays from the first pass's reduction.
+      const GramLayout Lg = p > 0 ? Lx : L;
+      prof_begin(c, 0);
+      HIPCHK(c, launch_gram(src, Lg, dd ? 1 : 0, c->part, c->part_cap, &nwg,
+                            p > 0 ? TuneGram{} : lookup(c->tune_gram, dd ? 1 : 0, kp, ky > 0),
                             c->stream),
-           "reduce");
+             "gram");
+      prof_end(c, 0);
+      HIPCHK(c, launch_reduce(Lg, dd ? 1 : 0, c->part, nwg, ws + W.g_hi, dd ? ws + W.g_lo : nullptr,
+                              c->stream),
+             "reduce");
+    }
     FactorArgs f;
     memset(&f, 0, sizeof(f));
     f.ky = ky;
@@ -641,11 +654,23 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
     u.dense = o.fact == BORTH_SVQB;
     u.Q = Q;
     u.ldq = ldq;
+    if (fuse) {
+      u.partials = c->part;
+      u.partial_cap_doubles = c->part_cap;
+      u.gram_xcols = 1;
+      u.gram_dd = dd ? 1 : 0;
+    }
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u, make_layout(ky, k, kp), lookup(c->tune_upd, 0, kp, ky > 0),
                             c->stream),
            "update");
     prof_end(c, 1);
+    if (fuse) {
+      HIPCHK(c, launch_reduce(u.glayout, dd ? 1 : 0, c->part, u.nwg, ws + W.g_hi,
+                              dd ? ws + W.g_lo : nullptr, c->stream),
+             "reduce (fused)");
+      have_gram = true;
+    }
     // stop test: status and the two norms of this pass
     HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 4, hipMemcpyDeviceToHost,
                              c->stream),

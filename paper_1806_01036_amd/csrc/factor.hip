@@ -446,6 +446,7 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
   const FactorArgs a = tab ? tab[blockIdx.x] : one;
   __shared__ double sM[64 * 65];
   __shared__ double sV[64 * 65];
+  __shared__ double sC[64 * 65];
   __shared__ double sc[32], ss[32];
   __shared__ int sp[32], sq[32];
   __shared__ int s_flag;
@@ -456,18 +457,42 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     for (int e = tid; e < kp * kp; e += NTF) a.Zp[e] = 0.0;
     return;
   }
-  // M = G_XX - C^T (2C - S C) in binary64 (hi + lo folded).
-  for (int e = tid; e < k * k; e += NTF) {
-    const int i = e / k, l = e - i * k;
-    auto g = [&](int r, int c) { return a.G_hi[r * W + c] + (a.G_lo ? a.G_lo[r * W + c] : 0.0); };
-    double v = g(ky + i, ky + l);
-    for (int r = 0; r < ky; ++r) {
-      double sc2 = 0.0;
-      for (int q = 0; q < ky; ++q) sc2 = __builtin_fma(g(r, q), g(q, ky + l), sc2);
-      v = __builtin_fma(-g(r, ky + i), 2.0 * g(r, ky + l) - sc2, v);
+  // M = G_XX - C^T (2C - S C) in binary64 (hi + lo folded), in three
+  // parallel steps through LDS: S and C staged, D = 2C - S C (one thread per
+  // element of D), then M (one thread per element of M); every element is
+  // the same fused multiply-add chain, in the same order, as one thread
+  // computing it alone.
+  auto g = [&](int r, int c) { return a.G_hi[r * W + c] + (a.G_lo ? a.G_lo[r * W + c] : 0.0); };
+  for (int e = tid; e < ky * ky; e += NTF) sM[(e / ky) * LD + e % ky] = g(e / ky, e % ky);
+  for (int e = tid; e < ky * k; e += NTF) sC[(e / k) * LD + e % k] = g(e / k, ky + e % k);
+  __syncthreads();
+  for (int e = tid; e < ky * k; e += NTF) {
+    const int r = e / k, l = e - r * k;
+    double sc2 = 0.0;
+    for (int q = 0; q < ky; ++q) sc2 = __builtin_fma(sM[r * LD + q], sC[q * LD + l], sc2);
+    sV[r * LD + l] = 2.0 * sC[r * LD + l] - sc2;
+  }
+  __syncthreads();
+  double mv[(64 * 64 + NTF - 1) / NTF];
+#pragma unroll
+  for (int u = 0; u < (64 * 64 + NTF - 1) / NTF; ++u) {
+    const int e = tid + u * NTF;
+    if (e < k * k) {
+      const int i = e / k, l = e - i * k;
+      double v = g(ky + i, ky + l);
+      for (int r = 0; r < ky; ++r) v = __builtin_fma(-sC[r * LD + i], sV[r * LD + l], v);
+      mv[u] = v;
     }
-    sM[i * LD + l] = v;
-    sV[i * LD + l] = (i == l) ? 1.0 : 0.0;
+  }
+  __syncthreads();  // D is read; sM and sV are free
+#pragma unroll
+  for (int u = 0; u < (64 * 64 + NTF - 1) / NTF; ++u) {
+    const int e = tid + u * NTF;
+    if (e < k * k) {
+      const int i = e / k, l = e - i * k;
+      sM[i * LD + l] = mv[u];
+      sV[i * LD + l] = (i == l) ? 1.0 : 0.0;
+    }
   }
   if (tid == 0) s_flag = 0;
   __syncthreads();

@@ -39,17 +39,31 @@ GramLayout make_layout(int ky, int k, int kp_min) {
   L.T4 = L.Wp / 4;
   L.ntiles = L.T4 * (L.T4 + 1) / 2;
   L.E = 16 * L.ntiles;
+  L.ty = 0;
   return L;
 }
 
-__device__ __forceinline__ void decode_tile(int t, int T4, int& ti, int& tj) {
+GramLayout make_layout_xcols(int ky, int k, int kp_min) {
+  GramLayout L = make_layout(ky, k, kp_min);
+  L.ty = L.kyp / 4;
+  int n = 0;
+  for (int ti = 0; ti < L.T4; ++ti) n += L.T4 - (ti > L.ty ? ti : L.ty);
+  L.ntiles = n;
+  L.E = 16 * n;
+  return L;
+}
+
+// Tile t of the layout's enumeration -> (ti, tj): row ti holds the tiles
+// tj = max(ti, ty) .. T4 - 1.
+__device__ __forceinline__ void decode_tile(int t, const GramLayout& L, int& ti, int& tj) {
   int r = 0, base = 0;
-  while (t >= base + (T4 - r)) {
-    base += T4 - r;
+  auto cnt = [&](int row) { return L.T4 - (row > L.ty ? row : L.ty); };
+  while (t >= base + cnt(r)) {
+    base += cnt(r);
     ++r;
   }
   ti = r;
-  tj = r + (t - base);
+  tj = (r > L.ty ? r : L.ty) + (t - base);
 }
 
 __device__ __forceinline__ int tile_index(int ti, int tj, int T4) {
@@ -91,7 +105,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   const int t = active ? tid % nt : 0;
   const int phase = active ? tid / nt : 0;
   int ti, tj;
-  decode_tile(t, L.T4, ti, tj);
+  decode_tile(t, L, ti, tj);
 
   double acs[16], acc[16];
 #pragma unroll
@@ -300,10 +314,22 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(GramSeg one,
 }
 
 // ---------------------------------------------------------------------------
+// Threads per Gram entry of the reduction (the rest of the 1024-thread block
+// covers 1024 / G entries): more of them for small Grams, so that the chain of
+// partials each thread walks stays short.  A function of the segment's own
+// size only, so a segment's summation order does not depend on the others
+// in a batched launch.
+__host__ __device__ inline int reduce_groups(int E) { return E <= 256 ? 64 : (E <= 1024 ? 32 : 16); }
+
+int reduce_blocks(int E) {
+  const int epb = 1024 / reduce_groups(E);
+  return (E + epb - 1) / epb;
+}
+
 template <bool DD>
 __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
                                                       const ReduceSeg* __restrict__ tab) {
-  __shared__ double sh[16][64], sl[16][64];
+  __shared__ double sh[1024], sl[1024];
   const ReduceSeg rs = tab ? tab[blockIdx.y] : one;
   const GramLayout& L = rs.L;
   const double BORTH_GLOBAL* __restrict__ part = gmem(rs.part);
@@ -311,26 +337,27 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
   double BORTH_GLOBAL* __restrict__ Ghi = gmem(rs.Ghi);
   double BORTH_GLOBAL* __restrict__ Glo = rs.Glo ? gmem(rs.Glo) : nullptr;
   const int E = L.E;
-  if ((int)blockIdx.x * 64 >= E) return;  // batched launch: a narrower block
-  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + el;
+  const int G = reduce_groups(E), EPB = 1024 / G;
+  if ((int)blockIdx.x * EPB >= E) return;  // batched launch: a smaller segment
+  const int el = threadIdx.x % EPB, g = threadIdx.x / EPB;
+  const int e = blockIdx.x * EPB + el;
   double h = 0.0, l = 0.0;
   if (e < E) {
-    // partials g, g + 16, ...: loaded 8 at a time so their latencies overlap,
+    // partials g, g + G, ...: loaded 8 at a time so their latencies overlap,
     // added in index order
     constexpr int B = 8;
-    for (int w0 = g; w0 < nwg; w0 += 16 * B) {
+    for (int w0 = g; w0 < nwg; w0 += G * B) {
       double vh[B], vl[B];
 #pragma unroll
       for (int u = 0; u < B; ++u) {
-        const int w = w0 + 16 * u;
+        const int w = w0 + G * u;
         const int64_t off = (int64_t)(w < nwg ? w : 0) * E + e;
         vh[u] = DD ? part[2 * off] : part[off];
         vl[u] = DD ? part[2 * off + 1] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < B; ++u) {
-        if (w0 + 16 * u >= nwg) break;
+        if (w0 + G * u >= nwg) break;
         if (DD) {
           const dd_t v = dd_add(dd_make(h, l), dd_make(vh[u], vl[u]));
           h = v.hi;
@@ -341,22 +368,22 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
       }
     }
   }
-  sh[g][el] = h;
-  sl[g][el] = l;
+  sh[threadIdx.x] = h;
+  sl[threadIdx.x] = l;
   __syncthreads();
   if (g != 0 || e >= E) return;
-  for (int q = 1; q < 16; ++q) {
+  for (int q = 1; q < G; ++q) {
     if (DD) {
-      const dd_t v = dd_add(dd_make(h, l), dd_make(sh[q][el], sl[q][el]));
+      const dd_t v = dd_add(dd_make(h, l), dd_make(sh[q * EPB + el], sl[q * EPB + el]));
       h = v.hi;
       l = v.lo;
     } else {
-      h += sh[q][el];
+      h += sh[q * EPB + el];
     }
   }
   const int t = e >> 4, a = (e >> 2) & 3, b = e & 3;
   int ti, tj;
-  decode_tile(t, L.T4, ti, tj);
+  decode_tile(t, L, ti, tj);
   const int pi = 4 * ti + a, pj = 4 * tj + b;
   if (pi > pj) return;  // lower half of a diagonal tile: written by its mirror
   auto logical = [&](int p) -> int {
@@ -381,7 +408,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
 
 int gram_kind(const GramLayout& L, int mode) {
   const int W16 = (L.Wp + 15) / 16;
-  return (mode == 0 && L.Wp >= 16 && W16 <= 5) ? 0 : 1;
+  return (mode == 0 && L.ty == 0 && L.Wp >= 16 && W16 <= 5) ? 0 : 1;
 }
 
 // 256 threads (one 4x4 tile each; row phases when there are fewer than 128
@@ -542,9 +569,8 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
   return launch_gram_segs(kind, mode, arg, shmem, nwg, g, nullptr, nullptr, st);
 }
 
-hipError_t launch_reduce_segs(int mode, int maxE, int nseg, const ReduceSeg& one,
+hipError_t launch_reduce_segs(int mode, int nb, int nseg, const ReduceSeg& one,
                               const ReduceSeg* tab, hipStream_t st) {
-  const int nb = (maxE + 63) / 64;
   if (nb < 1 || nseg < 1) return hipSuccess;
   if (mode == 1)
     hipLaunchKernelGGL(reduce_kernel<true>, dim3(nb, nseg), dim3(1024), 0, st, one, tab);
@@ -556,7 +582,7 @@ hipError_t launch_reduce_segs(int mode, int maxE, int nseg, const ReduceSeg& one
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
                          double* G_hi, double* G_lo, hipStream_t st) {
   ReduceSeg r{L, partials, nwg, G_hi, G_lo};
-  return launch_reduce_segs(mode, L.E, 1, r, nullptr, st);
+  return launch_reduce_segs(mode, reduce_blocks(L.E), 1, r, nullptr, st);
 }
 
 __global__ void fill_int_kernel(int* p, int n, int v) {

@@ -27,9 +27,14 @@ struct GramLayout {
   int T4;       // Wp / 4
   int ntiles;   // T4 (T4 + 1) / 2
   int E;        // ntiles * 16
+  int ty;       // first tile column computed: 0, or kyp / 4 for the columns of X only
 };
 
 GramLayout make_layout(int ky, int k, int kp_min);
+// The tiles of [Y | X]^T X only (Y^T Y left out): the Gram sweep of a pass
+// whose Y^T Y is already known.  Tiles (ti, tj), ti <= tj, tj >= kyp / 4, in
+// row-major order.
+GramLayout make_layout_xcols(int ky, int k, int kp_min);
 
 // Source block for a sweep: [Y | X] rows.
 struct Src {
@@ -96,8 +101,10 @@ struct ReduceSeg {
 };
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
                          double* G_hi, double* G_lo, hipStream_t st);
-// nseg segments (grid.y), maxE = the largest L.E among them.
-hipError_t launch_reduce_segs(int mode, int maxE, int nseg, const ReduceSeg& one,
+// Blocks (grid.x) of the reduction of a Gram with E entries.
+int reduce_blocks(int E);
+// nseg segments (grid.y); nb = the largest reduce_blocks(L.E) among them.
+hipError_t launch_reduce_segs(int mode, int nb, int nseg, const ReduceSeg& one,
                               const ReduceSeg* tab, hipStream_t st);
 
 // k x k factorization, one workgroup.
@@ -141,6 +148,8 @@ struct UpdateArgs {
   int dense;                           // Z dense (SVQB)
   double* Q; int64_t ldq;
   double* partials; int64_t partial_cap_doubles;
+  int gram_xcols;                      // narrow fused Gram: [Y | T]^T T only
+  int gram_dd;                         //   ... in DD
   int nwg;                             // out: partials written
   GramLayout glayout;                  // out: layout of those partials
 };
@@ -176,6 +185,17 @@ struct UpdClass {
   int gr;      // 0 no Gram, 1 Gram of T, 2 Gram of [Y | T]
   int f32;     // X stored as fp32
 };
+// Narrow blocks (k <= 8, ky <= 64), single stage, no fused Gram: the VALU
+// stream kernel of update_narrow.hip.  kp: row stride of C and Z.
+bool update_narrow_ok(int k, int ky, int kp);
+hipError_t launch_update_narrow(const UpdDev& d, int kp, hipStream_t st);
+// The same sweep with the next pass's Gram columns [Y | T]^T T written as
+// partials (binary64, or DD when mode = 1) in the layout G =
+// make_layout_xcols(ky, k, 4), one per workgroup, at most max_wg of them;
+// *nwg = partials written.  Needs ky + k <= 64 and Y dense with ky even.
+bool update_narrow_gram_ok(const UpdDev& d, int kp);
+hipError_t launch_update_narrow_gram(const UpdDev& d, int kp, int mode, const GramLayout& G,
+                                     int64_t max_wg, int* nwg, hipStream_t st);
 // One per padded width K (separate translation units, compiled in parallel).
 hipError_t launch_update_k4(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);
 hipError_t launch_update_k8(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);

@@ -1,10 +1,10 @@
 // Basis update sweep (TSMM), the product of the projected block with Z
-// (Sec. 4.2), with the phase-I
-// projection folded in: T = (S - Y C) Z = S Z + Y W per row (W = -C Z),
-// S = X (first pass) or Q_1 (later passes); optionally a second stage and
-// the next pass's Gram matrix fused in (kernels in update_impl.hpp, one
-// translation unit per padded width K).  This file holds the host-side
-// dispatch.
+// (Sec. 4.2), with the phase-I projection folded in: T = (S - Y C) Z per
+// row, S = X (first pass) or Q_1 (later passes); optionally a second stage
+// and the next pass's Gram matrix fused in (matrix-core kernels in
+// update_impl.hpp, one translation unit per padded width K).  Narrow
+// single-stage sweeps without a fused Gram go to the vector-ALU stream kernel
+// of update_narrow.hip.  This file holds the host-side dispatch.
 #include "update_impl.hpp"
 
 namespace borth {
@@ -69,6 +69,18 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.Z1 = a.Z1;
   d.C2 = a.C2;
   d.Z2 = a.Z2;
+  if (!a.partials && !a.two_stage && !a.src.x_f32 && a.Q && update_narrow_ok(L.k, L.ky, K)) {
+    a.nwg = 0;
+    return launch_update_narrow(d, K, st);
+  }
+  if (a.partials && a.gram_xcols) {
+    // only the narrow kernel computes the Gram columns [Y | T]^T T
+    if (a.two_stage || a.src.x_f32 || !a.Q || !update_narrow_gram_ok(d, K)) return hipErrorInvalidValue;
+    a.glayout = make_layout_xcols(L.ky, L.k, 4);
+    d.gE = a.glayout.E;
+    const int64_t slots = a.partial_cap_doubles / ((int64_t)a.glayout.E * (a.gram_dd ? 2 : 1));
+    return launch_update_narrow_gram(d, K, a.gram_dd, a.glayout, slots, &a.nwg, st);
+  }
   const int NW = upd::upd_waves(K, KYP, a.two_stage ? 2 : 1);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   const int64_t need = (d.npanels + NW - 1) / NW;

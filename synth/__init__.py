@@ -40,6 +40,7 @@ __all__ = [
     "projected_pair",
     "svd_matrix_device",
     "locked_basis_device",
+    "projected_pair_device",
 ]
 
 
@@ -192,3 +193,23 @@ def locked_basis_device(m: int, ky: int, seed: int, device="cuda"):
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
     return _haar_device(torch, gen, m, ky, device)
+
+
+def projected_pair_device(m: int, k: int, ky: int, kappa_x: float, kappa_xy: float,
+                          seed: int, device="cuda"):
+    """``projected_pair`` drawn on the device (torch Philox stream seeded with
+    ``seed``): Y (m x ky) and X = Y A + P B with P orthonormal and P^T Y = 0."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    yp = _haar_device(torch, gen, m, ky + k, device)
+    y = yp[:, :ky].contiguous()
+    p = yp[:, ky:]
+    a = torch.randn((ky, k), generator=gen, dtype=torch.float64, device=device)
+    a /= torch.linalg.matrix_norm(a, ord=2)
+    vb = _haar_device(torch, gen, k, k, device)
+    wb = _haar_device(torch, gen, k, k, device)
+    sig = (1.0 / kappa_xy) * kappa_x * torch.from_numpy(sigma_logspace(k, kappa_x)).to(device)
+    b = (vb * sig[None, :]) @ wb.t().contiguous()
+    x = y @ a + p @ b
+    return x.contiguous(), y

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import U64, dev, host, lib, note
+from gpu_common import U64, dev, host, lib, note, torch_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +40,41 @@ def test_iterated_scheme_converges(k, ky, gram, fact, kxy):
     assert o2["info"] == 0
     m2 = oracle.metrics(o2["Q"], X, o2["R_hi"] + o2["R_lo"], Y, o2["C_hi"] + o2["C_lo"])
     assert m2["omega_y"] <= 1e-14 and m2["omega"] <= 1e-14
+
+
+@pytest.mark.parametrize("m,k,ky,strided", [(30011, 8, 0, False), (30011, 3, 7, False),
+                                           (30011, 5, 59, False), (30011, 8, 60, False),
+                                           (30011, 2, 12, True), (20000, 1, 63, False),
+                                           (1000, 4, 16, False)])
+@pytest.mark.parametrize("gram,fact", [("f64", "svqb"), ("dd", "chol")])
+def test_iterated_scheme_layouts(m, k, ky, strided, gram, fact):
+    """Narrow blocks with Y dense and ky even take the update with the Gram
+    columns fused in; odd ky, ky + k > 64 and a strided Y take the separate
+    sweep over [Y | X]^T X; ky = 0 is iterated CholQR / SVQB.  All reach the
+    same levels."""
+    borth = lib()
+    torch = torch_gpu()
+    X, Y = synth.projected_pair(m, k, ky, 1e6, 1e10, 1900 + 7 * k + ky) if ky else \
+        (synth.svd_matrix(m, k, 1e6, 1900 + k), None)
+    Yd = None
+    if ky:
+        Yd = dev(np.hstack([Y, np.zeros((m, 3))]))[:, :ky] if strided else dev(Y)
+    Q, R, C, it, info = borth.orthonormalize_iter(dev(X), Yd, gram=gram, fact=fact, eps=1e-10,
+                                                  max_iter=8)
+    note("iter layouts", m, k, ky, strided, gram, fact, it)
+    assert info.status == 0 and it.converged
+    met = oracle.metrics(host(Q), X, host(R), Y, host(C) if ky else None)
+    note("  metrics", met)
+    # binary64 SVQB applies the dense symmetric Z as a product: its residual
+    # carries k kappa u times the norm of the part it factors (CholQR's
+    # triangular factor keeps it O(u)): kappa = 1e6 and, with Y present, the
+    # part outside span(Y) has norm kappa(X) / kappa(X, Y) = 1e-4
+    svqb_rho = 4 * k * 1e6 * U64 * (1e-4 if ky else 1.0)
+    assert met["rho"] <= (max(1e-14, svqb_rho) if fact == "svqb" else 1e-14)
+    assert met["omega"] <= (20 * k * U64 if fact == "svqb" else 1e-14)
+    if ky:
+        assert met["omega_y"] <= 1e-14
+        assert np.max(np.abs(host(C) - oracle.qr_q(X, Y)["C"])) <= 1e-13
 
 
 def test_iterated_scheme_dd_needs_fewer_passes():

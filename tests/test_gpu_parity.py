@@ -206,6 +206,45 @@ def test_update_vs_oracle(m, k, ky, dense):
     assert np.all(np.abs(Q - ex) <= bound)
 
 
+@pytest.mark.parametrize("m,k,ky,dense,strided", [
+    (5003, 1, 10, False, False), (5003, 2, 20, True, False), (5003, 4, 40, False, False),
+    (4099, 3, 17, False, False), (4099, 5, 33, True, False), (4099, 8, 64, False, False),
+    (4099, 1, 0, False, False), (4099, 4, 1, False, False), (4099, 2, 63, False, True),
+    (130, 4, 16, True, True), (65, 1, 64, False, False), (63, 8, 7, False, True),
+    (64, 4, 40, False, False), (1, 1, 0, False, False)])
+def test_update_narrow_vs_oracle(m, k, ky, dense, strided):
+    """Narrow blocks (k <= 8, any ky <= 64) take the vector-ALU stream kernel:
+    ragged panels, every Y width class, odd widths, and row strides larger
+    than the widths (then the flat loads of a panel are not contiguous)."""
+    borth = lib()
+    torch = torch_gpu()
+    note("update narrow", m, k, ky, dense, strided)
+    rng = np.random.default_rng(3000 + m + 7 * k + ky)
+    X = rng.standard_normal((m, k))
+    Y = rng.standard_normal((m, ky)) if ky else None
+    C = rng.standard_normal((ky, k)) if ky else None
+    Z = rng.standard_normal((k, k))
+    if not dense:
+        Z = np.triu(Z)
+
+    def place(A, extra):
+        if A is None or not strided:
+            return None if A is None else dev(A)
+        W = dev(np.hstack([A, np.full((A.shape[0], extra), np.nan)]))
+        return W[:, :A.shape[1]]
+
+    Xd, Yd = place(X, 3), place(Y, 5)
+    out = torch.full((m, k + (2 if strided else 0)), np.nan, dtype=torch.float64,
+                     device="cuda")[:, :k]
+    Q = host(borth.update(Xd, dev(Z), Yd, None if C is None else dev(C), dense=dense, out=out))
+    ex = oracle.update_q(X, Z, Y, C)
+    mag = np.abs(X) + (np.abs(Y) @ np.abs(C) if ky else 0)
+    bound = (2 * (k + ky) + 2) * U64 * (mag @ np.abs(Z)) + U64 * np.abs(ex)
+    assert np.all(np.abs(Q - ex) <= bound)
+    if strided:  # nothing written outside the k columns
+        assert torch.isnan(out.as_strided((m, 2), (k + 2, 1), out.storage_offset() + k)).all()
+
+
 def test_update_inplace_and_fp32():
     borth = lib()
     torch = torch_gpu()
