@@ -351,35 +351,41 @@ def run_c5(args, torch, borth, synth):
 # Runtime per block vector of the paper's iterated project / SVQB experiment
 # (Fig. 8, an Intel Haswell workstation; n = 8e6 rows, kappa(X) = 1e6,
 # kappa(X, W) = 1e12), read off the figure: (k_y, n_b) -> seconds, for the
-# binary64 variant and the fused DD variant.  Context only (other hardware).
-FIG8_PAPER = {"f64": {(10, 1): 0.0164, (10, 2): 0.0216, (10, 4): 0.0195, (20, 1): 0.0324,
-                      (20, 2): 0.0425, (20, 4): 0.0382, (40, 1): 0.0805, (40, 2): 0.0901,
-                      (40, 4): 0.0644},
-              "dd": {(10, 1): 0.0152, (10, 2): 0.0127, (10, 4): 0.0117, (20, 1): 0.0309,
-                     (20, 2): 0.0256, (20, 4): 0.0205, (40, 1): 0.0783, (40, 2): 0.0611,
-                     (40, 4): 0.0410}}
+# plain binary64 variant, the variant with fused operations and the one with
+# fused DD operations.  Context only (other hardware).
+FIG8_PAPER = {
+    "plain": {(10, 1): 0.0164, (10, 2): 0.0216, (10, 4): 0.0195, (20, 1): 0.0324, (20, 2): 0.0425,
+              (20, 4): 0.0382, (40, 1): 0.0805, (40, 2): 0.0901, (40, 4): 0.0644},
+    "fused": {(10, 1): 0.0151, (10, 2): 0.0180, (10, 4): 0.0138, (20, 1): 0.0307, (20, 2): 0.0357,
+              (20, 4): 0.0246, (40, 1): 0.0784, (40, 2): 0.0814, (40, 4): 0.0466},
+    "fused_dd": {(10, 1): 0.0152, (10, 2): 0.0127, (10, 4): 0.0117, (20, 1): 0.0309, (20, 2): 0.0256,
+                 (20, 4): 0.0205, (40, 1): 0.0783, (40, 2): 0.0611, (40, 4): 0.0410}}
+# variant -> (Gram precision, phase II, fused Gram columns)
+FIG8_VARIANTS = {"plain": ("f64", "svqb", False), "fused": ("f64", "svqb", True),
+                 "fused_dd": ("dd", "chol", True)}
 
 
 def run_fig8(args, torch, borth, synth):
     """Iterated two-phase scheme to convergence (eps 1e-10) on the shapes of
     the paper's runtime experiment: n = 8e6 rows, k_y in {10, 20, 40} locked
     vectors, n_b in {1, 2, 4} new ones, kappa(X) = 1e6, kappa(X, Y) = 1e12.
-    Variants: binary64 Gram with SVQB, DD Gram with DD Cholesky."""
+    Variants: binary64 Gram with SVQB, a full Gram sweep in every pass
+    ("plain"); the same with each update accumulating the next pass's Gram
+    columns ("fused"); DD Gram with DD Cholesky, fused ("fused_dd")."""
     n = 8_000_000
     rows = []
     for ky in (10, 20, 40):
         for k in (1, 2, 4):
             X, Y = synth.projected_pair_device(n, k, ky, 1e6, 1e12, 7000 + 10 * ky + k)
             Q = torch.empty_like(X)
-            for var, gram, fact in (("f64", "f64", "svqb"), ("dd", "dd", "chol")):
-                res = borth.orthonormalize_iter(X, Y, gram=gram, fact=fact, eps=1e-10, max_iter=10,
-                                                out=Q)
+            for var, (gram, fact, fuse) in FIG8_VARIANTS.items():
+                kw = dict(gram=gram, fact=fact, eps=1e-10, max_iter=10, out=Q, fuse=fuse)
+                res = borth.orthonormalize_iter(X, Y, **kw)
                 torch.cuda.synchronize()
                 ts = []
                 for _ in range(max(1, args.steps)):
                     t0 = time.perf_counter()
-                    res = borth.orthonormalize_iter(X, Y, gram=gram, fact=fact, eps=1e-10,
-                                                    max_iter=10, out=Q)
+                    res = borth.orthonormalize_iter(X, Y, **kw)
                     torch.cuda.synchronize()
                     ts.append(time.perf_counter() - t0)
                 t = sorted(ts)[len(ts) // 2]

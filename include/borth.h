@@ -80,6 +80,7 @@ typedef enum {
 #define BORTH_FLAG_SYNC 1u          /* synchronize before returning */
 #define BORTH_FLAG_PROJECT_ONCE 2u  /* project against Y in the first pass only (P,C,C) */
 #define BORTH_FLAG_GRAPH 4u         /* capture the launch sequence in a cached hipGraph */
+#define BORTH_FLAG_NO_FUSE 8u       /* iterated scheme: a separate Gram sweep in every pass */
 
 typedef struct {
   int gram;       /* borth_gram_prec of pass 1 */
@@ -175,10 +176,16 @@ typedef struct {
  * or after max_iter passes.  Every pass's Gram matrix is taken in
  * opts->gram precision (BORTH_GRAM_F64 or BORTH_GRAM_DD; DD also for the
  * factorization), opts->fact selects Cholesky or SVQB (binary64 only);
- * opts->passes, sched and PROJECT_ONCE are ignored.  Each pass is a Gram
- * sweep over [Y | S_j] and an update sweep writing Q (Q may alias X as in
- * borth_orthonormalize); ky <= 64.  The call synchronizes after every pass
- * to evaluate the stop test.  On return X = Y C + Q R with R, C the products
+ * opts->passes, sched and PROJECT_ONCE are ignored.  The first pass sweeps
+ * the Gram matrix of [Y | X]; Y^T Y is kept for the later passes.  For
+ * narrow blocks (k <= 8, ky + k <= 64, Y dense with ky even) each update
+ * sweep writing Q also accumulates the next pass's Gram columns
+ * [Y | S_{j+1}]^T S_{j+1} (fused operations, Sec. 4.2), so later passes make
+ * one sweep each; otherwise, or with BORTH_FLAG_NO_FUSE in opts->flags, each
+ * later pass sweeps [Y | S_j]^T S_j (NO_FUSE: the whole Gram matrix of
+ * [Y | S_j]) before its update.  Q may alias X as in borth_orthonormalize;
+ * ky <= 64.  The call synchronizes after every pass to evaluate the stop
+ * test.  On return X = Y C + Q R with R, C the products
  * of all passes (device, may be NULL); *it (host, required) reports the
  * passes run and the last pass's norms; info (host, may be NULL) the
  * numerical status.  Returns BORTH_OK whether or not the test was met

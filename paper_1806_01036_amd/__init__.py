@@ -26,7 +26,7 @@ __all__ = [
 GRAM = {"f64": 0, "dd": 1, "split": 2}
 FACT = {"chol": 0, "svqb": 1}
 SCHED = {"auto": 0, "materialize": 1, "recompute": 2}
-FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH = 1, 2, 4
+FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH, FLAG_NO_FUSE = 1, 2, 4, 8
 OK, ERR_ARG, ERR_HIP, ERR_NOMEM, BREAKDOWN, NONFINITE, UNSUPPORTED = range(7)
 
 
@@ -238,10 +238,12 @@ class IterInfo:
 
 
 def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5, out=None,
-                        R=None, C=None, check=True, ctx=None):
+                        R=None, C=None, fuse=True, check=True, ctx=None):
     """Iterated two-phase scheme: passes of projection against Y and
     orthonormalization until ||C_j||_F <= eps and ||R_j - I||_F <= eps (or
-    max_iter passes).  Returns (Q, R, C, IterInfo, Info)."""
+    max_iter passes).  ``fuse=False``: a full Gram sweep in every pass
+    instead of Gram columns accumulated by the previous update.  Returns
+    (Q, R, C, IterInfo, Info)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
     m, k = X.shape
@@ -251,7 +253,7 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
     R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
     if ky and C is None:
         C = torch.empty((ky, k), dtype=torch.float64, device=dev)
-    o = _opts(gram, fact, 1, "materialize", 0.0, 0)
+    o = _opts(gram, fact, 1, "materialize", 0.0, 0 if fuse else FLAG_NO_FUSE)
     it = _lib.borth_iter_info()
     inf = _lib.borth_info()
     st = ctx.lib.borth_orthonormalize_iter(

@@ -606,7 +606,8 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
   // Narrow blocks: each update also accumulates the next pass's Gram columns
   // (the fused operations of Sec. 4.2), so after the first pass no separate
   // sweep over the block is made.
-  const bool fuse = k <= 8 && ky + k <= 64 &&
+  const bool nofuse = (o.flags & BORTH_FLAG_NO_FUSE) != 0;
+  const bool fuse = !nofuse && k <= 8 && ky + k <= 64 &&
                     (ky == 0 || (ky % 2 == 0 && ldy == ky && ((uintptr_t)Y & 15) == 0));
   bool have_gram = false;  // the Gram of this pass's input is already reduced
   for (int p = 0; p < max_iter; ++p) {
@@ -617,10 +618,10 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
       int nwg = 0;
       // Y does not change between passes: after the first, only the columns
       // [Y | S]^T S are swept and Y^T Y stays from the first pass's reduction.
-      const GramLayout Lg = p > 0 ? Lx : L;
+      const GramLayout Lg = (p > 0 && !nofuse) ? Lx : L;
       prof_begin(c, 0);
       HIPCHK(c, launch_gram(src, Lg, dd ? 1 : 0, c->part, c->part_cap, &nwg,
-                            p > 0 ? TuneGram{} : lookup(c->tune_gram, dd ? 1 : 0, kp, ky > 0),
+                            Lg.ty > 0 ? TuneGram{} : lookup(c->tune_gram, dd ? 1 : 0, kp, ky > 0),
                             c->stream),
              "gram");
       prof_end(c, 0);

@@ -77,6 +77,30 @@ def test_iterated_scheme_layouts(m, k, ky, strided, gram, fact):
         assert np.max(np.abs(host(C) - oracle.qr_q(X, Y)["C"])) <= 1e-13
 
 
+@pytest.mark.parametrize("gram,fact", [("f64", "svqb"), ("dd", "chol")])
+def test_iterated_scheme_fused_matches_unfused(gram, fact):
+    """Gram columns accumulated by the update (fused) and a full Gram sweep
+    per pass (unfused) are the same arithmetic up to summation order: same
+    passes, R and C agree to rounding, both reach the same levels."""
+    borth = lib()
+    X, Y = synth.projected_pair(60_000, 2, 20, 1e6, 1e12, 951)
+    out = {}
+    for fuse in (True, False):
+        Q, R, C, it, info = borth.orthonormalize_iter(dev(X), dev(Y), gram=gram, fact=fact,
+                                                      eps=1e-10, max_iter=8, fuse=fuse)
+        assert info.status == 0 and it.converged
+        met = oracle.metrics(host(Q), X, host(R), Y, host(C))
+        note("fuse", fuse, gram, fact, it, met)
+        assert met["rho"] <= 1e-14 and met["omega_y"] <= 1e-14
+        assert met["omega"] <= (20 * 2 * U64 if fact == "svqb" else 1e-14)
+        out[fuse] = (it.passes_run, host(R), host(C))
+    assert out[True][0] == out[False][0]
+    # R factors the part outside span(Y), kappa = 1e6: two valid roundings
+    # differ by up to ~kappa u relative
+    assert np.max(np.abs(out[True][1] - out[False][1])) <= 1e3 * 1e6 * U64 * np.max(np.abs(out[False][1]))
+    assert np.max(np.abs(out[True][2] - out[False][2])) <= 1e-13
+
+
 def test_iterated_scheme_dd_needs_fewer_passes():
     """The point of the paper's DD variant: the DD projection resolves X's
     tiny component outside span(Y) in one pass, so the scheme converges in
