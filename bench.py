@@ -406,12 +406,56 @@ def run_fig8(args, torch, borth, synth):
             "data": "synthetic", "n_gpus": 1, "results": rows}
 
 
+def _orth_levels(borth, Q, Y, k, ky):
+    """||Q^T Q - I||_F and ||Y^T Q||_F from the library's DD Gram of [Y | Q]."""
+    ghi, glo = borth.gram(Q, A=Y, prec="dd") if ky else borth.gram(Q, prec="dd")
+    g = ghi.cpu().numpy() + glo.cpu().numpy()
+    om = float(np.linalg.norm(g[ky:, ky:] - np.eye(k)))
+    omy = float(np.linalg.norm(g[:ky, ky:])) if ky else 0.0
+    return om, omy
+
+
+def run_fig7(args, torch, borth, synth):
+    """One two-phase pass (projection against Y, then orthonormalization) on
+    the shape of the paper's accuracy experiment (Fig. 7): n = 1000 rows,
+    k_y = 20 locked vectors, n_b = 4 new ones.  Left: ||Y^T Q|| against
+    kappa(X, Y) at kappa(X) in {1, 1e3}; right: ||Q^T Q - I|| against kappa(X)
+    at kappa(X, Y) = kappa(X).  Variants: binary64 Gram with SVQB; DD Gram,
+    DD Cholesky and DD update."""
+    n, ky, k = 1000, 20, 4
+    variants = {"f64_svqb": ("f64", "svqb"), "dd_chol": ("dd", "chol")}
+    rows = []
+
+    def one(kx, kxy, seed):
+        X, Y = synth.projected_pair_device(n, k, ky, kx, kxy, seed)
+        for var, (gram, fact) in variants.items():
+            Q, R, C, info = borth.orthonormalize(X, Y, gram=gram, fact=fact, passes=1, check=False)
+            torch.cuda.synchronize()
+            om, omy = _orth_levels(borth, Q, Y, k, ky)
+            r = dict(kappa_x=kx, kappa_xy=kxy, variant=var, status=info.status, omega=om,
+                     omega_y=omy)
+            log(r)
+            rows.append(r)
+
+    for kx in (1.0, 1e3):
+        for e in range(0, 19, 3):
+            kxy = 10.0 ** e
+            if kxy >= kx:
+                one(kx, kxy, 4000 + e + (0 if kx == 1.0 else 100))
+    for e in range(0, 13, 3):
+        kx = 10.0 ** e
+        one(kx, kx, 4500 + e)
+    return {"workload": "one project / orthonormalize pass, n = 1000, k_y = 20, n_b = 4 "
+                        "(the paper's accuracy experiment)",
+            "data": "synthetic", "n_gpus": 1, "results": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "fig8"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "fig7", "fig8"])
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--blocks", type=int, default=256)
@@ -431,7 +475,7 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    fn = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fig8": run_fig8}.get(args.workload)
+    fn = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fig7": run_fig7, "fig8": run_fig8}.get(args.workload)
     if fn is None:
         raise SystemExit(f"workload {args.workload} not available")
     out = fn(args, torch, borth, synth)

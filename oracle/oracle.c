@@ -600,10 +600,16 @@ static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
 
 /* One DD pass: the same steps with every quantity in DD -- C by Dot2, Xt kept
  * as DD, M from the DD Xt, DD Cholesky and DD inverse, Q = Xt Z rounded to
- * binary64 once.  R and C are returned as hi/lo pairs. */
+ * binary64 once.  R and C are returned as hi/lo pairs.
+ *
+ * corrected: the projection coefficients are D = 2C - S C with S = Y^T Y (by
+ * Dot2), the first-order expansion of (Y^T Y)^{-1} Y^T X, so that the part of
+ * Xt left in span(Y) is O(||S - I||^2) instead of O(||S - I||) when the stored
+ * Y is orthonormal only to binary64 accuracy; D replaces C in Xt and in the
+ * returned coefficients.  For an exactly orthonormal Y, D = C. */
 static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
                    const double* Y, int64_t ldy, double* Q, int64_t ldq,
-                   dd* R, dd* C) {
+                   dd* R, dd* C, int corrected) {
   const int64_t np = npart(m);
   if (ky > 0) {
     for (int l = 0; l < ky; ++l)
@@ -613,6 +619,26 @@ static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
           s = dd_add(s, dot2_rows(pbeg(m, np, b), pbeg(m, np, b + 1), Y + l, ldy, X + j, ldx));
         C[(size_t)l * k + j] = s;
       }
+  }
+  if (ky > 0 && corrected) {
+    dd* S = (dd*)malloc(sizeof(dd) * ((size_t)ky * ky + 1));
+    for (int l = 0; l < ky; ++l)
+      for (int q = 0; q < ky; ++q) {
+        dd s = {0, 0};
+        for (int64_t b = 0; b < np; ++b)
+          s = dd_add(s, dot2_rows(pbeg(m, np, b), pbeg(m, np, b + 1), Y + l, ldy, Y + q, ldy));
+        S[(size_t)l * ky + q] = s;
+      }
+    dd* D = (dd*)malloc(sizeof(dd) * ((size_t)ky * k + 1));
+    for (int l = 0; l < ky; ++l)
+      for (int j = 0; j < k; ++j) {
+        dd s = dd_add(C[(size_t)l * k + j], C[(size_t)l * k + j]);
+        for (int q = 0; q < ky; ++q) s = dd_sub(s, dd_mul(S[(size_t)l * ky + q], C[(size_t)q * k + j]));
+        D[(size_t)l * k + j] = s;
+      }
+    memcpy(C, D, sizeof(dd) * (size_t)ky * k);
+    free(D);
+    free(S);
   }
   dd* xt = (dd*)malloc(sizeof(dd) * ((size_t)m * k + 1));
 #pragma omp parallel for schedule(static)
@@ -661,13 +687,14 @@ static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
 
 /* O2 driver: `passes` repetitions of (phase I if ky > 0 and (pass == 0 or
  * project_each_pass), then phase II).  The first pass runs in DD when dd_first
- * is set, later passes in binary64 -- the iterated two-phase scheme of
+ * is set (with the corrected coefficients of pass_dd when dd_corrected is
+ * set), later passes in binary64 -- the iterated two-phase scheme of
  * Sec. 4.2 cut to `passes` iterations (passes = 2 is CholQR2).
  * Outputs: Q (m x k), R = R_p ... R_1 (k x k, hi/lo), C = total projection
  * coefficients (ky x k, hi/lo) with X = Y C + Q R.  Returns 0, or
  * 100 * (pass + 1) + pivot on breakdown. */
 int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
-                    const double* Y, int64_t ldy, int dd_first, int passes,
+                    const double* Y, int64_t ldy, int dd_first, int dd_corrected, int passes,
                     int project_each_pass, double* Q, int64_t ldq, double* rhi,
                     double* rlo, double* chi, double* clo) {
   const size_t n = (size_t)k * k;
@@ -688,7 +715,7 @@ int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
     const int kyp = (ky > 0 && (p == 0 || project_each_pass)) ? ky : 0;
     int info;
     if (p == 0 && dd_first) {
-      info = pass_dd(m, k, cur, k, kyp, Y, ldy, cur, k, rp, cp);
+      info = pass_dd(m, k, cur, k, kyp, Y, ldy, cur, k, rp, cp, dd_corrected);
     } else {
       info = pass_f64(m, k, cur, k, kyp, Y, ldy, cur, k, rf, cf);
       for (size_t e = 0; e < n; ++e) rp[e] = dd_from(rf[e]);

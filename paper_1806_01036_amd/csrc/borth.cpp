@@ -78,7 +78,7 @@ borth_status ensure_status(borth_ctx c, int n) {
 
 // Small-matrix workspace layout (doubles), for W = ky + k <= 128, kp <= 64.
 struct WsLayout {
-  int64_t g_hi, g_lo, zp[3], cp[3], rtot, ctot, zu, cu, total;
+  int64_t g_hi, g_lo, zp[3], cp[3], rtot, ctot, zu, cu, zplo, cplo, total;
 };
 WsLayout ws_layout() {
   WsLayout w;
@@ -91,6 +91,8 @@ WsLayout ws_layout() {
   w.ctot = o; o += 2 * 64 * 64;
   w.zu = o; o += 64 * 64;
   w.cu = o; o += 64 * 64;
+  w.zplo = o; o += 64 * 64;  // low words of Z and C for a DD update
+  w.cplo = o; o += 64 * 64;
   w.total = o;
   return w;
 }
@@ -161,6 +163,9 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     HIPCHK(c, launch_reduce(L1, dd ? 1 : 0, c->part, nwg, ws + W.g_hi, dd ? ws + W.g_lo : nullptr, st),
            "reduce");
   }
+  // One DD pass on a narrow block: the update runs in DD as well (the
+  // factor then also gives the low words of Z and C).
+  const bool dd_update = dd && passes == 1 && a.dt == BORTH_F64 && a.k <= 8;
   auto factor = [&](int pass, int kyp_pass, const double* ghi, const double* glo, bool ddm,
                     double shrel, bool last) -> borth_status {
     FactorArgs f;
@@ -181,6 +186,10 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     f.status = c->status;
     f.R_out = last ? a.R : nullptr;
     f.C_out = (last && hasy) ? a.C : nullptr;
+    if (dd_update && pass == 0) {
+      f.Zplo = ws + W.zplo;
+      f.Cplo = ws + W.cplo;
+    }
     HIPCHK(c, launch_factor(f, st), "factor");
     return BORTH_OK;
   };
@@ -201,6 +210,10 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     u.src = s1;
     u.C1 = ws + W.cp[0];
     u.Z1 = ws + W.zp[0];
+    if (dd_update) {
+      u.C1lo = ws + W.cplo;
+      u.Z1lo = ws + W.zplo;
+    }
     u.dense = a.o.fact == BORTH_SVQB;
     u.Q = a.Q;
     u.ldq = a.ldq;
@@ -610,6 +623,8 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
   const bool fuse = !nofuse && k <= 8 && ky + k <= 64 &&
                     (ky == 0 || (ky % 2 == 0 && ldy == ky && ((uintptr_t)Y & 15) == 0));
   bool have_gram = false;  // the Gram of this pass's input is already reduced
+  // DD on a narrow block: the updates run in DD as well
+  const bool dd_update = dd && k <= 8;
   for (int p = 0; p < max_iter; ++p) {
     const double* S = p == 0 ? X : Q;
     const int64_t lds_ = p == 0 ? ldx : ldq;
@@ -646,6 +661,10 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
     f.Ctot = ws + W.ctot;
     f.status = c->status;
     f.conv = conv;
+    if (dd_update) {
+      f.Zplo = ws + W.zplo;
+      f.Cplo = ws + W.cplo;
+    }
     HIPCHK(c, launch_factor(f, c->stream), "factor");
     UpdateArgs u;
     memset(&u, 0, sizeof(u));
@@ -655,6 +674,10 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
     u.dense = o.fact == BORTH_SVQB;
     u.Q = Q;
     u.ldq = ldq;
+    if (dd_update) {
+      u.C1lo = ws + W.cplo;
+      u.Z1lo = ws + W.zplo;
+    }
     if (fuse) {
       u.partials = c->part;
       u.partial_cap_doubles = c->part_cap;

@@ -107,7 +107,10 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
   const bool first = (a.pass == 0);
 
   auto zero_out = [&]() {
-    for (int e = tid; e < kp * kp; e += NT) a.Zp[e] = 0.0;
+    for (int e = tid; e < kp * kp; e += NT) {
+      a.Zp[e] = 0.0;
+      if (a.Zplo) a.Zplo[e] = 0.0;
+    }
   };
   // A previous pass already failed: leave a zero transform and stop.
   if (a.status[0] != 0) {
@@ -165,6 +168,10 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
         const int r = e / k, l = e - r * k;
         s_r1[0][r * LD + l] = dreg[t].hi;
         s_r1[1][r * LD + l] = dreg[t].lo;
+        if (a.Cplo) {  // DD update: the corrected coefficients, read back below
+          a.Cp[r * kp + l] = dreg[t].hi;
+          a.Cplo[r * kp + l] = dreg[t].lo;
+        }
       }
     }
     __syncthreads();
@@ -306,14 +313,18 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
       const int i = ti + T * p, l = tj + T * q;
       if (i < k && l < k) {
         x[p][q] = A::mul(x[p][q], rs[p]);
-        const double z = (l < i) ? x[p][q].hi : (l == i ? rs[p].hi : 0.0);
-        s_r1[0][l * LD + i] = z;  // Z[l][i]
+        const dd_t z = (l < i) ? x[p][q] : (l == i ? rs[p] : dd_from(0.0));
+        s_r1[0][l * LD + i] = z.hi;  // Z[l][i]
+        s_r1[1][l * LD + i] = z.lo;
         if (a.Rp_out) a.Rp_out[i * k + l] = l >= i ? x[p][q].hi : 0.0;
       }
     }
+  // projection coefficients of this pass: C, or for the DD update the
+  // corrected D written above
   for (int e = tid; e < ky * k; e += NT) {
     const int r = e / k, l = e - r * k;
-    const dd_t cv = ld_g(a.G_hi, a.G_lo, r * W + ky + l);
+    const dd_t cv = a.Cplo ? dd_make(a.Cp[r * kp + l], a.Cplo[r * kp + l])
+                           : ld_g(a.G_hi, a.G_lo, r * W + ky + l);
     s_r0[0][r * LD + l] = cv.hi;
     s_r0[1][r * LD + l] = cv.lo;
   }
@@ -322,12 +333,17 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
     const int i = e / kp, l = e - i * kp;
     const double z = (i < k && l < k) ? s_r1[0][i * LD + l] : 0.0;
     a.Zp[e] = z;
+    if (a.Zplo) a.Zplo[e] = (i < k && l < k) ? s_r1[1][i * LD + l] : 0.0;
     if (a.Z_out && i < k && l < k) a.Z_out[i * k + l] = z;
   }
-  // C of this pass, rounded, for the update (S - Y C) Z
+  // C of this pass, rounded, for the update (S - Y C) Z (DD update: and the
+  // rounding remainder)
   for (int e = tid; e < ky * kp; e += NT) {
     const int r = e / kp, j = e - r * kp;
-    a.Cp[e] = j < k ? s_r0[0][r * LD + j] + s_r0[1][r * LD + j] : 0.0;
+    const double h = s_r0[0][r * LD + (j < k ? j : 0)], lo = s_r0[1][r * LD + (j < k ? j : 0)];
+    const double cr = j < k ? h + lo : 0.0;
+    a.Cp[e] = cr;
+    if (a.Cplo) a.Cplo[e] = j < k ? (h - cr) + lo : 0.0;
   }
 
   // Totals: X = Y C_tot + X_cur R_tot.  After this pass

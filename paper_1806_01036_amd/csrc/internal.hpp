@@ -126,6 +126,11 @@ struct FactorArgs {
   double* Z_out;            // optional unpadded Z (k x k)
   double* Rp_out;           // optional this-pass R (k x k)
   double* conv;             // optional: ||C_p||_F and ||R_p - I||_F of this pass
+  // DD update (Cholesky in DD only): the low words of Z_p and of the
+  // projection coefficients, which are then D = 2C - S C (C corrected to
+  // first order for Y^T Y != I) instead of C, in C_p and in the totals.
+  double* Zplo;             // kp x kp, or null
+  double* Cplo;             // ky x kp, or null (set together with Zplo)
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 // One workgroup per entry of the device table `tab` (n entries, all with
@@ -144,6 +149,7 @@ struct UpdateArgs {
   // (row-major, zero padded beyond k).
   const double* C1; const double* Z1;
   const double* C2; const double* Z2;
+  const double* C1lo; const double* Z1lo;  // DD stage 1 (narrow kernel only), or null
   int two_stage;
   int dense;                           // Z dense (SVQB)
   double* Q; int64_t ldq;
@@ -175,6 +181,8 @@ struct UpdDev {
   const double* Z1;
   const double* C2;
   const double* Z2;
+  const double* C1lo;  // low words of C1 and Z1: DD arithmetic (narrow kernel), or null
+  const double* Z1lo;
   int wg0, nwg;
 };
 // Kernel class of an update launch.

@@ -69,6 +69,11 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.Z1 = a.Z1;
   d.C2 = a.C2;
   d.Z2 = a.Z2;
+  d.C1lo = a.C1lo;
+  d.Z1lo = a.Z1lo;
+  // DD arithmetic exists in the narrow kernel only
+  if ((a.C1lo || a.Z1lo) && (a.two_stage || a.src.x_f32 || !update_narrow_ok(L.k, L.ky, K)))
+    return hipErrorInvalidValue;
   if (!a.partials && !a.two_stage && !a.src.x_f32 && a.Q && update_narrow_ok(L.k, L.ky, K)) {
     a.nwg = 0;
     return launch_update_narrow(d, K, st);

@@ -20,7 +20,9 @@
 //  * the next panel's loads are issued before the current panel is computed,
 //    so every wave keeps a panel in flight while it works;
 //  * C and Z are the same for every lane and are read through the scalar
-//    cache;
+//    cache; given their low words (the DD variant of Sec. 4.2, extended
+//    precision throughout the orthogonalization), the projection and the
+//    product with Z run with the Dot2 step and the result is rounded once;
 //  * the fused Gram switches to one column per lane: T goes next to Y in the
 //    panel's LDS rows and lane c accumulates column c of [Y | T] times each
 //    column of T over the panel's rows (in several row phases when the block
@@ -80,6 +82,9 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
   typedef const double __attribute__((address_space(4)))* cptr;
   const cptr Cg = (cptr)a.C1;
   const cptr Zg = (cptr)a.Z1;
+  const cptr Clg = (cptr)a.C1lo;  // DD arithmetic when the low words are given
+  const cptr Zlg = (cptr)a.Z1lo;
+  const bool pdd = a.C1lo != nullptr && a.Z1lo != nullptr;
   double BORTH_GLOBAL* __restrict__ Qg = gmem(a.Q);
   const int dense = a.dense;
   constexpr int NY = KYB > 0 ? KYB : 1;
@@ -181,26 +186,61 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
   // T = S - Y C (one fused multiply-add per product term, S first), Q = T Z;
   // with the fused Gram, T joins the panel and is accumulated column-wise.
   auto compute_store = [&](const double* xs, int64_t row0, int nrows) {
-    double t[KN];
-#pragma unroll
-    for (int j = 0; j < KN; ++j) t[j] = xs[j];
-    if (KYB > 0) {
-      const double* yrow = pan + lane * SP;
-#pragma unroll 4
-      for (int c = 0; c < ky; ++c) {
-        const double y = yrow[c];
-#pragma unroll
-        for (int j = 0; j < KN; ++j) t[j] = __builtin_fma(y, -Cg[c * kp + j], t[j]);
-      }
-    }
     double qv[KN];
+    if (!pdd) {
+      double t[KN];
 #pragma unroll
-    for (int j = 0; j < KN; ++j) {
-      double s = 0.0;
+      for (int j = 0; j < KN; ++j) t[j] = xs[j];
+      if (KYB > 0) {
+        const double* yrow = pan + lane * SP;
+#pragma unroll 4
+        for (int c = 0; c < ky; ++c) {
+          const double y = yrow[c];
 #pragma unroll
-      for (int l = 0; l < KN; ++l)
-        if (l <= j || dense) s = __builtin_fma(t[l], Zg[l * kp + j], s);  // Z upper triangular unless dense
-      qv[j] = s;
+          for (int j = 0; j < KN; ++j) t[j] = __builtin_fma(y, -Cg[c * kp + j], t[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KN; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < KN; ++l)
+          if (l <= j || dense) s = __builtin_fma(t[l], Zg[l * kp + j], s);  // Z upper triangular unless dense
+        qv[j] = s;
+      }
+    } else {
+      // DD: T = S - Y (C_hi + C_lo) with the Dot2 step (T kept as a pair),
+      // then Q = T (Z_hi + Z_lo) likewise, rounded once at the end
+      double ts[KN], te[KN];
+#pragma unroll
+      for (int j = 0; j < KN; ++j) {
+        ts[j] = xs[j];
+        te[j] = 0.0;
+      }
+      if (KYB > 0) {
+        const double* yrow = pan + lane * SP;
+#pragma unroll 2
+        for (int c = 0; c < ky; ++c) {
+          const double y = yrow[c];
+#pragma unroll
+          for (int j = 0; j < KN; ++j) {
+            dot2_step(ts[j], te[j], y, -Cg[c * kp + j]);
+            te[j] = __builtin_fma(y, -Clg[c * kp + j], te[j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KN; ++j) {
+        double s = 0.0, e = 0.0;
+#pragma unroll
+        for (int l = 0; l < KN; ++l)
+          if (l <= j || dense) {
+            const double zh = Zg[l * kp + j];
+            dot2_step(s, e, ts[l], zh);
+            e = __builtin_fma(ts[l], Zlg[l * kp + j], __builtin_fma(te[l], zh, e));
+          }
+        qv[j] = s + e;
+      }
     }
     if (lane < nrows) {
 #pragma unroll

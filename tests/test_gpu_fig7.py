@@ -1,0 +1,95 @@
+"""GPU tests on the shape of the paper's accuracy experiment (Sec. 4.2,
+Fig. 7): one two-phase pass -- projection against the locked vectors Y,
+then orthonormalization -- of n = 1000 rows, k_y = 20 locked and n_b = 4 new
+vectors, against the condition of X and the closeness of X to span(Y).
+
+The paper's claims checked here (levels measured by the oracle's exact
+metrics on the host):
+  * binary64 SVQB loses orthogonality like kappa(X)^2 u;
+  * with DD kernels throughout (Gram, factor, projection and update), the
+    orthogonality stays at the rounding level of the stored result up to
+    kappa(X) = 1e6;
+  * DD improves the orthogonality against Y by at least two orders of
+    magnitude, and the binary64 loss grows linearly with kappa(X, Y).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import U64, dev, host, lib, note
+
+pytestmark = pytest.mark.gpu
+
+N, KY, K = 1000, 20, 4
+
+
+def one_pass(borth, X, Y, variant):
+    gram, fact = {"f64": ("f64", "svqb"), "dd": ("dd", "chol")}[variant]
+    Q, R, C, info = borth.orthonormalize(dev(X), dev(Y), gram=gram, fact=fact, passes=1)
+    assert info.status == 0
+    met = oracle.metrics(host(Q), X, host(R), Y, host(C))
+    note(variant, met)
+    return met
+
+
+def test_fig7_orthogonality_against_y():
+    """kappa(X) = 1, kappa(X, Y) in {1e3, 1e6}."""
+    borth = lib()
+    lv = {}
+    for kxy in (1e3, 1e6):
+        X, Y = synth.projected_pair(N, K, KY, 1.0, kxy, 7100 + int(np.log10(kxy)))
+        lv[kxy] = {v: one_pass(borth, X, Y, v)["omega_y"] for v in ("f64", "dd")}
+        note("kappa(X, Y)", kxy, lv[kxy])
+        assert lv[kxy]["dd"] * 100 <= lv[kxy]["f64"]
+        assert lv[kxy]["dd"] <= 1e-15
+    slope = lv[1e6]["f64"] / lv[1e3]["f64"]
+    assert 1e2 <= slope <= 1e4  # linear in kappa(X, Y)
+
+
+def test_fig7_orthogonality_of_q():
+    """kappa(X, Y) = kappa(X) in {1e3, 1e6}."""
+    borth = lib()
+    om = {}
+    for kx in (1e3, 1e6):
+        X, Y = synth.projected_pair(N, K, KY, kx, kx, 7200 + int(np.log10(kx)))
+        om[kx] = {v: one_pass(borth, X, Y, v) for v in ("f64", "dd")}
+        f64 = om[kx]["f64"]["omega"]
+        assert 1e-3 * kx ** 2 * U64 <= f64 <= 1e3 * kx ** 2 * U64
+        dd = om[kx]["dd"]
+        assert dd["omega"] <= 1e-15 and dd["omega_y"] <= 1e-15 and dd["rho"] <= 1e-15
+    assert 1e4 <= om[1e6]["f64"]["omega"] / om[1e3]["f64"]["omega"] <= 1e8  # kappa^2
+
+
+def test_fig7_dd_one_pass_matches_iterated_levels():
+    """One DD pass reaches what the iterated binary64 scheme needs several
+    passes for (kappa(X) = 1e3, kappa(X, Y) = 1e6)."""
+    borth = lib()
+    X, Y = synth.projected_pair(N, K, KY, 1e3, 1e6, 7300)
+    dd = one_pass(borth, X, Y, "dd")
+    assert dd["omega"] <= 1e-15 and dd["omega_y"] <= 1e-15 and dd["rho"] <= 1e-15
+    *_, it, info = borth.orthonormalize_iter(dev(X), dev(Y), gram="f64", fact="svqb", eps=1e-10,
+                                             max_iter=10)
+    note("binary64 iterated passes", it.passes_run)
+    assert it.converged and it.passes_run >= 2
+
+
+@pytest.mark.parametrize("kx,kxy", [(1.0, 1e3), (1e3, 1e3), (10.0, 1e5)])
+def test_fig7_dd_pass_vs_oracle(kx, kxy):
+    """Parity of the DD pass (DD Gram, DD Cholesky, corrected projection
+    coefficients, DD update rounded once) with the oracle's DD steps.  Here
+    kappa(X)^2 kappa(X, Y)^2 u_DD << u, so both are the binary64 rounding of
+    the same exact quantities up to a few ulps."""
+    borth = lib()
+    X, Y = synth.projected_pair(N, K, KY, kx, kxy, 7400 + int(np.log10(kx * kxy)))
+    Q, R, C, info = borth.orthonormalize(dev(X), dev(Y), gram="dd", fact="chol", passes=1)
+    assert info.status == 0
+    o = oracle.cholqr_steps(X, Y, dd_first=True, dd_corrected=True, passes=1)
+    assert o["info"] == 0
+    dq = np.max(np.abs(host(Q) - o["Q"])) / np.max(np.abs(o["Q"]))
+    Ro = o["R_hi"] + o["R_lo"]
+    dr = np.max(np.abs(host(R) - Ro)) / np.max(np.abs(Ro))
+    Co = o["C_hi"] + o["C_lo"]
+    dc = np.max(np.abs(host(C) - Co)) / np.max(np.abs(Co))
+    note("dd pass vs oracle", kx, kxy, dq, dr, dc)
+    assert dq <= 8 * U64 and dr <= 8 * U64 and dc <= 8 * U64

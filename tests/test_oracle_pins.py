@@ -221,6 +221,35 @@ def test_projection_hadamard_exact():
         assert np.array_equal(s["Q"], H) and np.array_equal(s["C_hi"], o["C"])
 
 
+def test_corrected_projection_exact_basis_is_plain():
+    """Y exactly orthonormal (Hadamard columns): S = Y^T Y = I exactly, so the
+    corrected coefficients D = 2C - S C equal C and the pass is unchanged."""
+    Y = synth.hadamard_columns(5, [3, 9, 17, 30])
+    X = synth.svd_matrix(1024, 3, 1e4, 61) + Y @ np.array([[1.0, -2.0, 0.5]] * 4)
+    a = oracle.cholqr_steps(X, Y, dd_first=True, passes=1)
+    b = oracle.cholqr_steps(X, Y, dd_first=True, passes=1, dd_corrected=True)
+    for key in ("Q", "R_hi", "R_lo", "C_hi", "C_lo"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_corrected_projection_second_order():
+    """Y orthonormal only to ||S - I|| ~ 2e-7 (columns scaled by 1 + e_i):
+    the plain projection leaves O(||S - I||) of X in span(Y), amplified by
+    kappa(X, Y) in Q; the corrected one leaves O(||S - I||^2)."""
+    X, Y0 = synth.projected_pair(4000, 2, 6, 1.0, 1e3, 62)
+    Y = Y0 * (1.0 + 1e-7 * np.arange(1, 7))[None, :]
+    a = oracle.cholqr_steps(X, Y, dd_first=True, passes=1)
+    b = oracle.cholqr_steps(X, Y, dd_first=True, passes=1, dd_corrected=True)
+    wa = np.linalg.norm(Y.T @ a["Q"])
+    wb = np.linalg.norm(Y.T @ b["Q"])
+    assert wa >= 1e-5       # ~ ||S - I|| |C| kappa(X, Y)
+    assert wb <= 1e-8       # ~ ||S - I||^2 |C| kappa(X, Y), plus rounding
+    # both decompose X: X = Y C + Q R
+    for o in (a, b):
+        res = X - Y @ (o["C_hi"] + o["C_lo"]) - o["Q"] @ (o["R_hi"] + o["R_lo"])
+        assert np.linalg.norm(res) <= 1e-13 * np.linalg.norm(X)
+
+
 # --------------------------------------------------------------------------
 # LAPACK special cases and generator closed forms
 
