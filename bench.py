@@ -360,9 +360,10 @@ FIG8_PAPER = {
               (20, 4): 0.0246, (40, 1): 0.0784, (40, 2): 0.0814, (40, 4): 0.0466},
     "fused_dd": {(10, 1): 0.0152, (10, 2): 0.0127, (10, 4): 0.0117, (20, 1): 0.0309, (20, 2): 0.0256,
                  (20, 4): 0.0205, (40, 1): 0.0783, (40, 2): 0.0611, (40, 4): 0.0410}}
-# variant -> (Gram precision, phase II, fused Gram columns)
+# variant -> (Gram precision, phase II, fused Gram columns); "fused_dd" is the
+# paper's DD project / SVQB, "fused_dd_chol" the same with DD Cholesky
 FIG8_VARIANTS = {"plain": ("f64", "svqb", False), "fused": ("f64", "svqb", True),
-                 "fused_dd": ("dd", "chol", True)}
+                 "fused_dd": ("dd", "svqb", True), "fused_dd_chol": ("dd", "chol", True)}
 
 
 def run_fig8(args, torch, borth, synth):
@@ -371,7 +372,8 @@ def run_fig8(args, torch, borth, synth):
     vectors, n_b in {1, 2, 4} new ones, kappa(X) = 1e6, kappa(X, Y) = 1e12.
     Variants: binary64 Gram with SVQB, a full Gram sweep in every pass
     ("plain"); the same with each update accumulating the next pass's Gram
-    columns ("fused"); DD Gram with DD Cholesky, fused ("fused_dd")."""
+    columns ("fused"); DD Gram with DD SVQB, fused ("fused_dd"), and with DD
+    Cholesky ("fused_dd_chol")."""
     n = 8_000_000
     rows = []
     for ky in (10, 20, 40):
@@ -397,7 +399,7 @@ def run_fig8(args, torch, borth, synth):
                 omy = float(np.linalg.norm(g[:ky, ky:] + lo[:ky, ky:]))
                 r = dict(ky=ky, nb=k, variant=var, passes=it.passes_run, converged=it.converged,
                          s_per_vector=t / k, omega=om, omega_y=omy,
-                         paper_haswell_s_per_vector=FIG8_PAPER[var][(ky, k)])
+                         paper_haswell_s_per_vector=FIG8_PAPER[var.replace("_chol", "")][(ky, k)])
                 log(r)
                 rows.append(r)
             del X, Y, Q
@@ -423,7 +425,7 @@ def run_fig7(args, torch, borth, synth):
     at kappa(X, Y) = kappa(X).  Variants: binary64 Gram with SVQB; DD Gram,
     DD Cholesky and DD update."""
     n, ky, k = 1000, 20, 4
-    variants = {"f64_svqb": ("f64", "svqb"), "dd_chol": ("dd", "chol")}
+    variants = {"f64_svqb": ("f64", "svqb"), "dd_svqb": ("dd", "svqb"), "dd_chol": ("dd", "chol")}
     rows = []
 
     def one(kx, kxy, seed):

@@ -132,7 +132,8 @@ borth_status borth_gram(borth_ctx ctx, int64_t m, int ka, const double* A, int64
  *     C = G_YX,  M = G_XX - 2 C^T C + C^T G_YY C  (= Xt^T Xt exactly),
  * add shift * trace(M) to the diagonal if shift > 0, and factor M in DD
  * (G_lo != NULL) or binary64: Cholesky M = R^T R, Z = R^{-1} (upper), or SVQB
- * (binary64 only) Z = M^{-1/2}, R = M^{1/2}.  Outputs (device, may be NULL):
+ * Z = M^{-1/2}, R = M^{1/2} (Jacobi in the same precision; eigenvalues below
+ * 2^-52 lambda_max, DD: 2^-104 lambda_max, lifted to that floor).  Outputs (device, may be NULL):
  * Z (k x k), R (k x k), C (ky x k).  info (host, may be NULL) receives the
  * breakdown pivot; passing it synchronizes. */
 borth_status borth_factor(borth_ctx ctx, int ky, int k, const double* G_hi,
@@ -175,7 +176,7 @@ typedef struct {
  *     ||C_j||_F <= eps  and  ||R_j - I||_F <= eps,
  * or after max_iter passes.  Every pass's Gram matrix is taken in
  * opts->gram precision (BORTH_GRAM_F64 or BORTH_GRAM_DD; DD also for the
- * factorization), opts->fact selects Cholesky or SVQB (binary64 only);
+ * factorization), opts->fact selects Cholesky or SVQB;
  * opts->passes, sched and PROJECT_ONCE are ignored.  The first pass sweeps
  * the Gram matrix of [Y | X]; Y^T Y is kept for the later passes.  For
  * narrow blocks (k <= 8, ky + k <= 64, Y dense with ky even) each update

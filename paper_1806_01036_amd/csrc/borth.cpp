@@ -445,7 +445,6 @@ borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const 
   if (!c) return BORTH_ERR_ARG;
   if (k < 1 || k > 64 || ky < 0 || ky > 64 || !G_hi) return fail_arg(c, "shape");
   if (fact != BORTH_CHOL && fact != BORTH_SVQB) return fail_arg(c, "fact");
-  if (fact == BORTH_SVQB && G_lo) return fail_arg(c, "SVQB runs in binary64 (pass G_lo = NULL)");
   hipSetDevice(c->device);
   c->cur = c->stream;
   const WsLayout W = ws_layout();
@@ -527,10 +526,6 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
   if (o.gram == BORTH_GRAM_SPLIT_BF16 && (dt != BORTH_F32 || ky > 0))
     return fail_arg(c, "split mode needs fp32 X and no locked basis");
   if (o.gram != BORTH_GRAM_SPLIT_BF16 && dt == BORTH_F32) return fail_arg(c, "fp32 X needs the split mode");
-  if (o.fact == BORTH_SVQB && o.gram == BORTH_GRAM_DD) {
-    c->err = "SVQB runs in binary64 in this build";
-    return BORTH_ERR_UNSUPPORTED;
-  }
   if ((const void*)Q == X) {
     if (dt != BORTH_F64 || ldq != ldx) return fail_arg(c, "aliasing");
     if (o.sched == BORTH_SCHED_RECOMPUTE) return fail_arg(c, "recompute schedule cannot run in place");
@@ -597,10 +592,6 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
   if (!(eps >= 0.0) || max_iter < 1 || max_iter > 64) return fail_arg(c, "eps / max_iter");
   if (o.gram != BORTH_GRAM_F64 && o.gram != BORTH_GRAM_DD) return fail_arg(c, "opts.gram");
   if (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB) return fail_arg(c, "opts.fact");
-  if (o.fact == BORTH_SVQB && o.gram == BORTH_GRAM_DD) {
-    c->err = "SVQB runs in binary64 in this build";
-    return BORTH_ERR_UNSUPPORTED;
-  }
   hipSetDevice(c->device);
   c->cur = c->stream;
   const bool dd = o.gram == BORTH_GRAM_DD;

@@ -11,7 +11,7 @@
 //   barrier per eliminated column (details at the kernel).
 //   Breakdown rule: unpivoted; a pivot that is not > 0 or not finite stops
 //   the factorization and reports its 1-based index (LAPACK potrf style).
-// svqb_kernel (binary64): cyclic Jacobi with parallel round-robin rotations,
+// svqb_kernel (binary64), svqb_dd_kernel (DD): cyclic Jacobi with parallel round-robin rotations,
 //   Z = U L^{-1/2} U^T (the Procrustes-optimal, symmetric form) and
 //   R = U L^{1/2} U^T; eigenvalues below tau * lambda_max (tau = 2^-52) are
 //   lifted to tau * lambda_max (rank-deficient blocks stay finite).
@@ -695,6 +695,342 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
   if (tid == 0) a.status[3] = a.pass + 1;
 }
 
+// ---------------------------------------------------------------------------
+// SVQB in DD (the DD variant of Sec. 4.2 with SVQB as phase II): the
+// projected Gram matrix, the cyclic Jacobi eigensolver, Z = U L^{-1/2} U^T
+// and R = U L^{1/2} U^T all in DD; eigenvalues below 2^-104 lambda_max are
+// lifted to that floor.  The same round-robin structure as svqb_kernel; a
+// pair is rotated when |a_pq| > 2^-105 sqrt(|a_pp a_qq|).  With the low words
+// of Z and C requested (DD update), the projection coefficients are the
+// corrected D = 2C - S C, as in chol_kernel.
+__global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
+                                                      const FactorArgs* __restrict__ tab) {
+  using A = Ar<true>;
+  const FactorArgs a = tab ? tab[blockIdx.x] : one;
+  constexpr int LD = 65;
+  constexpr int NE = (64 * 64 + NTF - 1) / NTF;  // per-thread share of a 64 x 64 block
+  __shared__ double sMh[64 * LD], sMl[64 * LD], sVh[64 * LD], sVl[64 * LD];
+  __shared__ double rch[32], rcl[32], rsh[32], rsl[32];
+  __shared__ int sp[32], sq[32];
+  __shared__ double lh[64], ll[64], lrh[64], lrl[64], lsh[64], lsl[64];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x;
+  const int k = a.k, ky = a.ky, W = a.ky + a.k, kp = a.kp;
+  const bool corr = a.Cplo != nullptr;
+  auto zero_out = [&]() {
+    for (int e = tid; e < kp * kp; e += NTF) {
+      a.Zp[e] = 0.0;
+      if (a.Zplo) a.Zplo[e] = 0.0;
+    }
+  };
+  if (a.status[0] != 0) {
+    zero_out();
+    return;
+  }
+  auto g = [&](int r, int c) { return ld_g(a.G_hi, a.G_lo, r * W + c); };
+  auto ldm = [&](const double* h, const double* l, int i, int j) { return dd_make(h[i * LD + j], l[i * LD + j]); };
+  auto stm = [&](double* h, double* l, int i, int j, dd_t v) {
+    h[i * LD + j] = v.hi;
+    l[i * LD + j] = v.lo;
+  };
+
+  // Projected Gram matrix M = G_XX - C^T D, D = 2C - S C (S = G_YY, C = G_YX):
+  // S into sM and C into sV, then D, then M, each element one Dot2-style
+  // accumulation.  cpv: this pass's coefficients (D corrected, else C).
+  dd_t cpv[NE];
+  if (ky > 0) {
+    for (int e = tid; e < ky * ky; e += NTF) stm(sMh, sMl, e / ky, e % ky, g(e / ky, e % ky));
+    for (int e = tid; e < ky * k; e += NTF) stm(sVh, sVl, e / k, e % k, g(e / k, ky + e % k));
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + u * NTF;
+      cpv[u] = dd_from(0.0);
+      if (e < ky * k) {
+        const int r = e / k, l = e - r * k;
+        const dd_t c = ldm(sVh, sVl, r, l);
+        Acc<true> acc(dd_make(2.0 * c.hi, 2.0 * c.lo));
+        for (int q = 0; q < ky; ++q) acc.add(dd_neg(ldm(sMh, sMl, r, q)), ldm(sVh, sVl, q, l));
+        cpv[u] = acc.get();
+      }
+    }
+    __syncthreads();  // S is read: D goes into sM
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + u * NTF;
+      if (e < ky * k) stm(sMh, sMl, e / k, e % k, cpv[u]);
+    }
+    __syncthreads();
+    dd_t mv[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + u * NTF;
+      mv[u] = dd_from(0.0);
+      if (e < k * k) {
+        const int i = e / k, l = e - i * k;
+        if (i <= l) {
+          Acc<true> acc(g(ky + i, ky + l));
+          for (int r = 0; r < ky; ++r) acc.add(dd_neg(ldm(sVh, sVl, r, i)), ldm(sMh, sMl, r, l));
+          mv[u] = acc.get();
+        }
+      }
+      if (!corr && e < ky * k) cpv[u] = ldm(sVh, sVl, e / k, e % k);  // plain C
+    }
+    __syncthreads();  // C and D are read
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + u * NTF;
+      if (e < k * k) {
+        const int i = e / k, l = e - i * k;
+        if (i <= l) {
+          stm(sMh, sMl, i, l, mv[u]);
+          stm(sMh, sMl, l, i, mv[u]);
+        }
+      }
+    }
+  } else {
+    for (int e = tid; e < k * k; e += NTF) {
+      const int i = e / k, l = e - i * k;
+      if (i <= l) {
+        const dd_t v = g(i, l);
+        stm(sMh, sMl, i, l, v);
+        stm(sMh, sMl, l, i, v);
+      }
+    }
+  }
+  for (int e = tid; e < k * k; e += NTF) stm(sVh, sVl, e / k, e % k, dd_from((e / k) == (e % k) ? 1.0 : 0.0));
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  for (int e = tid; e < k * k; e += NTF)
+    if (!isfinite(sMh[(e / k) * LD + e % k]) || !isfinite(sMl[(e / k) * LD + e % k])) s_flag = 1;
+  __syncthreads();
+  if (s_flag) {
+    if (tid == 0) {
+      a.status[0] = 5;
+      a.status[1] = a.pass + 1;
+      a.status[2] = 0;
+    }
+    zero_out();
+    return;
+  }
+  if (a.shift_rel > 0.0) {
+    if (tid == 0) {
+      double tr = 0.0;
+      for (int i = 0; i < k; ++i) tr += sMh[i * LD + i];
+      for (int i = 0; i < k; ++i) stm(sMh, sMl, i, i, A::add(ldm(sMh, sMl, i, i), dd_from(a.shift_rel * tr)));
+    }
+    __syncthreads();
+  }
+
+  // Jacobi sweeps in DD
+  const int n = (k + 1) & ~1;
+  const int npair = n / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    __syncthreads();
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    for (int step = 0; step < n - 1; ++step) {
+      if (tid < npair) {
+        const int u = tid, v = n - 1 - tid;
+        auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + step) % (n - 1); };
+        int pp = pos(u), qq = pos(v);
+        if (pp > qq) {
+          const int t = pp;
+          pp = qq;
+          qq = t;
+        }
+        dd_t c = dd_from(1.0), sn = dd_from(0.0);
+        if (qq < k) {
+          const dd_t apq = ldm(sMh, sMl, pp, qq);
+          const dd_t app = ldm(sMh, sMl, pp, pp), aqq = ldm(sMh, sMl, qq, qq);
+          if (fabs(apq.hi) > 0x1p-105 * sqrt(fabs(app.hi * aqq.hi))) {
+            s_flag = 1;
+            const dd_t theta = dd_div(A::sub(aqq, app), A::add(apq, apq));
+            const dd_t at = theta.hi >= 0 ? theta : dd_neg(theta);
+            const dd_t den = A::add(at, A::sqrt_(A::add(A::mul(theta, theta), dd_from(1.0))));
+            dd_t t = A::recip(den);
+            if (theta.hi < 0) t = dd_neg(t);
+            c = A::rsqrt(A::add(A::mul(t, t), dd_from(1.0)));
+            sn = A::mul(t, c);
+          }
+        }
+        sp[tid] = pp;
+        sq[tid] = qq;
+        rch[tid] = c.hi;
+        rcl[tid] = c.lo;
+        rsh[tid] = sn.hi;
+        rsl[tid] = sn.lo;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J (pairs without a rotation are skipped: J = I)
+      for (int e = tid; e < npair * k; e += NTF) {
+        const int pr = e / k, r = e - pr * k;
+        const int p = sp[pr], q = sq[pr];
+        if (q >= k || (rsh[pr] == 0.0 && rsl[pr] == 0.0)) continue;
+        const dd_t c = dd_make(rch[pr], rcl[pr]), sn = dd_make(rsh[pr], rsl[pr]);
+        const dd_t arp = ldm(sMh, sMl, r, p), arq = ldm(sMh, sMl, r, q);
+        stm(sMh, sMl, r, p, A::sub(A::mul(c, arp), A::mul(sn, arq)));
+        stm(sMh, sMl, r, q, A::add(A::mul(sn, arp), A::mul(c, arq)));
+        const dd_t vrp = ldm(sVh, sVl, r, p), vrq = ldm(sVh, sVl, r, q);
+        stm(sVh, sVl, r, p, A::sub(A::mul(c, vrp), A::mul(sn, vrq)));
+        stm(sVh, sVl, r, q, A::add(A::mul(sn, vrp), A::mul(c, vrq)));
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = tid; e < npair * k; e += NTF) {
+        const int pr = e / k, r = e - pr * k;
+        const int p = sp[pr], q = sq[pr];
+        if (q >= k || (rsh[pr] == 0.0 && rsl[pr] == 0.0)) continue;
+        const dd_t c = dd_make(rch[pr], rcl[pr]), sn = dd_make(rsh[pr], rsl[pr]);
+        const dd_t apr = ldm(sMh, sMl, p, r), aqr = ldm(sMh, sMl, q, r);
+        stm(sMh, sMl, p, r, A::sub(A::mul(c, apr), A::mul(sn, aqr)));
+        stm(sMh, sMl, q, r, A::add(A::mul(sn, apr), A::mul(c, aqr)));
+      }
+      __syncthreads();
+    }
+    if (!s_flag) break;
+  }
+  // eigenvalues, lifted to 2^-104 lambda_max; their square roots and
+  // reciprocal square roots
+  if (tid == 0) {
+    double lmax = 0.0;
+    for (int i = 0; i < k; ++i) lmax = fmax(lmax, sMh[i * LD + i]);
+    const double floor_ = lmax * 0x1p-104;
+    for (int i = 0; i < k; ++i) {
+      dd_t l = ldm(sMh, sMl, i, i);
+      if (!(l.hi > floor_)) l = dd_from(floor_);
+      lh[i] = l.hi;
+      ll[i] = l.lo;
+    }
+  }
+  __syncthreads();
+  if (tid < k) {
+    const dd_t l = dd_make(lh[tid], ll[tid]);
+    const dd_t rs = A::rsqrt(l), sq_ = A::sqrt_(l);
+    lrh[tid] = rs.hi;
+    lrl[tid] = rs.lo;
+    lsh[tid] = sq_.hi;
+    lsl[tid] = sq_.lo;
+  }
+  __syncthreads();
+  // Z and R_p
+  dd_t rv[NE];
+  for (int e = tid; e < kp * kp; e += NTF) {
+    const int i = e / kp, j = e - i * kp;
+    dd_t z = dd_from(0.0);
+    if (i < k && j < k) {
+      Acc<true> az(dd_from(0.0));
+      for (int l = 0; l < k; ++l)
+        az.add(A::mul(ldm(sVh, sVl, i, l), ldm(sVh, sVl, j, l)), dd_make(lrh[l], lrl[l]));
+      z = az.get();
+      if (a.Z_out) a.Z_out[i * k + j] = z.hi;
+    }
+    const double zr = z.hi + z.lo;
+    a.Zp[e] = zr;
+    if (a.Zplo) a.Zplo[e] = (z.hi - zr) + z.lo;
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * NTF;
+    rv[u] = dd_from(0.0);
+    if (e < k * k) {
+      const int i = e / k, j = e - i * k;
+      Acc<true> ar(dd_from(0.0));
+      for (int l = 0; l < k; ++l)
+        ar.add(A::mul(ldm(sVh, sVl, i, l), ldm(sVh, sVl, j, l)), dd_make(lsh[l], lsl[l]));
+      rv[u] = ar.get();
+      if (a.Rp_out) a.Rp_out[e] = rv[u].hi;
+    }
+  }
+  __syncthreads();  // V is read: R_p into sM, C_p into sV
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * NTF;
+    if (e < k * k) stm(sMh, sMl, e / k, e % k, rv[u]);
+    if (e < ky * k) stm(sVh, sVl, e / k, e % k, cpv[u]);
+  }
+  __syncthreads();
+  // C of this pass for the update (rounded, and the remainder for a DD update)
+  for (int e = tid; e < ky * kp; e += NTF) {
+    const int r = e / kp, j = e - r * kp;
+    const dd_t v = j < k ? ldm(sVh, sVl, r, j) : dd_from(0.0);
+    const double cr = v.hi + v.lo;
+    a.Cp[e] = cr;
+    if (a.Cplo) a.Cplo[e] = (v.hi - cr) + v.lo;
+  }
+  // totals in DD: C_tot += C_p R_tot_old, R_tot = R_p R_tot_old
+  const bool first = (a.pass == 0);
+  dd_t cn[NE], rn[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * NTF;
+    cn[u] = rn[u] = dd_from(0.0);
+    if (e < ky * k) {
+      const int l = e / k, j = e - l * k;
+      if (first) {
+        cn[u] = ldm(sVh, sVl, l, j);
+      } else {
+        Acc<true> acc(dd_make(a.Ctot[e], a.Ctot[ky * k + e]));
+        for (int q = 0; q < k; ++q)
+          acc.add(ldm(sVh, sVl, l, q), dd_make(a.Rtot[q * k + j], a.Rtot[k * k + q * k + j]));
+        cn[u] = acc.get();
+      }
+    }
+    if (e < k * k) {
+      const int i = e / k, j = e - i * k;
+      if (first) {
+        rn[u] = ldm(sMh, sMl, i, j);
+      } else {
+        Acc<true> acc(dd_from(0.0));
+        for (int q = 0; q < k; ++q)
+          acc.add(ldm(sMh, sMl, i, q), dd_make(a.Rtot[q * k + j], a.Rtot[k * k + q * k + j]));
+        rn[u] = acc.get();
+      }
+    }
+  }
+  __syncthreads();  // every thread has read the old totals
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + u * NTF;
+    if (e < ky * k) {
+      a.Ctot[e] = cn[u].hi;
+      a.Ctot[ky * k + e] = cn[u].lo;
+      if (a.C_out) a.C_out[e] = cn[u].hi;
+    }
+    if (e < k * k) {
+      a.Rtot[e] = rn[u].hi;
+      a.Rtot[k * k + e] = rn[u].lo;
+      if (a.R_out) a.R_out[e] = rn[u].hi;
+    }
+  }
+  if (a.conv) {
+    double rr = 0.0, cc = 0.0;
+    for (int e = tid; e < k * k; e += NTF) {
+      const int i = e / k, j = e - i * k;
+      const double d = sMh[i * LD + j] - (i == j ? 1.0 : 0.0);
+      rr = __builtin_fma(d, d, rr);
+    }
+    for (int e = tid; e < ky * k; e += NTF) {
+      const double v = a.G_hi[(e / k) * W + ky + e % k];
+      cc = __builtin_fma(v, v, cc);
+    }
+    __syncthreads();
+    sVh[tid] = rr;
+    sVh[NTF + tid] = cc;
+    __syncthreads();
+    if (tid == 0) {
+      double sr = 0.0, sc = 0.0;
+      for (int t = 0; t < NTF; ++t) {
+        sr += sVh[t];
+        sc += sVh[NTF + t];
+      }
+      a.conv[0] = sqrt(sc);
+      a.conv[1] = sqrt(sr);
+    }
+  }
+  if (tid == 0) a.status[3] = a.pass + 1;
+}
+
 template <bool DD>
 void launch_chol(const FactorArgs& a, const FactorArgs* tab, int n, hipStream_t st) {
   if (a.k <= 8)
@@ -714,7 +1050,10 @@ void launch_chol(const FactorArgs& a, const FactorArgs* tab, int n, hipStream_t 
 hipError_t launch_factor_table(const FactorArgs& a, const FactorArgs* tab, int n, hipStream_t st) {
   if (a.k > 64 || a.ky > 64 || a.k < 1 || n < 1) return hipErrorInvalidValue;
   if (a.fact == 1) {
-    hipLaunchKernelGGL(svqb_kernel, dim3(n), dim3(NTF), 0, st, a, tab);
+    if (a.dd)
+      hipLaunchKernelGGL(svqb_dd_kernel, dim3(n), dim3(NTF), 0, st, a, tab);
+    else
+      hipLaunchKernelGGL(svqb_kernel, dim3(n), dim3(NTF), 0, st, a, tab);
   } else if (a.dd) {
     launch_chol<true>(a, tab, n, st);
   } else {

@@ -25,7 +25,7 @@ N, KY, K = 1000, 20, 4
 
 
 def one_pass(borth, X, Y, variant):
-    gram, fact = {"f64": ("f64", "svqb"), "dd": ("dd", "chol")}[variant]
+    gram, fact = {"f64": ("f64", "svqb"), "dd": ("dd", "chol"), "dd_svqb": ("dd", "svqb")}[variant]
     Q, R, C, info = borth.orthonormalize(dev(X), dev(Y), gram=gram, fact=fact, passes=1)
     assert info.status == 0
     met = oracle.metrics(host(Q), X, host(R), Y, host(C))
@@ -53,11 +53,12 @@ def test_fig7_orthogonality_of_q():
     om = {}
     for kx in (1e3, 1e6):
         X, Y = synth.projected_pair(N, K, KY, kx, kx, 7200 + int(np.log10(kx)))
-        om[kx] = {v: one_pass(borth, X, Y, v) for v in ("f64", "dd")}
+        om[kx] = {v: one_pass(borth, X, Y, v) for v in ("f64", "dd", "dd_svqb")}
         f64 = om[kx]["f64"]["omega"]
         assert 1e-3 * kx ** 2 * U64 <= f64 <= 1e3 * kx ** 2 * U64
-        dd = om[kx]["dd"]
-        assert dd["omega"] <= 1e-15 and dd["omega_y"] <= 1e-15 and dd["rho"] <= 1e-15
+        for v in ("dd", "dd_svqb"):  # the paper's DD project / SVQB, and DD CholQR
+            dd = om[kx][v]
+            assert dd["omega"] <= 1e-15 and dd["omega_y"] <= 1e-15 and dd["rho"] <= 1e-15
     assert 1e4 <= om[1e6]["f64"]["omega"] / om[1e3]["f64"]["omega"] <= 1e8  # kappa^2
 
 

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("k,ky", [(1, 10), (2, 20), (4, 40)])
 @pytest.mark.parametrize("gram,fact,kxy", [("f64", "svqb", 1e12), ("dd", "chol", 1e12),
-                                           ("f64", "chol", 1e4)])
+                                           ("dd", "svqb", 1e12), ("f64", "chol", 1e4)])
 def test_iterated_scheme_converges(k, ky, gram, fact, kxy):
     """binary64 Cholesky is run at kappa(X, Y) = 1e4 only: at 1e12 the
     projected Gram matrix (smallest eigenvalue ~1e-24 against an absolute
@@ -30,7 +30,7 @@ def test_iterated_scheme_converges(k, ky, gram, fact, kxy):
     met = oracle.metrics(host(Q), X, host(R), Y, host(C))
     note("  metrics", met)
     assert met["rho"] <= 1e-14
-    assert met["omega"] <= (20 * k * U64 if fact == "svqb" else 1e-14)
+    assert met["omega"] <= (20 * k * U64 if fact == "svqb" and gram == "f64" else 1e-14)
     assert met["omega_y"] <= 1e-14
     o1 = oracle.qr_q(X, Y)
     assert np.max(np.abs(host(C) - o1["C"])) <= 1e-13

@@ -162,6 +162,44 @@ def test_factor_svqb_vs_oracle():
     assert np.allclose(host(Z), host(Z).T, rtol=0, atol=1e-12 * np.abs(zex).max())
 
 
+@pytest.mark.parametrize("k,kappa,ky", [(4, 1e6, 0), (16, 1e10, 0), (33, 1e6, 0), (8, 1e5, 12),
+                                         (64, 1e3, 0)])
+def test_factor_svqb_dd_vs_oracle(k, kappa, ky):
+    """DD SVQB: Jacobi, Z = M^{-1/2} and R = M^{1/2} in DD from the DD Gram
+    of [Y | X].  The oracle's binary128 Jacobi on the same M (formed in
+    binary128 from the same Gram) gives the same Z to a few ulps: the DD
+    transform carries kappa(M) u_DD (below binary64 rounding up to
+    kappa(M) ~ 1e16), where binary64 SVQB is off by kappa(M) u."""
+    borth = lib()
+    m = 3000
+    X = synth.svd_matrix(m, k, kappa, 56 + k)
+    if ky:
+        Y = synth.locked_basis(m, ky, 57)
+        X = X + Y @ np.random.default_rng(58).standard_normal((ky, k))
+        ghi, glo = oracle.gram_q(np.hstack([Y, X]))
+    else:
+        ghi, glo = oracle.gram_q(X)
+    Z, R, C, info = borth.factor(dev(ghi), dev(glo), ky=ky, fact="svqb")
+    assert info.status == 0
+    # the oracle's M: the exact projected Gram (binary128), as hi/lo
+    if ky:
+        Xt = X - Y @ oracle.qr_q(X, Y)["C"]
+        mhi, mlo = oracle.gram_q(Xt)
+        # binary128 Gram of the rounded Xt differs from the projected Gram by
+        # rounding of Xt: compare at that level instead of ulps
+        zex, lam, _ = oracle.svqb_q(mhi, mlo)
+        tol = 1e3 * U64 * kappa
+    else:
+        zex, lam, _ = oracle.svqb_q(ghi, glo)
+        # the DD rotations carry u_DD |M|, i.e. kappa(M) u_DD relative to
+        # the smallest eigenvalue (kappa(M) = kappa^2)
+        tol = 8 * U64 + 100 * kappa ** 2 * 2.0 ** -106
+    Zh = host(Z)
+    note(" dd svqb", k, kappa, ky, rel_fro(Zh, zex))
+    assert rel_fro(Zh, zex) <= tol
+    assert np.max(np.abs(Zh - Zh.T)) <= 2 * U64 * np.max(np.abs(Zh))
+
+
 def test_factor_svqb_near_identity_k64():
     """Second-pass shape: M = Q_1^T Q_1 with ||M - I|| ~ 1e-10 at k = 64
     (2016 rotations per sweep).  Z must stay within O(k u) of the exact
