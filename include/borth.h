@@ -197,6 +197,23 @@ borth_status borth_orthonormalize_iter(borth_ctx ctx, int64_t m, int k, const do
                                        const borth_opts* opts, double eps, int max_iter,
                                        borth_iter_info* it, borth_info* info);
 
+/* The iterated scheme in a B-inner product, B = diag(bdiag) symmetric
+ * positive definite (Sec. 4.2: the technique carries over to B-inner
+ * products).  bdiag: m positive weights (device, binary64).  Y must be
+ * B-orthonormal (Y^T B Y = I, up to its own rounding: the projection uses
+ * the measured Y^T B Y as in the plain case).  Every Gram sweep takes
+ * [Y | S]^T B [Y | S] (the DD variant with an exact split of each weighted
+ * product); the factors and the update are those of the plain scheme.  On
+ * return Q^T B Q = I, Y^T B Q = 0 and X = Y C + Q R.  The Gram sweeps run on
+ * the vector-ALU tile kernel (binary64 or DD) and, for narrow blocks, the
+ * update's fused Gram columns; everything else as borth_orthonormalize_iter,
+ * whose arguments these are. */
+borth_status borth_orthonormalize_iter_b(borth_ctx ctx, int64_t m, int k, const double* X,
+                                         int64_t ldx, const double* Y, int64_t ldy, int ky,
+                                         const double* bdiag, double* Q, int64_t ldq, double* R,
+                                         double* C, const borth_opts* opts, double eps,
+                                         int max_iter, borth_iter_info* it, borth_info* info);
+
 /* One block of a batch (all pointers device, as in borth_orthonormalize;
  * X binary64). */
 typedef struct {

@@ -63,6 +63,7 @@ def _load():
             "or_gram_q": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp, _dp], _int),
             "or_gram_dot2": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp, _dp], _int),
             "or_gram_f64": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp], _int),
+            "or_gram_w_q": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp, _dp, _dp], _int),
             "or_chol_q": ([_int, _dp, _dp, _dp, _dp], _int),
             "or_trinv_q": ([_int, _dp, _dp, _dp, _dp], _int),
             "or_update_q": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp, _dp, _dp,
@@ -109,6 +110,36 @@ def gram_q(A, B=None):
     lo = np.empty((ka, kb))
     _load().or_gram_q(m, ka, _p(A), ka, kb, _p(B), kb, _p(hi), _p(lo))
     return hi, lo
+
+
+def gram_w_q(A, w, B=None):
+    """Exact A^T diag(w) B (B-inner products): binary128 accumulation, as
+    (hi, lo) float64."""
+    A = _c(A)
+    B = A if B is None else _c(B)
+    w = _c(np.asarray(w, dtype=np.float64).reshape(-1))
+    m, ka = A.shape
+    kb = B.shape[1]
+    if w.shape[0] != m or B.shape[0] != m:
+        raise ValueError("row counts differ")
+    ghi = np.zeros((ka, kb))
+    glo = np.zeros((ka, kb))
+    _load().or_gram_w_q(m, ka, _p(A), ka, kb, _p(B), kb, _p(w), _p(ghi), _p(glo))
+    return ghi, glo
+
+
+def metrics_b(Q, X, R, w, Y=None, C=None):
+    """B-inner-product measures, B = diag(w): omega_B = ||Q^T B Q - I||_F,
+    omega_Y = ||Y^T B Q||_F (binary128 Gram matrices), rho as in metrics."""
+    k = Q.shape[1]
+    ghi, glo = gram_w_q(Q, w)
+    om = float(np.linalg.norm((ghi - np.eye(k)) + glo))
+    omy = 0.0
+    if Y is not None and Y.shape[1] > 0:
+        yhi, ylo = gram_w_q(Y, w, Q)
+        omy = float(np.linalg.norm(yhi + ylo))
+    rho = metrics(Q, X, R, Y, C)["rho"]
+    return {"omega": om, "omega_y": omy, "rho": rho}
 
 
 def gram_dot2(A, B=None):

@@ -98,6 +98,37 @@ int or_gram_q(int64_t m, int ka, const double* A, int64_t lda, int kb,
   return 0;
 }
 
+/* O1: B-weighted Gram-type product  G = A^T diag(w) B  (ka x kb), the
+ * B-inner products of Sec. 4.2's closing remark: each term (w_r a_ri) b_rj
+ * in binary128 (w_r a_ri is exact there), accumulated as in or_gram_q. */
+int or_gram_w_q(int64_t m, int ka, const double* A, int64_t lda, int kb,
+                const double* B, int64_t ldb, const double* w, double* ghi, double* glo) {
+  const int64_t np = npart(m);
+  const size_t n = (size_t)ka * (size_t)kb;
+  f128* part = (f128*)calloc((size_t)np * n + 1, sizeof(f128));
+  if (!part) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t b = 0; b < np; ++b) {
+    f128* p = part + (size_t)b * n;
+    for (int64_t r = pbeg(m, np, b); r < pbeg(m, np, b + 1); ++r) {
+      const double* a = A + r * lda;
+      const double* c = B + r * ldb;
+      const f128 wr = (f128)w[r];
+      for (int i = 0; i < ka; ++i) {
+        const f128 ai = wr * (f128)a[i];
+        for (int j = 0; j < kb; ++j) p[(size_t)i * kb + j] += ai * (f128)c[j];
+      }
+    }
+  }
+  for (size_t e = 0; e < n; ++e) {
+    f128 s = 0;
+    for (int64_t b = 0; b < np; ++b) s += part[(size_t)b * n + e];
+    split_q(s, &ghi[e], glo ? &glo[e] : NULL);
+  }
+  free(part);
+  return 0;
+}
+
 /* O1: Cholesky  G = R^T R  (R upper, positive diagonal) of the symmetric G
  * given as hi(+lo), in binary128.  Reads the upper triangle of G.
  * info = 0 on success, j (1-based) if the j-th pivot is not positive/finite. */

@@ -238,12 +238,13 @@ class IterInfo:
 
 
 def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5, out=None,
-                        R=None, C=None, fuse=True, check=True, ctx=None):
+                        R=None, C=None, fuse=True, B=None, check=True, ctx=None):
     """Iterated two-phase scheme: passes of projection against Y and
     orthonormalization until ||C_j||_F <= eps and ||R_j - I||_F <= eps (or
     max_iter passes).  ``fuse=False``: a full Gram sweep in every pass
-    instead of Gram columns accumulated by the previous update.  Returns
-    (Q, R, C, IterInfo, Info)."""
+    instead of Gram columns accumulated by the previous update.  ``B``: the
+    diagonal of an SPD B (device vector of m weights) for the B-inner
+    product.  Returns (Q, R, C, IterInfo, Info)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
     m, k = X.shape
@@ -256,10 +257,18 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
     o = _opts(gram, fact, 1, "materialize", 0.0, 0 if fuse else FLAG_NO_FUSE)
     it = _lib.borth_iter_info()
     inf = _lib.borth_info()
-    st = ctx.lib.borth_orthonormalize_iter(
-        ctx.h, m, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y) if ky else 0, ky, _ptr(Q), _ld(Q), _ptr(R),
-        _ptr(C) if ky else None, ctypes.byref(o), float(eps), int(max_iter), ctypes.byref(it),
-        ctypes.byref(inf))
+    if B is None:
+        st = ctx.lib.borth_orthonormalize_iter(
+            ctx.h, m, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y) if ky else 0, ky, _ptr(Q), _ld(Q),
+            _ptr(R), _ptr(C) if ky else None, ctypes.byref(o), float(eps), int(max_iter),
+            ctypes.byref(it), ctypes.byref(inf))
+    else:
+        if B.dim() != 1 or B.shape[0] != m or B.dtype != torch.float64 or not B.is_contiguous():
+            raise ValueError("B must be a contiguous float64 vector of m weights")
+        st = ctx.lib.borth_orthonormalize_iter_b(
+            ctx.h, m, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y) if ky else 0, ky, _ptr(B), _ptr(Q),
+            _ld(Q), _ptr(R), _ptr(C) if ky else None, ctypes.byref(o), float(eps), int(max_iter),
+            ctypes.byref(it), ctypes.byref(inf))
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)
     return (Q, R, (C if ky else None),

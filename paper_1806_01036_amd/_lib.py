@@ -59,6 +59,10 @@ EXPORTS = {
                                    _vp, _vp, ctypes.POINTER(borth_opts), _dbl, _int,
                                    ctypes.POINTER(borth_iter_info), ctypes.POINTER(borth_info)],
                                   _int),
+    "borth_orthonormalize_iter_b": ([_vp, _i64, _int, _vp, _i64, _vp, _i64, _int, _vp, _vp,
+                                     _i64, _vp, _vp, ctypes.POINTER(borth_opts), _dbl, _int,
+                                     ctypes.POINTER(borth_iter_info), ctypes.POINTER(borth_info)],
+                                    _int),
     "borth_batch_orthonormalize": ([_vp, _int, ctypes.POINTER(borth_block),
                                     ctypes.POINTER(borth_opts), ctypes.POINTER(borth_info)],
                                    _int),

@@ -576,11 +576,12 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
   return BORTH_OK;
 }
 
-borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const double* X,
-                                       int64_t ldx, const double* Y, int64_t ldy, int ky,
-                                       double* Q, int64_t ldq, double* R, double* C,
-                                       const borth_opts* opts, double eps, int max_iter,
-                                       borth_iter_info* it, borth_info* info) {
+namespace {
+// The iterated scheme, in the inner product of B = diag(bw) (bw = null: B = I).
+borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t ldx,
+                       const double* Y, int64_t ldy, int ky, const double* bw, double* Q,
+                       int64_t ldq, double* R, double* C, const borth_opts* opts, double eps,
+                       int max_iter, borth_iter_info* it, borth_info* info) {
   if (!c) return BORTH_ERR_ARG;
   borth_opts o;
   if (opts) o = *opts; else borth_default_opts(&o);
@@ -620,13 +621,15 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
     const double* S = p == 0 ? X : Q;
     const int64_t lds_ = p == 0 ? ldx : ldq;
     Src src{Y, ldy, S, lds_, 0, m};
+    Src gsrc = src;  // the Gram sweeps take B's diagonal
+    gsrc.bw = bw;
     if (!have_gram) {
       int nwg = 0;
       // Y does not change between passes: after the first, only the columns
       // [Y | S]^T S are swept and Y^T Y stays from the first pass's reduction.
       const GramLayout Lg = (p > 0 && !nofuse) ? Lx : L;
       prof_begin(c, 0);
-      HIPCHK(c, launch_gram(src, Lg, dd ? 1 : 0, c->part, c->part_cap, &nwg,
+      HIPCHK(c, launch_gram(gsrc, Lg, dd ? 1 : 0, c->part, c->part_cap, &nwg,
                             Lg.ty > 0 ? TuneGram{} : lookup(c->tune_gram, dd ? 1 : 0, kp, ky > 0),
                             c->stream),
              "gram");
@@ -674,6 +677,7 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
       u.partial_cap_doubles = c->part_cap;
       u.gram_xcols = 1;
       u.gram_dd = dd ? 1 : 0;
+      u.bw = bw;
     }
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u, make_layout(ky, k, kp), lookup(c->tune_upd, 0, kp, ky > 0),
@@ -712,6 +716,27 @@ borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const doub
                              c->stream),
            "copy C");
   return read_status(c, info);
+}
+}  // namespace
+
+borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const double* X,
+                                       int64_t ldx, const double* Y, int64_t ldy, int ky,
+                                       double* Q, int64_t ldq, double* R, double* C,
+                                       const borth_opts* opts, double eps, int max_iter,
+                                       borth_iter_info* it, borth_info* info) {
+  return iter_impl(c, m, k, X, ldx, Y, ldy, ky, nullptr, Q, ldq, R, C, opts, eps, max_iter, it,
+                   info);
+}
+
+borth_status borth_orthonormalize_iter_b(borth_ctx c, int64_t m, int k, const double* X,
+                                         int64_t ldx, const double* Y, int64_t ldy, int ky,
+                                         const double* bdiag, double* Q, int64_t ldq, double* R,
+                                         double* C, const borth_opts* opts, double eps,
+                                         int max_iter, borth_iter_info* it, borth_info* info) {
+  if (!c) return BORTH_ERR_ARG;
+  if (!bdiag) return fail_arg(c, "bdiag");
+  return iter_impl(c, m, k, X, ldx, Y, ldy, ky, bdiag, Q, ldq, R, C, opts, eps, max_iter, it,
+                   info);
 }
 
 borth_status borth_set_profiling(borth_ctx c, int on) {

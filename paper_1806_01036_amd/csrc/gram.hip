@@ -87,7 +87,9 @@ __device__ __forceinline__ double fetch(const Src& s, const GramLayout& L, int64
 // ---------------------------------------------------------------------------
 // VALU tile kernel (binary64 or DD).
 
-template <bool DD, int NTB, bool BATCH>
+// WB: rows weighted by the diagonal of B (s.bw): each product a_i (w b_j),
+// with w b_j split exactly (TwoProduct) in DD mode.
+template <bool DD, int NTB, bool BATCH, bool WB>
 __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
                                                          const GramSeg* __restrict__ tab,
                                                          const int* __restrict__ wg2seg) {
@@ -134,8 +136,18 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   // zero for rows beyond m and padding columns is selected there), so the
   // wait for the loads falls after the arithmetic of the current panel.
   double pf[NQ];
+  // WB: weights of panel rows tid and tid + NT (P <= 8 NT / Wp <= 2 NT)
+  double pfw[2] = {0.0, 0.0};
   const int64_t step = (int64_t)RS * ld;
   auto fetch_panel = [&](int64_t pnl) {
+    if (WB) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = tid + h * NT;
+        const int64_t rw = pnl * P + (t < P ? t : 0);
+        pfw[h] = gmem(s.bw)[rw < s.m ? rw : s.m - 1];
+      }
+    }
     const int64_t row0 = pnl * P + lr;
     if ((pnl + 1) * P <= s.m) {
       // full panel (uniform branch): rows in range, pointer steps of RS rows
@@ -161,26 +173,46 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
       for (int q = 0; q < NQ; ++q)
         if (q < nq) lds[(lr + q * RS) * stride + lc] = (ldr && row0 + q * RS < s.m) ? pf[q] : 0.0;
     }
+    // the weight of each row sits in the spare column Wp of its LDS row
+    if (WB) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = tid + h * NT;
+        if (t < P) lds[t * stride + L.Wp] = pnl * P + t < s.m ? pfw[h] : 0.0;
+      }
+    }
     __syncthreads();
     fetch_panel(pnl + nwg);
     if (active) {
 #pragma unroll 2
       for (int r = phase; r < P; r += S) {
         const double* row = lds + r * stride;
-        double a[4], b[4];
+        double a[4], b[4], bl[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           a[i] = row[4 * ti + i];
           b[i] = row[4 * tj + i];
+          bl[i] = 0.0;
+        }
+        if (WB) {
+          const double w = row[L.Wp];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double h = b[j] * w;
+            bl[j] = DD ? __builtin_fma(b[j], w, -h) : 0.0;  // w b_j = h + bl exactly
+            b[j] = h;
+          }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            if (DD)
+            if (DD) {
               dot2_step(acs[4 * i + j], acc[4 * i + j], a[i], b[j]);
-            else
+              if (WB) acc[4 * i + j] = __builtin_fma(a[i], bl[j], acc[4 * i + j]);
+            } else {
               acs[4 * i + j] = __builtin_fma(a[i], b[j], acs[4 * i + j]);
+            }
           }
       }
     }
@@ -406,9 +438,9 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
 // Host side.  A sweep's shape: the MFMA kernel (binary64, 16 <= Wp <= 80) or
 // the VALU tile kernel (DD, or binary64 outside that range).
 
-int gram_kind(const GramLayout& L, int mode) {
+int gram_kind(const GramLayout& L, int mode, bool weighted) {
   const int W16 = (L.Wp + 15) / 16;
-  return (mode == 0 && L.ty == 0 && L.Wp >= 16 && W16 <= 5) ? 0 : 1;
+  return (mode == 0 && !weighted && L.ty == 0 && L.Wp >= 16 && W16 <= 5) ? 0 : 1;
 }
 
 // 256 threads (one 4x4 tile each; row phases when there are fewer than 128
@@ -436,14 +468,14 @@ static int gram_tiles_rows(const GramLayout& L, int NT) {
 }
 
 int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
-  if (gram_kind(L, mode) == 0) return (s.m + 3) / 4;
+  if (gram_kind(L, mode, s.bw != nullptr) == 0) return (s.m + 3) / 4;
   const int P = gram_tiles_rows(L, NT);
   return (s.m + P - 1) / P;
 }
 
 int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT) {
   const int64_t u = gram_units(s, L, mode, NT);
-  const int64_t need = gram_kind(L, mode) == 0 ? (u + 3) / 4 : u;
+  const int64_t need = gram_kind(L, mode, s.bw != nullptr) == 0 ? (u + 3) / 4 : u;
   return (int)(need < 1 ? 1 : (need > (1 << 20) ? (1 << 20) : need));
 }
 
@@ -459,7 +491,7 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
   g.P = 0;
   g.S = 0;
   *shmem = 0;
-  if (gram_kind(L, mode) == 1) {
+  if (gram_kind(L, mode, s.bw != nullptr) == 1) {
     g.S = NT / L.ntiles;
     if (g.S < 1 || NT / L.Wp < 1) return false;
     g.P = gram_tiles_rows(L, NT);
@@ -487,9 +519,11 @@ hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int g
 #define BORTH_TILES(D, N)                                                                      \
   do {                                                                                         \
     if (b)                                                                                     \
-      hipLaunchKernelGGL((gram_tiles_kernel<D, N, true>), dim3(grid), dim3(N), shmem, st, one, tab, wg2seg); \
+      hipLaunchKernelGGL((gram_tiles_kernel<D, N, true, false>), dim3(grid), dim3(N), shmem, st, one, tab, wg2seg); \
+    else if (one.s.bw)                                                                         \
+      hipLaunchKernelGGL((gram_tiles_kernel<D, N, false, true>), dim3(grid), dim3(N), shmem, st, one, tab, wg2seg); \
     else                                                                                       \
-      hipLaunchKernelGGL((gram_tiles_kernel<D, N, false>), dim3(grid), dim3(N), shmem, st, one, tab, wg2seg); \
+      hipLaunchKernelGGL((gram_tiles_kernel<D, N, false, false>), dim3(grid), dim3(N), shmem, st, one, tab, wg2seg); \
   } while (0)
   if (kind == 0) {
     switch (NT_or_T) {
@@ -530,11 +564,11 @@ int gram_tiles_resident(int mode, int NT, size_t shmem) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   hipError_t e;
   if (NT == 256)
-    e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 256, false>, 256, shmem)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 256, false>, 256, shmem);
+    e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 256, false, false>, 256, shmem)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 256, false, false>, 256, shmem);
   else
-    e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 1024, false>, 1024, shmem)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 1024, false>, 1024, shmem);
+    e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 1024, false, false>, 1024, shmem)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 1024, false, false>, 1024, shmem);
   if (e != hipSuccess || per < 1) return 0;
   std::lock_guard<std::mutex> lk(mu);
   cache[key] = per * cus;
@@ -543,7 +577,8 @@ int gram_tiles_resident(int mode, int NT, size_t shmem) {
 
 hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* partials,
                        int64_t cap, int* nwg_out, const TuneGram& tune, hipStream_t st) {
-  const int kind = gram_kind(L, mode);
+  if (s.bw && s.x_f32) return hipErrorInvalidValue;
+  const int kind = gram_kind(L, mode, s.bw != nullptr);
   const int NT = kind == 0 ? 256 : gram_tiles_threads(L);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   if (tune.nwg <= 0 && kind == 1) {

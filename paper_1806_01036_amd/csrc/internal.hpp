@@ -44,6 +44,9 @@ struct Src {
   int64_t ldx;
   int x_f32;  // X is fp32
   int64_t m;
+  // Diagonal of B for a B-weighted Gram sweep [Y | X]^T B [Y | X] (m
+  // entries), or null (B = I).  Only the VALU tile kernel takes weights.
+  const double* bw = nullptr;
 };
 
 struct TuneGram {
@@ -75,7 +78,7 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
                        int64_t partial_cap_doubles, int* nwg_out, const TuneGram& tune,
                        hipStream_t st);
 // Pieces of launch_gram for the batched driver.
-int gram_kind(const GramLayout& L, int mode);  // 0 MFMA (binary64), 1 VALU tiles
+int gram_kind(const GramLayout& L, int mode, bool weighted = false);  // 0 MFMA (binary64), 1 VALU tiles
 int gram_tiles_threads(const GramLayout& L);   // 256 or 1024
 int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT);
 bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part, int wg0,
@@ -156,6 +159,7 @@ struct UpdateArgs {
   double* partials; int64_t partial_cap_doubles;
   int gram_xcols;                      // narrow fused Gram: [Y | T]^T T only
   int gram_dd;                         //   ... in DD
+  const double* bw;                    //   ... B-weighted (diagonal of B), or null
   int nwg;                             // out: partials written
   GramLayout glayout;                  // out: layout of those partials
 };
@@ -183,6 +187,7 @@ struct UpdDev {
   const double* Z2;
   const double* C1lo;  // low words of C1 and Z1: DD arithmetic (narrow kernel), or null
   const double* Z1lo;
+  const double* bw;    // diagonal of B for the narrow kernel's fused Gram, or null
   int wg0, nwg;
 };
 // Kernel class of an update launch.

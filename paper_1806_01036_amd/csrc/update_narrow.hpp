@@ -48,8 +48,16 @@ __device__ __forceinline__ void lds_sync() {
 
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
-// LDS row stride of a panel: Y, then (fused Gram) the KN columns of T; odd.
-__host__ __device__ inline int row_stride(int ky, int kn, int gr) { return (ky + (gr ? kn : 0)) | 1; }
+// Fused Gram kinds: 0 none, 1 binary64, 2 DD; 3 and 4 the same weighted by
+// the diagonal of B (B-inner products).
+__host__ __device__ constexpr int gr_prec(int gr) { return gr > 2 ? gr - 2 : gr; }
+__host__ __device__ constexpr bool gr_weighted(int gr) { return gr > 2; }
+
+// LDS row stride of a panel: Y, then (fused Gram) the KN columns of T and
+// (weighted) the row's weight; odd.
+__host__ __device__ inline int row_stride(int ky, int kn, int gr) {
+  return (ky + (gr ? kn : 0) + (gr_weighted(gr) ? 1 : 0)) | 1;
+}
 
 // LDS doubles of one wave: the panel, or the phase sums of the fused Gram.
 inline size_t lds_doubles(int ky, int kn, int gr) {
@@ -67,7 +75,8 @@ inline size_t lds_doubles(int ky, int kn, int gr) {
 // once.  Otherwise (and for a ragged last panel) value q of lane l is value
 // 64 q + l of the panel, addressed through its row and column.
 // GR: 0 no Gram; 1 binary64, 2 DD partials of [Y | T]^T T in the layout G
-// (make_layout_xcols), one per workgroup (ky + k <= 64).
+// (make_layout_xcols), one per workgroup (ky + k <= 64); 3, 4: the same of
+// [Y | T]^T B T with B = diag(a.bw).
 template <int KN, int KYB, bool FAST, int GR>
 __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout G) {
   extern __shared__ double pan[];
@@ -93,6 +102,9 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
   d2_t yp[NP];
   int loff[NP];
   double xv[KN];
+  constexpr bool WB = gr_weighted(GR);
+  constexpr int GP = gr_prec(GR);  // 1 binary64, 2 DD
+  double wv = 1.0;                 // WB: weight of this lane's row of the loaded panel
 
   // Fused Gram: lane -> column c of [Y | T], row phase h of H.
   const int W = ky + k;
@@ -151,6 +163,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
       const double v = Xg[(row0 + rx) * a.ldx + (j < k ? j : k - 1)];
       xv[j] = j < k ? v : 0.0;
     }
+    if (WB) wv = gmem(a.bw)[row0 + rx];
   };
   auto store_generic = [&]() {
     if (KYB > 0) {
@@ -175,6 +188,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
       const double v = Xg[(row0 + lane) * a.ldx + (j < k ? j : k - 1)];
       xv[j] = j < k ? v : 0.0;
     }
+    if (WB) wv = gmem(a.bw)[row0 + lane];
   };
   auto store_fast = [&]() {
 #pragma unroll
@@ -185,7 +199,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
   };
   // T = S - Y C (one fused multiply-add per product term, S first), Q = T Z;
   // with the fused Gram, T joins the panel and is accumulated column-wise.
-  auto compute_store = [&](const double* xs, int64_t row0, int nrows) {
+  auto compute_store = [&](const double* xs, double ws, int64_t row0, int nrows) {
     double qv[KN];
     if (!pdd) {
       double t[KN];
@@ -251,17 +265,24 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
       // rows past m contribute nothing: their T is zero (their Y is finite)
 #pragma unroll
       for (int j = 0; j < KN; ++j) pan[lane * SP + ky + j] = lane < nrows ? qv[j] : 0.0;
+      if (WB) pan[lane * SP + ky + KN] = ws;
       lds_sync();
       if (gact) {
         for (int r = gh; r < 64; r += H) {
           const double* row = pan + r * SP;
           const double v = row[gc];
+          const double w = WB ? row[ky + KN] : 1.0;
 #pragma unroll
           for (int j = 0; j < KN; ++j) {
-            if (GR == 2)
-              dot2_step(gs[j], gcmp[j], v, row[ky + j]);
-            else
-              gs[j] = __builtin_fma(v, row[ky + j], gs[j]);
+            // weighted: w t_j = th + tl exactly (TwoProduct), then v (th + tl)
+            const double t = row[ky + j];
+            const double th = WB ? t * w : t;
+            if (GP == 2) {
+              dot2_step(gs[j], gcmp[j], v, th);
+              if (WB) gcmp[j] = __builtin_fma(v, __builtin_fma(t, w, -th), gcmp[j]);
+            } else {
+              gs[j] = __builtin_fma(v, th, gs[j]);
+            }
           }
         }
       }
@@ -280,12 +301,13 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
       double xs[KN];
 #pragma unroll
       for (int j = 0; j < KN; ++j) xs[j] = xv[j];
+      const double ws = wv;
       const int64_t nx = p + stride;
       if (nx < nfull) {  // in flight while this panel is computed
         if (FAST) load_fast(nx); else load_generic(nx);
       }
       lds_sync();
-      compute_store(xs, row0, nrows);
+      compute_store(xs, ws, row0, nrows);
       if (nx >= nfull) break;
       p = nx;
     }
@@ -297,7 +319,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
     load_generic(nfull);
     store_generic();
     lds_sync();
-    compute_store(xv, nfull * 64, (int)(m - nfull * 64));
+    compute_store(xv, wv, nfull * 64, (int)(m - nfull * 64));
   }
   if (!GR) return;
 
@@ -309,7 +331,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
   if (gact) {
 #pragma unroll
     for (int j = 0; j < KN; ++j) {
-      const dd_t v = GR == 2 ? dot2_finish(gs[j], gcmp[j]) : dd_from(gs[j]);
+      const dd_t v = GP == 2 ? dot2_finish(gs[j], gcmp[j]) : dd_from(gs[j]);
       ph[(gh * W + gc) * KN + j] = v.hi;
       ph[PW + (gh * W + gc) * KN + j] = v.lo;
     }
@@ -321,7 +343,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
       dd_t v = dd_make(ph[gc * KN + j], ph[PW + gc * KN + j]);
       for (int h = 1; h < H; ++h) {
         const int x = (h * W + gc) * KN + j;
-        v = GR == 2 ? dd_add(v, dd_make(ph[x], ph[PW + x])) : dd_from(v.hi + ph[x]);
+        v = GP == 2 ? dd_add(v, dd_make(ph[x], ph[PW + x])) : dd_from(v.hi + ph[x]);
       }
       gs[j] = v.hi;
       gcmp[j] = v.lo;
@@ -336,7 +358,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
     }
   }
   lds_sync();
-  double BORTH_GLOBAL* out = gmem(a.part) + (int64_t)blockIdx.x * G.E * (GR == 2 ? 2 : 1);
+  double BORTH_GLOBAL* out = gmem(a.part) + (int64_t)blockIdx.x * G.E * (GP == 2 ? 2 : 1);
   for (int e = lane; e < G.E; e += 64) {
     // tile t of the layout: row ti holds tiles tj = max(ti, ty) .. T4 - 1
     int t = e >> 4, ti = 0;
@@ -353,7 +375,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
     const bool ok = li >= 0 && j >= 0 && j < k;
     const double hi = ok ? ph[li * KN + (ok ? j : 0)] : 0.0;
     const double lo = ok ? ph[PW + li * KN + (ok ? j : 0)] : 0.0;
-    if (GR == 2) {
+    if (GP == 2) {
       out[2 * e] = hi;
       out[2 * e + 1] = lo;
     } else {

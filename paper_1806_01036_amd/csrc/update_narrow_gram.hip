@@ -1,6 +1,7 @@
 // Narrow basis update sweep with the next pass's Gram columns fused in
 // (kernel in update_narrow.hpp): host dispatch.  Y must be stored densely
-// with an even number of columns (or be absent), and ky + k <= 64.
+// with an even number of columns (or be absent), and ky + k <= 64.  With
+// d.bw the Gram columns are B-weighted (B = diag(d.bw)).
 #include "update_narrow.hpp"
 
 namespace borth {
@@ -37,6 +38,7 @@ hipError_t launch_update_narrow_gram(const UpdDev& d, int kp, int mode, const Gr
                                      int64_t max_wg, int* nwg, hipStream_t st) {
   if (!update_narrow_gram_ok(d, kp) || d.m < 1 || !d.Q || !d.part || G.ky != d.ky || G.k != d.k)
     return hipErrorInvalidValue;
+  if (d.bw) return mode ? launch_g<4>(d, kp, G, max_wg, nwg, st) : launch_g<3>(d, kp, G, max_wg, nwg, st);
   return mode ? launch_g<2>(d, kp, G, max_wg, nwg, st) : launch_g<1>(d, kp, G, max_wg, nwg, st);
 }
 

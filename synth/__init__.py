@@ -41,6 +41,7 @@ __all__ = [
     "svd_matrix_device",
     "locked_basis_device",
     "projected_pair_device",
+    "b_weighted_pair",
 ]
 
 
@@ -213,3 +214,21 @@ def projected_pair_device(m: int, k: int, ky: int, kappa_x: float, kappa_xy: flo
     b = (vb * sig[None, :]) @ wb.t().contiguous()
     x = y @ a + p @ b
     return x.contiguous(), y
+
+
+def b_weighted_pair(m: int, k: int, ky: int, kappa_x: float, kappa_xy: float, kappa_b: float,
+                    seed: int):
+    """Inputs for a B-inner product, B = diag(w) with w log-uniform in
+    [kappa_b^-1/2, kappa_b^1/2]: (X, Y, w) = (W^-1/2 X0, W^-1/2 Y0, w) with
+    (X0, Y0) from ``projected_pair``, so Y^T B Y = I and X has the
+    B-condition and B-closeness to span(Y) of X0."""
+    if ky:
+        X0, Y0 = projected_pair(m, k, ky, kappa_x, kappa_xy, seed)
+    else:
+        X0, Y0 = svd_matrix(m, k, kappa_x, seed), np.zeros((m, 0))
+    rng = np.random.default_rng(seed + 99)
+    lw = rng.uniform(-0.5, 0.5, size=m) * np.log(kappa_b)
+    w = np.exp(lw)
+    s = 1.0 / np.sqrt(w)
+    return (np.ascontiguousarray(X0 * s[:, None]), np.ascontiguousarray(Y0 * s[:, None]),
+            np.ascontiguousarray(w))

@@ -250,6 +250,36 @@ def test_corrected_projection_second_order():
         assert np.linalg.norm(res) <= 1e-13 * np.linalg.norm(X)
 
 
+def test_gram_w_q_reduces_to_gram_q():
+    """B = I gives the unweighted binary128 Gram bitwise; B = diag(4^e) gives
+    the Gram of the rows scaled by 2^e (exact scalings) bitwise."""
+    X = synth.svd_matrix(3000, 6, 1e5, 63)
+    A = synth.locked_basis(3000, 3, 64)
+    ones = np.ones(3000)
+    for a, b in zip(oracle.gram_q(A, X), oracle.gram_w_q(A, ones, X)):
+        assert np.array_equal(a, b)
+    e = np.random.default_rng(65).integers(-6, 7, size=3000)
+    w = np.ldexp(1.0, 2 * e)
+    s = np.ldexp(1.0, e)[:, None]
+    for a, b in zip(oracle.gram_q(A * s, X * s), oracle.gram_w_q(A, w, X)):
+        assert np.array_equal(a, b)
+    mb = oracle.metrics_b(synth.locked_basis(3000, 4, 66), X[:, :4], np.eye(4), ones)
+    mp = oracle.metrics(synth.locked_basis(3000, 4, 66), X[:, :4], np.eye(4))
+    assert mb["omega"] == pytest.approx(mp["omega"], rel=1e-12, abs=1e-30)
+
+
+def test_b_weighted_inputs():
+    """The generator's Y is B-orthonormal and X keeps its B-condition."""
+    X, Y, w = synth.b_weighted_pair(2000, 3, 5, 1e4, 1e4, 1e4, 67)
+    yhi, ylo = oracle.gram_w_q(Y, w)
+    assert np.linalg.norm(yhi + ylo - np.eye(5)) <= 1e-14
+    assert 1e-2 <= w.min() and w.max() <= 1e2
+    Xt = X - Y @ (oracle.gram_w_q(Y, w, X)[0])
+    ghi, glo = oracle.gram_w_q(Xt, w)
+    ev = np.linalg.eigvalsh(ghi + glo)
+    assert np.sqrt(ev.max() / ev.min()) == pytest.approx(1e4, rel=1e-3)
+
+
 # --------------------------------------------------------------------------
 # LAPACK special cases and generator closed forms
 
