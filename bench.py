@@ -452,12 +452,59 @@ def run_fig7(args, torch, borth, synth):
             "data": "synthetic", "n_gpus": 1, "results": rows}
 
 
+def run_binner(args, torch, borth, synth):
+    """Iterated scheme in a B-inner product, B = diag(w), w log-uniform with
+    kappa(B) = 1e4, on the runtime experiment's shapes (n = 8e6, kappa(X) =
+    1e6, kappa(X, Y) = 1e12), against the same call with B = I."""
+    n = 8_000_000
+    rows = []
+    for ky, k in ((20, 4), (40, 1), (10, 2)):
+        X0, Y0 = synth.projected_pair_device(n, k, ky, 1e6, 1e12, 7000 + 10 * ky + k)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(8000 + ky + k)
+        w = torch.exp((torch.rand(n, generator=gen, dtype=torch.float64, device="cuda") - 0.5)
+                      * np.log(1e4))
+        s = torch.rsqrt(w)[:, None]
+        X = (X0 * s).contiguous()  # B-orthonormal Y, same conditions as (X0, Y0) in B
+        Y = (Y0 * s).contiguous()
+        Q = torch.empty_like(X)
+        for var, gram, fact in (("f64_svqb", "f64", "svqb"), ("dd_svqb", "dd", "svqb")):
+            for weighted in (True, False):
+                # B = I: the Euclidean problem (X0, Y0) of the same shape
+                kw = dict(gram=gram, fact=fact, eps=1e-10, max_iter=10, out=Q,
+                          B=w if weighted else None)
+                Xi, Yi = (X, Y) if weighted else (X0, Y0)
+                res = borth.orthonormalize_iter(Xi, Yi, **kw)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(max(1, args.steps)):
+                    t0 = time.perf_counter()
+                    res = borth.orthonormalize_iter(Xi, Yi, **kw)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                t = sorted(ts)[len(ts) // 2]
+                r = dict(ky=ky, nb=k, variant=var, B="diag(w)" if weighted else "I",
+                         passes=res[3].passes_run, converged=res[3].converged,
+                         s_per_vector=t / k)
+                if weighted:
+                    # B-orthogonality from the DD Gram of [W^1/2 Y | W^1/2 Q]
+                    sw = torch.sqrt(w)[:, None]
+                    om, omy = _orth_levels(borth, (Q * sw).contiguous(), (Y * sw).contiguous(),
+                                           k, ky)
+                    r.update(omega_b=om, omega_y_b=omy)
+                log(r)
+                rows.append(r)
+        del X, Y, Q, w, X0, Y0
+    return {"workload": "iterated project / orthonormalize in a B-inner product, n = 8e6, "
+                        "kappa(B) = 1e4", "data": "synthetic", "n_gpus": 1, "results": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "fig7", "fig8"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "fig7", "fig8", "binner"])
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--blocks", type=int, default=256)
@@ -477,7 +524,7 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    fn = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fig7": run_fig7, "fig8": run_fig8}.get(args.workload)
+    fn = {"c3": run_c3, "c2": run_c2, "c4": run_c4, "c5": run_c5, "fig7": run_fig7, "fig8": run_fig8, "binner": run_binner}.get(args.workload)
     if fn is None:
         raise SystemExit(f"workload {args.workload} not available")
     out = fn(args, torch, borth, synth)
