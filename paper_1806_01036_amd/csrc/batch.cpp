@@ -524,10 +524,6 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
     return fail_arg(c, "opts.gram");
   }
   if (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB) return fail_arg(c, "opts.fact");
-  if (o.fact == BORTH_SVQB && o.gram == BORTH_GRAM_DD) {
-    c->err = "SVQB runs in binary64 in this build";
-    return BORTH_ERR_UNSUPPORTED;
-  }
   for (int b = 0; b < nblocks; ++b) {
     const borth_block& x = blocks[b];
     if (x.k < 1 || x.k > 64 || x.ky < 0 || x.ky > 16 || x.m < (int64_t)x.k + x.ky)

@@ -123,7 +123,7 @@ def test_batch_breakdown_stays_in_its_block():
 
 @pytest.mark.parametrize("gram,fact,passes,project_once", [
     ("f64", "chol", 2, False), ("f64", "chol", 1, False), ("dd", "chol", 3, False),
-    ("dd", "chol", 2, True), ("f64", "svqb", 2, False)])
+    ("dd", "chol", 2, True), ("f64", "svqb", 2, False), ("dd", "svqb", 2, False)])
 def test_batch_options(gram, fact, passes, project_once):
     borth = lib()
     specs = [(4001, 8, 16, 1e3, 41), (9001, 32, 0, 1e5, 42), (3003, 17, 16, 1e4, 43),
@@ -136,7 +136,7 @@ def test_batch_options(gram, fact, passes, project_once):
         met = oracle.metrics(host(Q), X, host(R), Y, host(C) if C is not None else None)
         note(gram, fact, passes, project_once, spec, met)
         kappa, k = spec[3], spec[1]
-        if fact == "svqb":
+        if fact == "svqb" and gram == "f64":
             # binary64 SVQB: the dense symmetric Z is applied as a product, so
             # the residual carries k kappa u (CholQR's triangular structure
             # keeps its residual O(u)), and omega is the orthogonality level
@@ -151,6 +151,15 @@ def test_batch_options(gram, fact, passes, project_once):
             assert met["rho"] <= 4 * ms["rho"] + 1e-15
             assert met["omega"] <= 20 * k * U64
             assert met["omega"] <= 4 * ms["omega"] + 1e-15
+            continue
+        if fact == "svqb":
+            # DD SVQB in the first pass, binary64 SVQB in the second: the
+            # batched update applies the dense Z in binary64, so the residual
+            # carries k kappa u, and the last pass's Jacobi gives O(k u)
+            assert met["rho"] <= max(1e-14, k * kappa * U64)
+            assert met["omega"] <= 20 * k * U64
+            if Y is not None:
+                assert met["omega_y"] <= 1e-14
             continue
         assert met["rho"] <= 1e-14
         if passes == 1:
