@@ -81,6 +81,7 @@ typedef enum {
 #define BORTH_FLAG_PROJECT_ONCE 2u  /* project against Y in the first pass only (P,C,C) */
 #define BORTH_FLAG_GRAPH 4u         /* capture the launch sequence in a cached hipGraph */
 #define BORTH_FLAG_NO_FUSE 8u       /* iterated scheme: a separate Gram sweep in every pass */
+#define BORTH_FLAG_RANK_REVEAL 16u  /* iterated scheme, SVQB: drop null directions (see below) */
 
 typedef struct {
   int gram;       /* borth_gram_prec of pass 1 */
@@ -166,7 +167,8 @@ typedef struct {
   int converged;  /* 1 if the stop test held after passes_run passes */
   int passes_run;
   double c_norm;  /* ||C_j||_F of the last pass (its projection coefficients) */
-  double r_dev;   /* ||R_j - I||_F of the last pass */
+  double r_dev;   /* ||R_j - I_r||_F of the last pass (I_r: the first r diagonal ones) */
+  int rank;       /* numerical rank r of the last pass (k unless RANK_REVEAL) */
 } borth_iter_info;
 
 /* Iterated two-phase scheme (Sec. 4.2: phase I and phase II alternated until
@@ -184,7 +186,14 @@ typedef struct {
  * [Y | S_{j+1}]^T S_{j+1} (fused operations, Sec. 4.2), so later passes make
  * one sweep each; otherwise, or with BORTH_FLAG_NO_FUSE in opts->flags, each
  * later pass sweeps [Y | S_j]^T S_j (NO_FUSE: the whole Gram matrix of
- * [Y | S_j]) before its update.  Q may alias X as in borth_orthonormalize;
+ * [Y | S_j]) before its update.  With BORTH_FLAG_RANK_REVEAL and SVQB, each
+ * pass keeps the eigenpairs of M above k 2^-52 lambda_max (DD: k 2^-104
+ * lambda_max), in their order, as Z = U_r L_r^{-1/2} (k x r, zero columns
+ * after r) and R_j = L_r^{1/2} U_r^T: Q's first r columns are an
+ * orthonormal basis of the projected block's numerical range, the others
+ * zero, and X = Y C + Q R still holds up to the dropped directions;
+ * it->rank reports r (the paper's solver resizes its subspace by this
+ * rank).  Q may alias X as in borth_orthonormalize;
  * ky <= 64.  The call synchronizes after every pass to evaluate the stop
  * test.  On return X = Y C + Q R with R, C the products
  * of all passes (device, may be NULL); *it (host, required) reports the

@@ -26,7 +26,7 @@ __all__ = [
 GRAM = {"f64": 0, "dd": 1, "split": 2}
 FACT = {"chol": 0, "svqb": 1}
 SCHED = {"auto": 0, "materialize": 1, "recompute": 2}
-FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH, FLAG_NO_FUSE = 1, 2, 4, 8
+FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH, FLAG_NO_FUSE, FLAG_RANK_REVEAL = 1, 2, 4, 8, 16
 OK, ERR_ARG, ERR_HIP, ERR_NOMEM, BREAKDOWN, NONFINITE, UNSUPPORTED = range(7)
 
 
@@ -235,16 +235,20 @@ class IterInfo:
     passes_run: int
     c_norm: float
     r_dev: float
+    rank: int = 0
 
 
 def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5, out=None,
-                        R=None, C=None, fuse=True, B=None, check=True, ctx=None):
+                        R=None, C=None, fuse=True, B=None, rank_reveal=False, check=True,
+                        ctx=None):
     """Iterated two-phase scheme: passes of projection against Y and
     orthonormalization until ||C_j||_F <= eps and ||R_j - I||_F <= eps (or
     max_iter passes).  ``fuse=False``: a full Gram sweep in every pass
     instead of Gram columns accumulated by the previous update.  ``B``: the
     diagonal of an SPD B (device vector of m weights) for the B-inner
-    product.  Returns (Q, R, C, IterInfo, Info)."""
+    product.  ``rank_reveal`` (SVQB): drop the null directions of each pass
+    (Q's first IterInfo.rank columns span the block, the rest are zero).
+    Returns (Q, R, C, IterInfo, Info)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
     m, k = X.shape
@@ -254,7 +258,8 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
     R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
     if ky and C is None:
         C = torch.empty((ky, k), dtype=torch.float64, device=dev)
-    o = _opts(gram, fact, 1, "materialize", 0.0, 0 if fuse else FLAG_NO_FUSE)
+    o = _opts(gram, fact, 1, "materialize", 0.0,
+              (0 if fuse else FLAG_NO_FUSE) | (FLAG_RANK_REVEAL if rank_reveal else 0))
     it = _lib.borth_iter_info()
     inf = _lib.borth_info()
     if B is None:
@@ -272,7 +277,7 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)
     return (Q, R, (C if ky else None),
-            IterInfo(bool(it.converged), it.passes_run, it.c_norm, it.r_dev),
+            IterInfo(bool(it.converged), it.passes_run, it.c_norm, it.r_dev, it.rank),
             Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run))
 
 

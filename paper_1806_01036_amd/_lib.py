@@ -36,7 +36,8 @@ class borth_block(ctypes.Structure):
 
 
 class borth_iter_info(ctypes.Structure):
-    _fields_ = [("converged", _int), ("passes_run", _int), ("c_norm", _dbl), ("r_dev", _dbl)]
+    _fields_ = [("converged", _int), ("passes_run", _int), ("c_norm", _dbl), ("r_dev", _dbl),
+                ("rank", _int)]
 
 
 EXPORTS = {

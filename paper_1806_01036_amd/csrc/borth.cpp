@@ -608,10 +608,12 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
   it->converged = 0;
   it->passes_run = 0;
   it->c_norm = it->r_dev = 0.0;
+  it->rank = k;
   // Narrow blocks: each update also accumulates the next pass's Gram columns
   // (the fused operations of Sec. 4.2), so after the first pass no separate
   // sweep over the block is made.
   const bool nofuse = (o.flags & BORTH_FLAG_NO_FUSE) != 0;
+  const bool rank_reveal = (o.flags & BORTH_FLAG_RANK_REVEAL) != 0 && o.fact == BORTH_SVQB;
   const bool fuse = !nofuse && k <= 8 && ky + k <= 64 &&
                     (ky == 0 || (ky % 2 == 0 && ldy == ky && ((uintptr_t)Y & 15) == 0));
   bool have_gram = false;  // the Gram of this pass's input is already reduced
@@ -655,6 +657,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     f.Ctot = ws + W.ctot;
     f.status = c->status;
     f.conv = conv;
+    f.rank_reveal = rank_reveal ? 1 : 0;
     if (dd_update) {
       f.Zplo = ws + W.zplo;
       f.Cplo = ws + W.cplo;
@@ -691,7 +694,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
       have_gram = true;
     }
     // stop test: status and the two norms of this pass
-    HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 4, hipMemcpyDeviceToHost,
+    HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 5, hipMemcpyDeviceToHost,
                              c->stream),
            "status readback");
     double hn[2] = {0.0, 0.0};
@@ -700,6 +703,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     it->passes_run = p + 1;
     it->c_norm = hn[0];
     it->r_dev = hn[1];
+    it->rank = rank_reveal ? c->h_status[4] : k;
     if (c->h_status[0] != 0) break;
     if (hn[0] <= eps && hn[1] <= eps) {
       it->converged = 1;

@@ -591,8 +591,12 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     }
     if (!s_flag) break;  // read after the last step's barrier, by every thread
   }
-  // eigenvalues on the diagonal; lift tiny ones
+  // eigenvalues on the diagonal; lift tiny ones, or (rank revealing) keep
+  // those above k u lambda_max in their order: perm[0..rank) kept, the rest
+  // dropped
   __shared__ double lam[64];
+  __shared__ int perm[64];
+  __shared__ int s_rank;
   if (tid == 0) {
     double lmax = 0.0;
     for (int i = 0; i < k; ++i) lmax = fmax(lmax, sM[i * LD + i]);
@@ -602,19 +606,42 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
       if (!(l > floor_)) l = floor_;
       lam[i] = l;
     }
+    int r = 0;
+    if (a.rank_reveal) {
+      const double thr = lmax * k * 0x1p-52;
+      for (int i = 0; i < k; ++i)
+        if (sM[i * LD + i] > thr) perm[r++] = i;
+      int q = r;
+      for (int i = 0; i < k; ++i)
+        if (!(sM[i * LD + i] > thr)) perm[q++] = i;
+    } else {
+      for (int i = 0; i < k; ++i) perm[i] = i;
+      r = k;
+    }
+    s_rank = r;
+    if (a.rank_reveal) a.status[4] = r;  // single-block status words only
   }
   __syncthreads();
+  const int rank = s_rank;
+  // Z and R_p: symmetric U L^{-1/2} U^T and U L^{1/2} U^T, or (rank
+  // revealing) U_r L_r^{-1/2} and L_r^{1/2} U_r^T
+  auto rp_entry = [&](int i, int j) -> double {
+    if (a.rank_reveal) return i < rank ? sqrt(lam[perm[i]]) * sV[j * LD + perm[i]] : 0.0;
+    double r = 0.0;
+    for (int l = 0; l < k; ++l) r = __builtin_fma(sV[i * LD + l] * sV[j * LD + l], sqrt(lam[l]), r);
+    return r;
+  };
   for (int e = tid; e < kp * kp; e += NTF) {
     const int i = e / kp, j = e - i * kp;
-    double z = 0.0, r = 0.0;
+    double z = 0.0;
     if (i < k && j < k) {
-      for (int l = 0; l < k; ++l) {
-        const double w = sV[i * LD + l] * sV[j * LD + l];
-        z = __builtin_fma(w, 1.0 / sqrt(lam[l]), z);
-        r = __builtin_fma(w, sqrt(lam[l]), r);
+      if (a.rank_reveal) {
+        z = j < rank ? sV[i * LD + perm[j]] / sqrt(lam[perm[j]]) : 0.0;
+      } else {
+        for (int l = 0; l < k; ++l) z = __builtin_fma(sV[i * LD + l] * sV[j * LD + l], 1.0 / sqrt(lam[l]), z);
       }
       if (a.Z_out) a.Z_out[i * k + j] = z;
-      if (a.Rp_out) a.Rp_out[i * k + j] = r;
+      if (a.Rp_out) a.Rp_out[i * k + j] = rp_entry(i, j);
     }
     a.Zp[e] = z;
   }
@@ -628,9 +655,7 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
   // R_p into sM (reuse), computed from V and lam
   for (int e = tid; e < k * k; e += NTF) {
     const int i = e / k, j = e - i * k;
-    double r = 0.0;
-    for (int l = 0; l < k; ++l) r = __builtin_fma(sV[i * LD + l] * sV[j * LD + l], sqrt(lam[l]), r);
-    sM[i * LD + j] = r;
+    sM[i * LD + j] = rp_entry(i, j);
   }
   __syncthreads();
   double cnew[16], rnew[16];
@@ -671,7 +696,7 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     double rr = 0.0, cc = 0.0;
     for (int e = tid; e < k * k; e += NTF) {
       const int i = e / k, j = e - i * k;
-      const double d = sM[i * LD + j] - (i == j ? 1.0 : 0.0);
+      const double d = sM[i * LD + j] - (i == j && i < rank ? 1.0 : 0.0);
       rr = __builtin_fma(d, d, rr);
     }
     for (int e = tid; e < ky * k; e += NTF) {
@@ -822,9 +847,15 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
     __syncthreads();
   }
 
-  // Jacobi sweeps in DD
+  // Jacobi sweeps in DD.  Rank revealing after the first pass: the input
+  // is a binary64 Q with r orthonormal columns, whose Gram matrix is I_r + 0
+  // up to binary64 rounding; pairs below that level are not rotated, so
+  // the (nearly equal) kept eigenvalues are not mixed and Q's columns stay
+  // in place (the non-symmetric Z = U_r L_r^{-1/2} is not invariant to such
+  // rotations, unlike the symmetric form).
   const int n = (k + 1) & ~1;
   const int npair = n / 2;
+  const double rot_thr = (a.rank_reveal && a.pass > 0) ? 0x1p-53 : 0x1p-105;
   for (int sweep = 0; sweep < 40; ++sweep) {
     __syncthreads();
     if (tid == 0) s_flag = 0;
@@ -843,7 +874,7 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
         if (qq < k) {
           const dd_t apq = ldm(sMh, sMl, pp, qq);
           const dd_t app = ldm(sMh, sMl, pp, pp), aqq = ldm(sMh, sMl, qq, qq);
-          if (fabs(apq.hi) > 0x1p-105 * sqrt(fabs(app.hi * aqq.hi))) {
+          if (fabs(apq.hi) > rot_thr * sqrt(fabs(app.hi * aqq.hi))) {
             s_flag = 1;
             const dd_t theta = dd_div(A::sub(aqq, app), A::add(apq, apq));
             const dd_t at = theta.hi >= 0 ? theta : dd_neg(theta);
@@ -890,8 +921,11 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
     }
     if (!s_flag) break;
   }
-  // eigenvalues, lifted to 2^-104 lambda_max; their square roots and
-  // reciprocal square roots
+  // eigenvalues, lifted to 2^-104 lambda_max, or (rank revealing) those
+  // above k 2^-104 lambda_max kept in their order (perm[0..rank)); their
+  // square roots and reciprocal square roots
+  __shared__ int perm[64];
+  __shared__ int s_rank;
   if (tid == 0) {
     double lmax = 0.0;
     for (int i = 0; i < k; ++i) lmax = fmax(lmax, sMh[i * LD + i]);
@@ -902,8 +936,23 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
       lh[i] = l.hi;
       ll[i] = l.lo;
     }
+    int r = 0;
+    if (a.rank_reveal) {
+      const double thr = lmax * k * 0x1p-104;
+      for (int i = 0; i < k; ++i)
+        if (sMh[i * LD + i] > thr) perm[r++] = i;
+      int q = r;
+      for (int i = 0; i < k; ++i)
+        if (!(sMh[i * LD + i] > thr)) perm[q++] = i;
+    } else {
+      for (int i = 0; i < k; ++i) perm[i] = i;
+      r = k;
+    }
+    s_rank = r;
+    if (a.rank_reveal) a.status[4] = r;  // single-block status words only
   }
   __syncthreads();
+  const int rank = s_rank;
   if (tid < k) {
     const dd_t l = dd_make(lh[tid], ll[tid]);
     const dd_t rs = A::rsqrt(l), sq_ = A::sqrt_(l);
@@ -919,10 +968,14 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
     const int i = e / kp, j = e - i * kp;
     dd_t z = dd_from(0.0);
     if (i < k && j < k) {
-      Acc<true> az(dd_from(0.0));
-      for (int l = 0; l < k; ++l)
-        az.add(A::mul(ldm(sVh, sVl, i, l), ldm(sVh, sVl, j, l)), dd_make(lrh[l], lrl[l]));
-      z = az.get();
+      if (a.rank_reveal) {
+        if (j < rank) z = A::mul(ldm(sVh, sVl, i, perm[j]), dd_make(lrh[perm[j]], lrl[perm[j]]));
+      } else {
+        Acc<true> az(dd_from(0.0));
+        for (int l = 0; l < k; ++l)
+          az.add(A::mul(ldm(sVh, sVl, i, l), ldm(sVh, sVl, j, l)), dd_make(lrh[l], lrl[l]));
+        z = az.get();
+      }
       if (a.Z_out) a.Z_out[i * k + j] = z.hi;
     }
     const double zr = z.hi + z.lo;
@@ -935,10 +988,14 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
     rv[u] = dd_from(0.0);
     if (e < k * k) {
       const int i = e / k, j = e - i * k;
-      Acc<true> ar(dd_from(0.0));
-      for (int l = 0; l < k; ++l)
-        ar.add(A::mul(ldm(sVh, sVl, i, l), ldm(sVh, sVl, j, l)), dd_make(lsh[l], lsl[l]));
-      rv[u] = ar.get();
+      if (a.rank_reveal) {
+        if (i < rank) rv[u] = A::mul(dd_make(lsh[perm[i]], lsl[perm[i]]), ldm(sVh, sVl, j, perm[i]));
+      } else {
+        Acc<true> ar(dd_from(0.0));
+        for (int l = 0; l < k; ++l)
+          ar.add(A::mul(ldm(sVh, sVl, i, l), ldm(sVh, sVl, j, l)), dd_make(lsh[l], lsl[l]));
+        rv[u] = ar.get();
+      }
       if (a.Rp_out) a.Rp_out[e] = rv[u].hi;
     }
   }
@@ -1007,7 +1064,7 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
     double rr = 0.0, cc = 0.0;
     for (int e = tid; e < k * k; e += NTF) {
       const int i = e / k, j = e - i * k;
-      const double d = sMh[i * LD + j] - (i == j ? 1.0 : 0.0);
+      const double d = sMh[i * LD + j] - (i == j && i < rank ? 1.0 : 0.0);
       rr = __builtin_fma(d, d, rr);
     }
     for (int e = tid; e < ky * k; e += NTF) {

@@ -134,6 +134,9 @@ struct FactorArgs {
   // first order for Y^T Y != I) instead of C, in C_p and in the totals.
   double* Zplo;             // kp x kp, or null
   double* Cplo;             // ky x kp, or null (set together with Zplo)
+  // SVQB: keep only the eigenpairs above k u lambda_max (stable order),
+  // Z = U_r L_r^{-1/2}, R = L_r^{1/2} U_r^T; the rank goes to status[4].
+  int rank_reveal;
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 // One workgroup per entry of the device table `tab` (n entries, all with

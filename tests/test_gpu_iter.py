@@ -132,3 +132,38 @@ def test_iterated_scheme_limits_and_errors():
         borth.orthonormalize_iter(dev(X), dev(Y), gram="split")
     with pytest.raises(borth.BorthError):
         borth.orthonormalize_iter(dev(X), dev(Y), max_iter=0)
+
+
+@pytest.mark.parametrize("gram", ["f64", "dd"])
+@pytest.mark.parametrize("k,ky,deps", [(4, 10, [(3, (0, 1))]), (8, 0, [(2, (0, 5)), (6, (1, 3))]),
+                                       (3, 0, [])])
+def test_iterated_scheme_rank_revealing(gram, k, ky, deps):
+    """SVQB with rank revelation on blocks whose columns are exact linear
+    combinations of others (each (j, (a, b)) sets column j to column a plus
+    column b): the rank is k minus the number of dependent columns, the first
+    rank columns of Q are orthonormal (and orthogonal to Y), the others are
+    zero, X = Y C + Q R still holds, and the stop test converges."""
+    borth = lib()
+    m = 20011
+    X, Y = (synth.projected_pair(m, k, ky, 1e3, 1e3, 3100 + k) if ky
+            else (synth.svd_matrix(m, k, 1e3, 3100 + k), None))
+    X = X.copy()
+    for j, (a, b) in deps:
+        X[:, j] = X[:, a] + X[:, b]
+    Q, R, C, it, info = borth.orthonormalize_iter(dev(X), None if Y is None else dev(Y), gram=gram,
+                                                  fact="svqb", eps=1e-10, max_iter=8,
+                                                  rank_reveal=True)
+    r = k - len(deps)
+    note("rank revealing", gram, k, ky, deps, it)
+    assert info.status == 0 and it.converged and it.rank == r
+    Qh = host(Q)
+    assert np.all(Qh[:, r:] == 0.0)
+    Qr = Qh[:, :r].copy()
+    g = oracle.gram_q(Qr)
+    assert np.linalg.norm(g[0] - np.eye(r) + g[1]) <= 20 * k * U64
+    if ky:
+        gy = oracle.gram_q(Y, Qr)
+        assert np.linalg.norm(gy[0] + gy[1]) <= 1e-14
+    Rh = host(R)
+    res = X - (Y @ host(C) if ky else 0) - Qh @ Rh
+    assert np.linalg.norm(res) <= 1e3 * k * U64 * np.linalg.norm(X)
