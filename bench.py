@@ -39,9 +39,9 @@ FP64_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP64 lane-ops per second (39.3 T
 # device copy of known size, see profiles/dd_cholqr2_4Mx32_hbm_counters.md).
 # Valid only for the kernel sources they were taken on: reported as null once
 # those sources change.
-DD_GRAM_TRAFFIC = {"bytes": 1.0337e9,
+DD_GRAM_TRAFFIC = {"bytes": 1.0383e9,
                    "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
-                   "sha256": "b8a0b90527cbea22b15bb964c30c18d75ca2360171870fb12fc9b0a1a601e1b5"}
+                   "sha256": "2482b2749731fcd63caba5f94f21cea74f71386299b6135ebdf5f19388a4d533"}
 
 
 def measured_traffic(rec):
