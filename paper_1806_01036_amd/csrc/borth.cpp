@@ -604,7 +604,9 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
   double* ws = c->ws;
   const int kp = pow2pad(k);
   double* conv = ws + W.cu;  // two doubles of the spare k x k area
-  HIPCHK(c, launch_fill_int(c->status, 4, 0, c->stream), "fill");
+  // status[5]: the stop word (0 = running; else the number of passes made)
+  HIPCHK(c, launch_fill_int(c->status, 6, 0, c->stream), "fill");
+  int* stop = c->status + 5;
   it->converged = 0;
   it->passes_run = 0;
   it->c_norm = it->r_dev = 0.0;
@@ -619,10 +621,17 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
   bool have_gram = false;  // the Gram of this pass's input is already reduced
   // DD on a narrow block: the updates run in DD as well
   const bool dd_update = dd && k <= 8;
+  // The stop test runs on the device: the factor of the pass that meets it
+  // (or breaks down) sets the stop word, and every kernel of a later pass
+  // returns at once.  Passes are enqueued in chunks with one host
+  // synchronization per chunk instead of one per pass.
+  int chunk_end = max_iter < 3 ? max_iter : 3;
   for (int p = 0; p < max_iter; ++p) {
     const double* S = p == 0 ? X : Q;
     const int64_t lds_ = p == 0 ? ldx : ldq;
     Src src{Y, ldy, S, lds_, 0, m};
+    src.stop = stop;
+    src.pass = p;
     Src gsrc = src;  // the Gram sweeps take B's diagonal
     gsrc.bw = bw;
     if (!have_gram) {
@@ -637,7 +646,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
              "gram");
       prof_end(c, 0);
       HIPCHK(c, launch_reduce(Lg, dd ? 1 : 0, c->part, nwg, ws + W.g_hi, dd ? ws + W.g_lo : nullptr,
-                              c->stream),
+                              c->stream, stop, p),
              "reduce");
     }
     FactorArgs f;
@@ -658,6 +667,8 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     f.status = c->status;
     f.conv = conv;
     f.rank_reveal = rank_reveal ? 1 : 0;
+    f.stop = stop;
+    f.stop_eps = eps;
     if (dd_update) {
       f.Zplo = ws + W.zplo;
       f.Cplo = ws + W.cplo;
@@ -689,26 +700,28 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     prof_end(c, 1);
     if (fuse) {
       HIPCHK(c, launch_reduce(u.glayout, dd ? 1 : 0, c->part, u.nwg, ws + W.g_hi,
-                              dd ? ws + W.g_lo : nullptr, c->stream),
+                              dd ? ws + W.g_lo : nullptr, c->stream, stop, p),
              "reduce (fused)");
       have_gram = true;
     }
-    // stop test: status and the two norms of this pass
-    HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 5, hipMemcpyDeviceToHost,
+    if (p + 1 < chunk_end) continue;
+    // end of a chunk: status, stop word and the norms of the last pass made
+    HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 6, hipMemcpyDeviceToHost,
                              c->stream),
            "status readback");
     double hn[2] = {0.0, 0.0};
     HIPCHK(c, hipMemcpyAsync(hn, conv, sizeof(hn), hipMemcpyDeviceToHost, c->stream), "norms");
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-    it->passes_run = p + 1;
+    const int done = c->h_status[5];
+    it->passes_run = done ? done : p + 1;
     it->c_norm = hn[0];
     it->r_dev = hn[1];
     it->rank = rank_reveal ? c->h_status[4] : k;
-    if (c->h_status[0] != 0) break;
-    if (hn[0] <= eps && hn[1] <= eps) {
-      it->converged = 1;
+    if (done) {
+      it->converged = c->h_status[0] == 0;
       break;
     }
+    chunk_end = p + 3 < max_iter ? p + 3 : max_iter;
   }
   // totals: R = R_j ... R_1 and C (hi words of the DD totals)
   if (R)

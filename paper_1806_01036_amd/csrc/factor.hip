@@ -93,6 +93,7 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
                                                      const FactorArgs* __restrict__ tab) {
   using A = Ar<DD>;
   const FactorArgs a = tab ? tab[blockIdx.x] : one;
+  if (stopped(a.stop, a.pass)) return;
   constexpr int NT = T * T, KP = T * NS, LD = 65;
   constexpr int ND = (64 * KP + NT - 1) / NT;  // per-thread share of a ky x k block
   __shared__ double s_r0[2][64 * LD];  // C (DD) / R_p (DD)
@@ -213,6 +214,7 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
       a.status[0] = 5;
       a.status[1] = a.pass + 1;
       a.status[2] = 0;
+      if (a.stop) a.stop[0] = a.pass + 1;
     }
     zero_out();
     return;
@@ -292,6 +294,7 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
       a.status[0] = 4;
       a.status[1] = a.pass + 1;
       a.status[2] = fail;
+      if (a.stop) a.stop[0] = a.pass + 1;
     }
     zero_out();
     return;
@@ -450,6 +453,8 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
       }
       a.conv[0] = sqrt(sc);
       a.conv[1] = sqrt(sr);
+      // iterated scheme: this pass is the last one when both norms are small
+      if (a.stop && sqrt(sc) <= a.stop_eps && sqrt(sr) <= a.stop_eps) a.stop[0] = a.pass + 1;
     }
   }
   if (tid == 0) a.status[3] = a.pass + 1;
@@ -460,6 +465,7 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
 __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
                                                    const FactorArgs* __restrict__ tab) {
   const FactorArgs a = tab ? tab[blockIdx.x] : one;
+  if (stopped(a.stop, a.pass)) return;
   __shared__ double sM[64 * 65];
   __shared__ double sV[64 * 65];
   __shared__ double sC[64 * 65];
@@ -516,7 +522,12 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     if (!isfinite(sM[(e / k) * LD + e % k])) s_flag = 1;
   __syncthreads();
   if (s_flag) {
-    if (tid == 0) { a.status[0] = 5; a.status[1] = a.pass + 1; a.status[2] = 0; }
+    if (tid == 0) {
+      a.status[0] = 5;
+      a.status[1] = a.pass + 1;
+      a.status[2] = 0;
+      if (a.stop) a.stop[0] = a.pass + 1;
+    }
     for (int e = tid; e < kp * kp; e += NTF) a.Zp[e] = 0.0;
     return;
   }
@@ -715,6 +726,8 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
       }
       a.conv[0] = sqrt(sc);
       a.conv[1] = sqrt(sr);
+      // iterated scheme: this pass is the last one when both norms are small
+      if (a.stop && sqrt(sc) <= a.stop_eps && sqrt(sr) <= a.stop_eps) a.stop[0] = a.pass + 1;
     }
   }
   if (tid == 0) a.status[3] = a.pass + 1;
@@ -732,6 +745,7 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
                                                       const FactorArgs* __restrict__ tab) {
   using A = Ar<true>;
   const FactorArgs a = tab ? tab[blockIdx.x] : one;
+  if (stopped(a.stop, a.pass)) return;
   constexpr int LD = 65;
   constexpr int NE = (64 * 64 + NTF - 1) / NTF;  // per-thread share of a 64 x 64 block
   __shared__ double sMh[64 * LD], sMl[64 * LD], sVh[64 * LD], sVl[64 * LD];
@@ -834,6 +848,7 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
       a.status[0] = 5;
       a.status[1] = a.pass + 1;
       a.status[2] = 0;
+      if (a.stop) a.stop[0] = a.pass + 1;
     }
     zero_out();
     return;
@@ -1083,6 +1098,8 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
       }
       a.conv[0] = sqrt(sc);
       a.conv[1] = sqrt(sr);
+      // iterated scheme: this pass is the last one when both norms are small
+      if (a.stop && sqrt(sc) <= a.stop_eps && sqrt(sr) <= a.stop_eps) a.stop[0] = a.pass + 1;
     }
   }
   if (tid == 0) a.status[3] = a.pass + 1;

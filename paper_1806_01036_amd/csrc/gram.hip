@@ -96,6 +96,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   extern __shared__ double lds[];
   const GramSeg g = BATCH ? tab[wg2seg[blockIdx.x]] : one;
   const Src& s = g.s;
+  if (stopped(s.stop, s.pass)) return;
   const GramLayout& L = g.L;
   const int P = g.P, S = g.S;
   const int64_t npanels = g.nunits;
@@ -273,6 +274,7 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(GramSeg one,
   __shared__ double red[NTL * 4 * 64];
   const GramSeg gs = BATCH ? tab[wg2seg[blockIdx.x]] : one;
   const Src& s = gs.s;
+  if (stopped(s.stop, s.pass)) return;
   const GramLayout& L = gs.L;
   const int64_t ngroups = gs.nunits;
   const int wg = (int)blockIdx.x - gs.wg0;
@@ -363,6 +365,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
                                                       const ReduceSeg* __restrict__ tab) {
   __shared__ double sh[1024], sl[1024];
   const ReduceSeg rs = tab ? tab[blockIdx.y] : one;
+  if (stopped(rs.stop, rs.pass)) return;
   const GramLayout& L = rs.L;
   const double BORTH_GLOBAL* __restrict__ part = gmem(rs.part);
   const int nwg = rs.nwg;
@@ -615,8 +618,8 @@ hipError_t launch_reduce_segs(int mode, int nb, int nseg, const ReduceSeg& one,
 }
 
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
-                         double* G_hi, double* G_lo, hipStream_t st) {
-  ReduceSeg r{L, partials, nwg, G_hi, G_lo};
+                         double* G_hi, double* G_lo, hipStream_t st, const int* stop, int pass) {
+  ReduceSeg r{L, partials, nwg, G_hi, G_lo, stop, pass};
   return launch_reduce_segs(mode, reduce_blocks(L.E), 1, r, nullptr, st);
 }
 

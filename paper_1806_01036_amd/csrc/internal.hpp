@@ -47,7 +47,16 @@ struct Src {
   // Diagonal of B for a B-weighted Gram sweep [Y | X]^T B [Y | X] (m
   // entries), or null (B = I).  Only the VALU tile kernel takes weights.
   const double* bw = nullptr;
+  // Iterated scheme: the kernels of pass `pass` do nothing once *stop is
+  // non-zero and <= pass (set by an earlier pass's factor), or null.
+  const int* stop = nullptr;
+  int pass = 0;
 };
+
+// True when a kernel of pass `pass` is to be skipped (uniform per launch).
+__host__ __device__ inline bool stopped(const int* stop, int pass) {
+  return stop && stop[0] != 0 && pass >= stop[0];
+}
 
 struct TuneGram {
   int nwg;    // workgroups of the sweep (0 = automatic)
@@ -101,9 +110,12 @@ struct ReduceSeg {
   int nwg;
   double* Ghi;
   double* Glo;
+  const int* stop = nullptr;  // as in Src
+  int pass = 0;
 };
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
-                         double* G_hi, double* G_lo, hipStream_t st);
+                         double* G_hi, double* G_lo, hipStream_t st, const int* stop = nullptr,
+                         int pass = 0);
 // Blocks (grid.x) of the reduction of a Gram with E entries.
 int reduce_blocks(int E);
 // nseg segments (grid.y); nb = the largest reduce_blocks(L.E) among them.
@@ -137,6 +149,10 @@ struct FactorArgs {
   // SVQB: keep only the eigenpairs above k u lambda_max (stable order),
   // Z = U_r L_r^{-1/2}, R = L_r^{1/2} U_r^T; the rank goes to status[4].
   int rank_reveal;
+  // Iterated scheme: skip when stopped(stop, pass); after a breakdown, or
+  // (with conv) once both norms are <= stop_eps, set *stop = pass + 1.
+  int* stop;
+  double stop_eps;
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 // One workgroup per entry of the device table `tab` (n entries, all with
@@ -191,6 +207,8 @@ struct UpdDev {
   const double* C1lo;  // low words of C1 and Z1: DD arithmetic (narrow kernel), or null
   const double* Z1lo;
   const double* bw;    // diagonal of B for the narrow kernel's fused Gram, or null
+  const int* stop;     // as in Src
+  int pass;
   int wg0, nwg;
 };
 // Kernel class of an update launch.

@@ -72,6 +72,8 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.C1lo = a.C1lo;
   d.Z1lo = a.Z1lo;
   d.bw = a.bw;
+  d.stop = a.src.stop;
+  d.pass = a.src.pass;
   if (a.bw && !(a.partials && a.gram_xcols)) return hipErrorInvalidValue;
   // DD arithmetic exists in the narrow kernel only
   if ((a.C1lo || a.Z1lo) && (a.two_stage || a.src.x_f32 || !update_narrow_ok(L.k, L.ky, K)))

@@ -86,6 +86,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
                                                      const int* __restrict__ wg2seg) {
   extern __shared__ double lds[];
   const UpdDev a = BATCH ? tab[wg2seg[blockIdx.x]] : one;
+  if (stopped(a.stop, a.pass)) return;
   const int wg = (int)blockIdx.x - a.wg0;
   constexpr int S = KYP + K + 2;     // LDS row stride (doubles)
   constexpr int KC = (K + 15) / 16;  // 16-column blocks of T

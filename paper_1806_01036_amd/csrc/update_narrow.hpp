@@ -80,6 +80,7 @@ inline size_t lds_doubles(int ky, int kn, int gr) {
 template <int KN, int KYB, bool FAST, int GR>
 __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout G) {
   extern __shared__ double pan[];
+  if (stopped(a.stop, a.pass)) return;
   const int lane = threadIdx.x;
   const int ky = a.ky, k = a.k;
   const int SP = row_stride(ky, KN, GR);
