@@ -33,6 +33,10 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP64 lane-ops per second (39.3 T)
+# The DD Gram's algorithmic work per (i <= j) pair and row: the biased
+# accumulation's fma, exact difference, fma for the remainder and add (its
+# once-per-panel fold and the padding of diagonal tiles are overhead).
+DD_GRAM_OPS = 4.0
 
 # HBM bytes per dispatch of the dominant kernel of the default workload, from
 # two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; calibrated on a plain
@@ -150,8 +154,8 @@ def run_c3(args, torch, borth, synth):
     bytes_step = 32.0 * m * k
     gbs = bytes_step / t / 1e9 if om <= 1e-14 else 0.0
     # dominant kernel: the DD Gram sweep, bound by the FP64 vector ALUs.
-    # Algorithmic work: 8 FP64 VALU lane-ops per (i <= j) pair per row.
-    ops = 8.0 * k * (k + 1) / 2 * m
+    # Algorithmic work: DD_GRAM_OPS FP64 VALU lane-ops per (i <= j) pair per row.
+    ops = DD_GRAM_OPS * k * (k + 1) / 2 * m
     achieved = ops / (gram_ms * 1e-3) / 1e12
     out = {
         "metric": "block-orth GB/s (% HBM peak) at ||Q^T Q - I|| <= 1e-14: DD/split vs plain FP64 CholQR",
@@ -309,7 +313,7 @@ def run_c5(args, torch, borth, synth):
     nbytes = sum(8.0 * tt["m"] * (4 * tt["k"] + 3 * ky) for tt in table)
     gbs = nbytes / t / 1e9 if ok else 0.0
     # dominant kernels: the batched DD Gram launches (one per shape class)
-    ops = sum(8.0 * tt["m"] * (ky + tt["k"]) * (ky + tt["k"] + 1) / 2 for tt in table)
+    ops = sum(DD_GRAM_OPS * tt["m"] * (ky + tt["k"]) * (ky + tt["k"] + 1) / 2 for tt in table)
     gram_total_ms = g_ms * g_n
     achieved = ops / (gram_total_ms * 1e-3) / 1e12
     log(f"batch: {t*1e3:.3f} ms/step, {gbs:.1f} GB/s, omega_max={om_max:.2e} "

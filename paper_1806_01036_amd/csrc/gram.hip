@@ -110,11 +110,25 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   int ti, tj;
   decode_tile(t, L, ti, tj);
 
-  double acs[16], acc[16];
+  // BIAS (DD without weights): each panel's sums are accumulated on top of a
+  // power-of-two bias sigma >= 3x the largest sum the panel's rows can reach,
+  // so that the running value never leaves [2 sigma / 3, 4 sigma / 3]: the
+  // rounded sum s' = fma(a, b, s) then gives the exact increment s' - s
+  // (Sterbenz) and the exact rounding error a b - (s' - s) up to one final
+  // rounding -- 4 instructions per product instead of Dot2's 8.  sigma comes
+  // from the panel's column maxima (M_c < 2^E_c: sigma = 2^(E_i + E_j + cb),
+  // 2^cb >= 3 x rows per thread); at the end of the panel the exact sum
+  // acs - sigma is added into the running total th with TwoSum, its error
+  // and the panel's rounding errors go to acc, and (th, acc) is renormalized
+  // so that acc stays below ulp(th).  Panels are twice as tall as in the
+  // other modes (up to 16 load steps) so that the fold is paid over more rows.
+  constexpr bool BIAS = DD && !WB && NTB == 256;
+  double acs[16], acc[16], th[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     acs[e] = 0.0;
     acc[e] = 0.0;
+    th[e] = 0.0;
   }
 
   // Panel loads: thread t owns column lc = t % Wp and rows lr + q RS
@@ -123,7 +137,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   // one stride per thread address all its loads.  The next panel's loads are
   // issued into registers before the current panel is processed, so HBM
   // latency overlaps the arithmetic.
-  constexpr int NQ = 8;
+  constexpr int NQ = BIAS ? 16 : 8;
   const int nq = P / (NT / L.Wp);
   const int RS = NT / L.Wp;
   const int lc = tid % L.Wp, lr = tid / L.Wp;
@@ -165,15 +179,35 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
       }
     }
   };
+  // BIAS: per-column maxima of |V| over the panel, as the bit patterns of
+  // non-negative doubles (ordered like unsigned integers), two buffers
+  // alternating between panels; cb from the rows a thread takes per panel.
+  unsigned long long* cmx = (unsigned long long*)(lds + P * stride);
+  int cb = 0;
+  if (BIAS) {
+    const int np = (P + S - 1) / S;
+    while ((1 << cb) < 3 * np) ++cb;
+    for (int x = tid; x < 2 * L.Wp; x += NT) cmx[x] = 0ull;
+  }
+  int par = 0;
   fetch_panel(wg);
-  for (int64_t pnl = wg; pnl < npanels; pnl += nwg) {
+  for (int64_t pnl = wg; pnl < npanels; pnl += nwg, par ^= 1) {
     __syncthreads();
     if (lr < RS) {
       const int64_t row0 = pnl * P + lr;
+      double mx = 0.0;
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        if (q < nq) lds[(lr + q * RS) * stride + lc] = (ldr && row0 + q * RS < s.m) ? pf[q] : 0.0;
+        if (q < nq) {
+          const double v = (ldr && row0 + q * RS < s.m) ? pf[q] : 0.0;
+          lds[(lr + q * RS) * stride + lc] = v;
+          if (BIAS) mx = fmax(mx, fabs(v));
+        }
+      if (BIAS) atomicMax(&cmx[par * L.Wp + lc], (unsigned long long)__double_as_longlong(mx));
     }
+    // the other buffer is free (its panel's readers passed the barrier above)
+    if (BIAS)
+      for (int x = tid; x < L.Wp; x += NT) cmx[(par ^ 1) * L.Wp + x] = 0ull;
     // the weight of each row sits in the spare column Wp of its LDS row
     if (WB) {
 #pragma unroll
@@ -184,7 +218,49 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
     }
     __syncthreads();
     fetch_panel(pnl + nwg);
-    if (active) {
+    if (BIAS && active) {
+      int ea[4], eb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ea[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[par * L.Wp + 4 * ti + i]));
+        eb[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[par * L.Wp + 4 * tj + i])) + cb;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acs[e] = __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
+#pragma unroll 2
+      for (int r = phase; r < P; r += S) {
+        const double* row = lds + r * stride;
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = row[4 * ti + i];
+          b[i] = row[4 * tj + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int e = 4 * i + j;
+            const double sn = __builtin_fma(a[i], b[j], acs[e]);
+            const double d = sn - acs[e];  // exact
+            acc[e] = acc[e] + __builtin_fma(a[i], b[j], -d);
+            acs[e] = sn;
+          }
+      }
+      // fold: th += acs - sigma (exact difference) with TwoSum.  sigma is
+      // recomputed from the exponents (the empty asm keeps the compiler from
+      // holding 16 sigmas in registers across the row loop instead).
+#pragma unroll
+      for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(ea[i]), "+v"(eb[i]));
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double h = acs[e] - __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
+        const dd_t t = two_sum(th[e], h);
+        const dd_t n = fast_two_sum(t.hi, acc[e] + t.lo);
+        th[e] = n.hi;
+        acc[e] = n.lo;
+      }
+    } else if (active) {
 #pragma unroll 2
       for (int r = phase; r < P; r += S) {
         const double* row = lds + r * stride;
@@ -227,7 +303,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       if (DD) {
-        const dd_t v = dot2_finish(acs[e], acc[e]);
+        const dd_t v = dot2_finish(BIAS ? th[e] : acs[e], acc[e]);
         out[2 * (t * 16 + e)] = v.hi;
         out[2 * (t * 16 + e) + 1] = v.lo;
       } else {
@@ -247,7 +323,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
       for (int e = 0; e < 16; ++e) {
         const int x = t * 16 + e;
         if (DD) {
-          dd_t v = dot2_finish(acs[e], acc[e]);
+          dd_t v = dot2_finish(BIAS ? th[e] : acs[e], acc[e]);
           if (ph > 0) v = dd_add(dd_make(red[2 * x], red[2 * x + 1]), v);
           red[2 * x] = v.hi;
           red[2 * x + 1] = v.lo;
@@ -450,15 +526,20 @@ int gram_kind(const GramLayout& L, int mode, bool weighted) {
 // tiles) up to 256 tiles (Wp <= 88); wider blocks take 1024 threads.
 int gram_tiles_threads(const GramLayout& L) { return L.ntiles <= 256 ? 256 : 1024; }
 
+// The DD tile kernel without weights at 256 threads accumulates on biased
+// sums (see gram_tiles_kernel).
+static bool gram_biased(int mode, const Src& s, int NT) { return mode == 1 && !s.bw && NT == 256; }
+
 // Rows per panel of the tile kernel: nq load steps of NT / Wp rows, nq in
-// 5..8 chosen so that the S = NT / ntiles row phases get equal shares (the
-// fewest idle rows per panel row).
-static int gram_tiles_rows(const GramLayout& L, int NT) {
+// 5..8 (biased DD: 9..16) chosen so that the S = NT / ntiles row phases get
+// equal shares (the fewest idle rows per panel row).
+static int gram_tiles_rows(const GramLayout& L, int NT, bool biased) {
   const int RS = NT / L.Wp, S = NT / L.ntiles;
-  if (RS < 1 || S < 1) return 8 * (RS > 0 ? RS : 1);
-  int best = 8;
+  const int qmax = biased ? 16 : 8, qmin = biased ? 9 : 5;
+  if (RS < 1 || S < 1) return qmax * (RS > 0 ? RS : 1);
+  int best = qmax;
   double best_w = 1e9;
-  for (int nq = 8; nq >= 5; --nq) {
+  for (int nq = qmax; nq >= qmin; --nq) {
     const int P = nq * RS;
     const int per = (P + S - 1) / S;
     const double w = (double)(per * S - P) / P;
@@ -472,7 +553,7 @@ static int gram_tiles_rows(const GramLayout& L, int NT) {
 
 int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
   if (gram_kind(L, mode, s.bw != nullptr) == 0) return (s.m + 3) / 4;
-  const int P = gram_tiles_rows(L, NT);
+  const int P = gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
   return (s.m + P - 1) / P;
 }
 
@@ -497,9 +578,10 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
   if (gram_kind(L, mode, s.bw != nullptr) == 1) {
     g.S = NT / L.ntiles;
     if (g.S < 1 || NT / L.Wp < 1) return false;
-    g.P = gram_tiles_rows(L, NT);
+    g.P = gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
     g.nunits = (s.m + g.P - 1) / g.P;
-    const int panel = g.P * (L.Wp + 2);
+    // biased DD (256 threads): two column-maxima buffers after the panel
+    const int panel = g.P * (L.Wp + 2) + (gram_biased(mode, s, NT) ? 2 * L.Wp : 0);
     const int redn = g.S > 1 ? L.E * (mode ? 2 : 1) : 0;  // one phase: no LDS reduction
     *shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
   }

@@ -4,8 +4,10 @@ Tolerances (derived from the arithmetic, stated per test):
 * binary64 Gram: elementwise |dG_ij| <= gamma_n (|X|^T|X|)_ij with n the
   longest serial accumulation chain of the kernels (rows per accumulator plus
   the fixed reduction tree), and normwise ||dG||_F / ||G||_F <= 1e-14.
-* DD Gram: elementwise |dG_ij| <= gamma_n^2 (|X|^T|X|)_ij + 4u^2 |G_ij| (Dot2
-  bound) and normwise <= 1e-28.
+* DD Gram: elementwise |dG_ij| <= gamma_n^2 (|X|^T|X|)_ij + 4u^2 |G_ij| (the
+  Dot2 bound, which the biased accumulation's per-panel bound
+  (n_p + n_p^2) u^2 sigma also meets at these sizes) and normwise <= 1e-28;
+  at a million rows, max |dG_ij| <= 2e-30 sqrt(G_ii G_jj).
 * update: |dQ_ij| <= (2(k + ky) + 2) u ((|X| + |Y||C|)|Z|)_ij.
 * end to end: reconstruction rho and orthogonality omega <= 1e-14 where the
   method guarantees it; bitwise equality on the exact Hadamard families.
@@ -79,6 +81,28 @@ def test_gram_near_parallel_dd_exact():
     ghi, glo = borth.gram(dev(X), prec="dd")
     ex_hi, ex_lo = oracle.gram_q(X)
     assert np.array_equal(host(ghi), ex_hi) and np.array_equal(host(glo), ex_lo)
+
+
+@pytest.mark.parametrize("m,k,ky", [(1_000_000, 32, 0), (400_000, 4, 40), (250_000, 64, 0)])
+def test_gram_dd_accuracy_large(m, k, ky):
+    """The DD sweep at sizes where every thread folds many panels (biased
+    accumulation, one to many row phases): the error against the exact Gram
+    stays at the double-double level, max |dG_ij| <= 2e-30 sqrt(G_ii G_jj)
+    (measured 2.6e-31 at most, Dot2 about 5e-32), columns graded by 1e-5."""
+    borth = lib()
+    note("gram dd large", m, k, ky)
+    rng = np.random.default_rng(4100 + k + ky)
+    V = rng.standard_normal((m, ky + k))
+    V[:, 1::3] *= 1e-5
+    Y = V[:, :ky] if ky else None
+    ghi, glo = borth.gram(dev(V[:, ky:]), None if Y is None else dev(Y), prec="dd")
+    ex_hi, ex_lo = oracle.gram_q(V)
+    err = np.abs((host(ghi) - ex_hi) + (host(glo) - ex_lo))
+    d = np.sqrt(np.diag(ex_hi))
+    rel = err / np.outer(d, d)
+    note("  max", rel.max(), "rms", np.sqrt(np.mean(rel ** 2)))
+    assert rel.max() <= 2e-30
+    assert np.sqrt(np.mean(rel ** 2)) <= 2e-31
 
 
 def test_gram_split_bf16_vs_oracle():
