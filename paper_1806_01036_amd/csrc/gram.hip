@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   int ti, tj;
   decode_tile(t, L, ti, tj);
 
-  // BIAS (DD without weights): each panel's sums are accumulated on top of a
+  // BIAS (DD, 256 threads): each panel's sums are accumulated on top of a
   // power-of-two bias sigma >= 3x the largest sum the panel's rows can reach,
   // so that the running value never leaves [2 sigma / 3, 4 sigma / 3]: the
   // rounded sum s' = fma(a, b, s) then gives the exact increment s' - s
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   // and the panel's rounding errors go to acc, and (th, acc) is renormalized
   // so that acc stays below ulp(th).  Panels are twice as tall as in the
   // other modes (up to 16 load steps) so that the fold is paid over more rows.
-  constexpr bool BIAS = DD && !WB && NTB == 256;
+  constexpr bool BIAS = DD && NTB == 256;
   double acs[16], acc[16], th[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   // zero for rows beyond m and padding columns is selected there), so the
   // wait for the loads falls after the arithmetic of the current panel.
   double pf[NQ];
-  // WB: weights of panel rows tid and tid + NT (P <= 8 NT / Wp <= 2 NT)
+  // WB: weights of panel rows tid and tid + NT (P <= 2 NT)
   double pfw[2] = {0.0, 0.0};
   const int64_t step = (int64_t)RS * ld;
   auto fetch_panel = [&](int64_t pnl) {
@@ -179,15 +179,17 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
       }
     }
   };
-  // BIAS: per-column maxima of |V| over the panel, as the bit patterns of
-  // non-negative doubles (ordered like unsigned integers), two buffers
-  // alternating between panels; cb from the rows a thread takes per panel.
+  // BIAS: per-column maxima of |V| over the panel (and, WB, of the weights
+  // in slot Wp), as the bit patterns of non-negative doubles (ordered like
+  // unsigned integers), two buffers of CW entries alternating between
+  // panels; cb from the rows a thread takes per panel.
   unsigned long long* cmx = (unsigned long long*)(lds + P * stride);
+  const int CW = L.Wp + 1;
   int cb = 0;
   if (BIAS) {
     const int np = (P + S - 1) / S;
     while ((1 << cb) < 3 * np) ++cb;
-    for (int x = tid; x < 2 * L.Wp; x += NT) cmx[x] = 0ull;
+    for (int x = tid; x < 2 * CW; x += NT) cmx[x] = 0ull;
   }
   int par = 0;
   fetch_panel(wg);
@@ -203,38 +205,64 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
           lds[(lr + q * RS) * stride + lc] = v;
           if (BIAS) mx = fmax(mx, fabs(v));
         }
-      if (BIAS) atomicMax(&cmx[par * L.Wp + lc], (unsigned long long)__double_as_longlong(mx));
+      if (BIAS) atomicMax(&cmx[par * CW + lc], (unsigned long long)__double_as_longlong(mx));
     }
     // the other buffer is free (its panel's readers passed the barrier above)
     if (BIAS)
-      for (int x = tid; x < L.Wp; x += NT) cmx[(par ^ 1) * L.Wp + x] = 0ull;
+      for (int x = tid; x < CW; x += NT) cmx[(par ^ 1) * CW + x] = 0ull;
     // the weight of each row sits in the spare column Wp of its LDS row
     if (WB) {
+      double mw = 0.0;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int t = tid + h * NT;
-        if (t < P) lds[t * stride + L.Wp] = pnl * P + t < s.m ? pfw[h] : 0.0;
+        if (t < P) {
+          const double w = pnl * P + t < s.m ? pfw[h] : 0.0;
+          lds[t * stride + L.Wp] = w;
+          mw = fmax(mw, fabs(w));
+        }
       }
+      if (BIAS && tid < P) atomicMax(&cmx[par * CW + L.Wp], (unsigned long long)__double_as_longlong(mw));
     }
     __syncthreads();
     fetch_panel(pnl + nwg);
     if (BIAS && active) {
+      // WB: |w b_j| <= M_w M_j with M_w <= 2^ew (ew = ceil(log2 M_w): 0 for
+      // unit weights, which then take exactly the unweighted path's sigma)
+      int ew = 0;
+      if (WB) {
+        const double mw = __longlong_as_double((long long)cmx[par * CW + L.Wp]);
+        ew = __builtin_amdgcn_frexp_exp(mw);
+        if (__builtin_amdgcn_frexp_mant(mw) == 0.5) --ew;
+      }
       int ea[4], eb[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        ea[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[par * L.Wp + 4 * ti + i]));
-        eb[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[par * L.Wp + 4 * tj + i])) + cb;
+        ea[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[par * CW + 4 * ti + i]));
+        eb[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[par * CW + 4 * tj + i])) + cb + ew;
       }
 #pragma unroll
       for (int e = 0; e < 16; ++e) acs[e] = __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
-#pragma unroll 2
+      // two rows per trip (the new sums alternate register sets, no copies);
+      // one with weights, whose split products need the registers
+      constexpr int UNR = WB ? 1 : 2;
+#pragma unroll UNR
       for (int r = phase; r < P; r += S) {
         const double* row = lds + r * stride;
-        double a[4], b[4];
+        double a[4], b[4], bl[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           a[i] = row[4 * ti + i];
           b[i] = row[4 * tj + i];
+        }
+        if (WB) {
+          const double w = row[L.Wp];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double h = b[j] * w;
+            bl[j] = __builtin_fma(b[j], w, -h);  // w b_j = h + bl exactly
+            b[j] = h;
+          }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -244,6 +272,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
             const double sn = __builtin_fma(a[i], b[j], acs[e]);
             const double d = sn - acs[e];  // exact
             acc[e] = acc[e] + __builtin_fma(a[i], b[j], -d);
+            if (WB) acc[e] = __builtin_fma(a[i], bl[j], acc[e]);
             acs[e] = sn;
           }
       }
@@ -526,16 +555,22 @@ int gram_kind(const GramLayout& L, int mode, bool weighted) {
 // tiles) up to 256 tiles (Wp <= 88); wider blocks take 1024 threads.
 int gram_tiles_threads(const GramLayout& L) { return L.ntiles <= 256 ? 256 : 1024; }
 
-// The DD tile kernel without weights at 256 threads accumulates on biased
-// sums (see gram_tiles_kernel).
-static bool gram_biased(int mode, const Src& s, int NT) { return mode == 1 && !s.bw && NT == 256; }
+// The DD tile kernel at 256 threads accumulates on biased sums (see
+// gram_tiles_kernel).
+static bool gram_biased(int mode, const Src& s, int NT) {
+  (void)s;
+  return mode == 1 && NT == 256;
+}
 
 // Rows per panel of the tile kernel: nq load steps of NT / Wp rows, nq in
-// 5..8 (biased DD: 9..16) chosen so that the S = NT / ntiles row phases get
-// equal shares (the fewest idle rows per panel row).
+// 5..8 (biased DD: 9..16, at most 2 NT rows) chosen so that the S = NT /
+// ntiles row phases get equal shares (the fewest idle rows per panel row).
 static int gram_tiles_rows(const GramLayout& L, int NT, bool biased) {
   const int RS = NT / L.Wp, S = NT / L.ntiles;
-  const int qmax = biased ? 16 : 8, qmin = biased ? 9 : 5;
+  // biased: at most 2 NT rows (each thread stages the weights of two rows)
+  const int q2 = RS > 0 ? 2 * NT / RS : 16;
+  const int qmax = biased ? (q2 < 16 ? q2 : 16) : 8;
+  const int qmin = biased ? (qmax < 9 ? qmax : 9) : 5;
   if (RS < 1 || S < 1) return qmax * (RS > 0 ? RS : 1);
   int best = qmax;
   double best_w = 1e9;
@@ -581,7 +616,7 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
     g.P = gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
     g.nunits = (s.m + g.P - 1) / g.P;
     // biased DD (256 threads): two column-maxima buffers after the panel
-    const int panel = g.P * (L.Wp + 2) + (gram_biased(mode, s, NT) ? 2 * L.Wp : 0);
+    const int panel = g.P * (L.Wp + 2) + (gram_biased(mode, s, NT) ? 2 * (L.Wp + 1) : 0);
     const int redn = g.S > 1 ? L.E * (mode ? 2 : 1) : 0;  // one phase: no LDS reduction
     *shmem = sizeof(double) * (size_t)(panel > redn ? panel : redn);
   }
