@@ -43,9 +43,9 @@ DD_GRAM_OPS = 4.0
 # device copy of known size, see profiles/dd_cholqr2_4Mx32_hbm_counters.md).
 # Valid only for the kernel sources they were taken on: reported as null once
 # those sources change.
-DD_GRAM_TRAFFIC = {"bytes": 1.0383e9,
+DD_GRAM_TRAFFIC = {"bytes": 1.0337e9,
                    "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
-                   "sha256": "2482b2749731fcd63caba5f94f21cea74f71386299b6135ebdf5f19388a4d533"}
+                   "sha256": "1c5f71acdd06def5c003cf884b4233fd321cb17863db1bf016dc1ee58ff86f76"}
 
 
 def measured_traffic(rec):
@@ -426,10 +426,12 @@ def run_fig7(args, torch, borth, synth):
     the shape of the paper's accuracy experiment (Fig. 7): n = 1000 rows,
     k_y = 20 locked vectors, n_b = 4 new ones.  Left: ||Y^T Q|| against
     kappa(X, Y) at kappa(X) in {1, 1e3}; right: ||Q^T Q - I|| against kappa(X)
-    at kappa(X, Y) = kappa(X).  Variants: binary64 Gram with SVQB; DD Gram,
-    DD Cholesky and DD update."""
+    at kappa(X, Y) = kappa(X).  Variants: binary64 Gram with SVQB; DD Gram
+    (biased accumulation) with DD SVQB or DD Cholesky and DD update; the
+    latter with the Dot2 accumulation."""
     n, ky, k = 1000, 20, 4
-    variants = {"f64_svqb": ("f64", "svqb"), "dd_svqb": ("dd", "svqb"), "dd_chol": ("dd", "chol")}
+    variants = {"f64_svqb": ("f64", "svqb"), "dd_svqb": ("dd", "svqb"), "dd_chol": ("dd", "chol"),
+                "dd_chol_dot2": ("dd_dot2", "chol")}
     rows = []
 
     def one(kx, kxy, seed):

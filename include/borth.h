@@ -64,9 +64,24 @@ typedef enum { BORTH_F64 = 0, BORTH_F32 = 1 } borth_dtype;
 /* Precision of the first pass's Gram accumulation (later passes: binary64). */
 typedef enum {
   BORTH_GRAM_F64 = 0,        /* binary64 FMAs on the matrix cores (k >= 16) or VALU */
-  BORTH_GRAM_DD = 1,         /* double-double: Dot2-style TwoSum/TwoProduct, DD k x k step */
-  BORTH_GRAM_SPLIT_BF16 = 2  /* X in fp32: (hi, lo) bf16 split, MFMA with fp32 accumulation */
+  BORTH_GRAM_DD = 1,         /* double-double Gram (see "DD accumulation" below), DD k x k step */
+  BORTH_GRAM_SPLIT_BF16 = 2, /* X in fp32: (hi, lo) bf16 split, MFMA with fp32 accumulation */
+  BORTH_GRAM_DD_DOT2 = 3     /* borth_gram only: BORTH_GRAM_DD with the Dot2 accumulation */
 } borth_gram_prec;
+
+/* DD accumulation.  A double-double Gram sweep (Sec. 4.2's extended-precision
+ * Gram matrix) accumulates each product error-free in one of two ways:
+ *   biased (default): every sum of a row panel runs on a power-of-two bias
+ *     sigma > 2 x (rows per thread) x max|a| max|b| of the panel, so that the
+ *     rounded sum's increment and the product's remainder are exact up to one
+ *     rounding of u ulp(sigma): 4 VALU instructions per product, error per
+ *     panel and thread about rows x u^2 sigma (~1e-31 relative to
+ *     sqrt(G_ii G_jj) where few panels are summed, 5e-32 at millions of rows);
+ *   Dot2 (BORTH_FLAG_DD_DOT2, BORTH_GRAM_DD_DOT2): TwoProduct and TwoSum,
+ *     8 instructions per product, error about u^2 |G| per thread (~2e-32).
+ * The narrow update's fused Gram columns (k <= 8) always use Dot2; sweeps
+ * weighted by B (borth_orthonormalize_iter_b) always use the biased sums;
+ * blocks wider than 88 columns always use Dot2. */
 
 typedef enum { BORTH_CHOL = 0, BORTH_SVQB = 1 } borth_fact;
 
@@ -82,6 +97,7 @@ typedef enum {
 #define BORTH_FLAG_GRAPH 4u         /* capture the launch sequence in a cached hipGraph */
 #define BORTH_FLAG_NO_FUSE 8u       /* iterated scheme: a separate Gram sweep in every pass */
 #define BORTH_FLAG_RANK_REVEAL 16u  /* iterated scheme, SVQB: drop null directions (see below) */
+#define BORTH_FLAG_DD_DOT2 32u      /* DD Gram sweeps accumulate with Dot2 (see above) */
 
 typedef struct {
   int gram;       /* borth_gram_prec of pass 1 */
@@ -120,9 +136,10 @@ borth_status borth_get_info(borth_ctx ctx, borth_info* info);
  * coefficients "C = W^T X", Sec. 4.2): with V = [A | B] (m x (ka + kb)),
  *     G = V^T V   (W x W, W = ka + kb <= 128, symmetric, both halves written).
  * A: binary64 (may be NULL with ka = 0).  B: `dt_b` (BORTH_F32 only with
- * prec = BORTH_GRAM_SPLIT_BF16 and ka = 0).  prec BORTH_GRAM_DD writes the
- * low words to G_lo (device, W x W); G_lo may be NULL otherwise.  The
- * summation order is fixed: results are bitwise reproducible. */
+ * prec = BORTH_GRAM_SPLIT_BF16 and ka = 0).  prec BORTH_GRAM_DD (biased
+ * accumulation) or BORTH_GRAM_DD_DOT2 writes the low words to G_lo (device,
+ * W x W); G_lo may be NULL otherwise.  The summation order is fixed: results
+ * are bitwise reproducible. */
 borth_status borth_gram(borth_ctx ctx, int64_t m, int ka, const double* A, int64_t lda,
                         int kb, borth_dtype dt_b, const void* B, int64_t ldb, int prec,
                         double* G_hi, double* G_lo);

@@ -23,10 +23,13 @@ __all__ = [
     "SCHED",
 ]
 
-GRAM = {"f64": 0, "dd": 1, "split": 2}
+# "dd": DD Gram with the biased accumulation; "dd_dot2": DD Gram with Dot2
+# (borth_gram's BORTH_GRAM_DD_DOT2, elsewhere BORTH_GRAM_DD + BORTH_FLAG_DD_DOT2)
+GRAM = {"f64": 0, "dd": 1, "split": 2, "dd_dot2": 3}
 FACT = {"chol": 0, "svqb": 1}
 SCHED = {"auto": 0, "materialize": 1, "recompute": 2}
 FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH, FLAG_NO_FUSE, FLAG_RANK_REVEAL = 1, 2, 4, 8, 16
+FLAG_DD_DOT2 = 32
 OK, ERR_ARG, ERR_HIP, ERR_NOMEM, BREAKDOWN, NONFINITE, UNSUPPORTED = range(7)
 
 
@@ -144,14 +147,15 @@ def _dt(t):
 
 
 def gram(B, A=None, prec="f64", ctx=None):
-    """G = [A | B]^T [A | B] (hi, lo); lo is None unless prec == 'dd'."""
+    """G = [A | B]^T [A | B] (hi, lo); lo is None unless prec is 'dd' or 'dd_dot2'."""
     torch = _torch()
     ctx = ctx or default_context(B.device.index)
     m, kb = B.shape
     ka = 0 if A is None else A.shape[1]
     W = ka + kb
     ghi = torch.empty((W, W), dtype=torch.float64, device=B.device)
-    glo = torch.empty((W, W), dtype=torch.float64, device=B.device) if prec == "dd" else None
+    glo = (torch.empty((W, W), dtype=torch.float64, device=B.device)
+           if prec in ("dd", "dd_dot2") else None)
     ctx.check(ctx.lib.borth_gram(ctx.h, m, ka, _ptr(A), _ld(A) if A is not None else ka, kb,
                                  _dt(B), _ptr(B), _ld(B), GRAM[prec], _ptr(ghi), _ptr(glo)))
     return ghi, glo
@@ -194,6 +198,9 @@ def update(X, Z, Y=None, C=None, dense=False, out=None, ctx=None):
 def _opts(gram, fact, passes, sched, shift, flags):
     o = _lib.borth_opts()
     o.gram = GRAM[gram]
+    if gram == "dd_dot2":
+        o.gram = GRAM["dd"]
+        flags |= FLAG_DD_DOT2
     o.fact = FACT[fact]
     o.passes = int(passes)
     o.sched = SCHED[sched]

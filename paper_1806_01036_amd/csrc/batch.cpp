@@ -282,6 +282,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
     size_t shmem = 0;
     for (int b : g.blocks) {
       Src s{B[b].Y, B[b].ldy, B[b].X, B[b].ldx, 0, B[b].m};
+      s.dot2 = (o.flags & BORTH_FLAG_DD_DOT2) ? 1 : 0;
       GramSeg gs;
       size_t sh = 0;
       if (!gram_seg(s, L1[b], gmode, NT, part + W[b].part, (int)map.size(), nwg_g[b], &gs, &sh))

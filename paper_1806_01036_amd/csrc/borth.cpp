@@ -145,6 +145,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
 
   // ---- pass 1: Gram sweep + reduction + factor
   Src s1{a.Y, a.ldy, a.X, a.ldx, a.dt == BORTH_F32 ? 1 : 0, a.m};
+  s1.dot2 = (a.o.flags & BORTH_FLAG_DD_DOT2) ? 1 : 0;
   GramLayout L1 = make_layout(a.ky, a.k, 4);
   int nwg = 0;
   prof_begin(c, 0);
@@ -404,10 +405,10 @@ borth_status borth_gram(borth_ctx c, int64_t m, int ka, const double* A, int64_t
   if (m < 0 || ka < 0 || kb < 1 || ka + kb > 128 || !B || !G_hi) return fail_arg(c, "shape/pointers");
   if (ka > 0 && (!A || lda < ka)) return fail_arg(c, "A");
   if (ldb < kb) return fail_arg(c, "ldb");
-  if (prec < 0 || prec > 2) return fail_arg(c, "prec");
+  if (prec < 0 || prec > 3) return fail_arg(c, "prec");
   if (prec == BORTH_GRAM_SPLIT_BF16 && (dt_b != BORTH_F32 || ka != 0 || kb > 64))
     return fail_arg(c, "split mode needs fp32 B, no A, kb <= 64");
-  if (prec != BORTH_GRAM_SPLIT_BF16 && dt_b == BORTH_F32 && prec == BORTH_GRAM_DD)
+  if (dt_b == BORTH_F32 && (prec == BORTH_GRAM_DD || prec == BORTH_GRAM_DD_DOT2))
     return fail_arg(c, "DD Gram needs binary64 input");
   hipSetDevice(c->device);
   c->cur = c->stream;
@@ -430,7 +431,8 @@ borth_status borth_gram(borth_ctx c, int64_t m, int ka, const double* A, int64_t
     HIPCHK(c, launch_reduce(L, 0, c->part, nwg, G_hi, G_lo, c->stream), "reduce");
   } else {
     Src s{A, lda, B, ldb, dt_b == BORTH_F32 ? 1 : 0, m};
-    const int mode = prec == BORTH_GRAM_DD ? 1 : 0;
+    s.dot2 = prec == BORTH_GRAM_DD_DOT2 ? 1 : 0;
+    const int mode = prec == BORTH_GRAM_DD || prec == BORTH_GRAM_DD_DOT2 ? 1 : 0;
     prof_begin(c, 0);
     HIPCHK(c, launch_gram(s, L, mode, c->part, c->part_cap, &nwg, lookup(c->tune_gram, mode, kp, ka > 0), c->stream), "gram");
     prof_end(c, 0);
@@ -634,6 +636,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     src.pass = p;
     Src gsrc = src;  // the Gram sweeps take B's diagonal
     gsrc.bw = bw;
+    gsrc.dot2 = (o.flags & BORTH_FLAG_DD_DOT2) ? 1 : 0;
     if (!have_gram) {
       int nwg = 0;
       // Y does not change between passes: after the first, only the columns

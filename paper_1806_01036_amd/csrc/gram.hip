@@ -111,18 +111,24 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   decode_tile(t, L, ti, tj);
 
   // BIAS (DD, 256 threads): each panel's sums are accumulated on top of a
-  // power-of-two bias sigma >= 3x the largest sum the panel's rows can reach,
-  // so that the running value never leaves [2 sigma / 3, 4 sigma / 3]: the
-  // rounded sum s' = fma(a, b, s) then gives the exact increment s' - s
+  // power-of-two bias sigma > 2x the largest sum B the thread's rows of the
+  // panel can reach (plus one product), so that the running value stays in
+  // [sigma - B, sigma + B] and consecutive values are within a factor 1.5:
+  // the rounded sum s' = fma(a, b, s) then gives the exact increment s' - s
   // (Sterbenz) and the exact rounding error a b - (s' - s) up to one final
-  // rounding -- 4 instructions per product instead of Dot2's 8.  sigma comes
-  // from the panel's column maxima (M_c < 2^E_c: sigma = 2^(E_i + E_j + cb),
-  // 2^cb >= 3 x rows per thread); at the end of the panel the exact sum
-  // acs - sigma is added into the running total th with TwoSum, its error
-  // and the panel's rounding errors go to acc, and (th, acc) is renormalized
-  // so that acc stays below ulp(th).  Panels are twice as tall as in the
-  // other modes (up to 16 load steps) so that the fold is paid over more rows.
+  // rounding of at most u ulp(sigma) -- 4 instructions per product instead
+  // of Dot2's 8.  sigma comes from the panel's column maxima (M_c < 2^E_c:
+  // sigma = 2^(E_i + E_j + cb), 2^cb >= 2 x rows per thread + 1); at the end
+  // of the panel the exact sum acs - sigma is added into the running total th
+  // with TwoSum, its error and the panel's rounding errors go to acc, and
+  // (th, acc) is renormalized so that acc stays below ulp(th).  The panel
+  // height is chosen on the host for a small 2^cb (the rounding error per
+  // product scales with sigma) and few idle rows.
   constexpr bool BIAS = DD && NTB == 256;
+  // the caller may ask for Dot2 instead (uniform per launch); the weighted
+  // sweep always runs biased (both loops in one kernel would not fit two
+  // waves per SIMD)
+  const bool biased = BIAS && (WB || !s.dot2);
   double acs[16], acc[16], th[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -188,7 +194,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   int cb = 0;
   if (BIAS) {
     const int np = (P + S - 1) / S;
-    while ((1 << cb) < 3 * np) ++cb;
+    while ((1 << cb) < 2 * np + 1) ++cb;
     for (int x = tid; x < 2 * CW; x += NT) cmx[x] = 0ull;
   }
   int par = 0;
@@ -226,7 +232,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
     }
     __syncthreads();
     fetch_panel(pnl + nwg);
-    if (BIAS && active) {
+    if (biased && active) {
       // WB: |w b_j| <= M_w M_j with M_w <= 2^ew (ew = ceil(log2 M_w): 0 for
       // unit weights, which then take exactly the unweighted path's sigma)
       int ew = 0;
@@ -332,7 +338,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       if (DD) {
-        const dd_t v = dot2_finish(BIAS ? th[e] : acs[e], acc[e]);
+        const dd_t v = dot2_finish(biased ? th[e] : acs[e], acc[e]);
         out[2 * (t * 16 + e)] = v.hi;
         out[2 * (t * 16 + e) + 1] = v.lo;
       } else {
@@ -352,7 +358,7 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
       for (int e = 0; e < 16; ++e) {
         const int x = t * 16 + e;
         if (DD) {
-          dd_t v = dot2_finish(BIAS ? th[e] : acs[e], acc[e]);
+          dd_t v = dot2_finish(biased ? th[e] : acs[e], acc[e]);
           if (ph > 0) v = dd_add(dd_make(red[2 * x], red[2 * x + 1]), v);
           red[2 * x] = v.hi;
           red[2 * x + 1] = v.lo;
@@ -570,14 +576,31 @@ static int gram_tiles_rows(const GramLayout& L, int NT, bool biased) {
   // biased: at most 2 NT rows (each thread stages the weights of two rows)
   const int q2 = RS > 0 ? 2 * NT / RS : 16;
   const int qmax = biased ? (q2 < 16 ? q2 : 16) : 8;
-  const int qmin = biased ? (qmax < 9 ? qmax : 9) : 5;
+  const int qmin = qmax < 5 ? qmax : 5;
   if (RS < 1 || S < 1) return qmax * (RS > 0 ? RS : 1);
+  auto cbits = [](int per) {
+    int c = 0;
+    while ((1 << c) < 2 * per + 1) ++c;
+    return c;
+  };
+  // biased: the smallest bias exponent reachable with at least 8 rows per
+  // thread (24 with a single row phase, whose panels are short), then the
+  // estimated time: idle rows and one fold per panel (about 3 rows' work)
+  const int pmin = S == 1 ? 24 : 8;
+  int cmin = 99;
+  if (biased)
+    for (int nq = qmax; nq >= qmin; --nq) {
+      const int per = (nq * RS + S - 1) / S;
+      if (per >= pmin || nq == qmax) cmin = cbits(per) < cmin ? cbits(per) : cmin;
+    }
   int best = qmax;
   double best_w = 1e9;
-  for (int nq = qmax; nq >= qmin; --nq) {
+  for (int nq = qmax; nq >= (biased ? qmin : 5); --nq) {
     const int P = nq * RS;
     const int per = (P + S - 1) / S;
-    const double w = (double)(per * S - P) / P;
+    if (biased && (cbits(per) > cmin || (per < pmin && nq != qmax))) continue;
+    const double idle = (double)(per * S - P) / P;
+    const double w = biased ? (1.0 + idle) * (1.0 + 3.0 / per) : idle;
     if (w < best_w - 1e-12) {
       best_w = w;
       best = nq;

@@ -51,6 +51,8 @@ struct Src {
   // non-zero and <= pass (set by an earlier pass's factor), or null.
   const int* stop = nullptr;
   int pass = 0;
+  // DD tile sweeps: accumulate with Dot2 instead of the biased sums.
+  int dot2 = 0;
 };
 
 // True when a kernel of pass `pass` is to be skipped (uniform per launch).

@@ -25,7 +25,8 @@ N, KY, K = 1000, 20, 4
 
 
 def one_pass(borth, X, Y, variant):
-    gram, fact = {"f64": ("f64", "svqb"), "dd": ("dd", "chol"), "dd_svqb": ("dd", "svqb")}[variant]
+    gram, fact = {"f64": ("f64", "svqb"), "dd": ("dd", "chol"), "dd_svqb": ("dd", "svqb"),
+                  "dd_dot2": ("dd_dot2", "chol")}[variant]
     Q, R, C, info = borth.orthonormalize(dev(X), dev(Y), gram=gram, fact=fact, passes=1)
     assert info.status == 0
     met = oracle.metrics(host(Q), X, host(R), Y, host(C))
@@ -94,3 +95,19 @@ def test_fig7_dd_pass_vs_oracle(kx, kxy):
     dc = np.max(np.abs(host(C) - Co)) / np.max(np.abs(Co))
     note("dd pass vs oracle", kx, kxy, dq, dr, dc)
     assert dq <= 8 * U64 and dr <= 8 * U64 and dc <= 8 * U64
+
+
+@pytest.mark.parametrize("kxy", [1e9, 1e12])
+def test_fig7_dd_accumulations(kxy):
+    """One DD pass with X close to span(Y): omega grows like eps_G kappa(X, Y)^2
+    with eps_G the DD Gram's relative error -- about 1e-31 with Dot2, a few
+    times 1e-31 with the biased accumulation (measured 7e-32 and 4e-31 to
+    9e-31 at kappa(X, Y) = 1e12)."""
+    borth = lib()
+    X, Y = synth.projected_pair(N, K, KY, 1.0, kxy, 7800 + int(np.log10(kxy)))
+    lv = {v: one_pass(borth, X, Y, v) for v in ("dd", "dd_dot2")}
+    note("dd accumulations", kxy, {v: lv[v]["omega"] for v in lv})
+    assert lv["dd_dot2"]["omega"] <= 5e-31 * kxy ** 2
+    assert lv["dd"]["omega"] <= 5e-30 * kxy ** 2
+    for v in lv:
+        assert lv[v]["omega_y"] <= 1e-15

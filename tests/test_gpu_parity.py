@@ -36,7 +36,7 @@ def chain(m):
 @pytest.mark.parametrize("m,k,ky", [(5003, 4, 0), (5003, 8, 0), (5003, 16, 0), (5003, 20, 0),
                                     (7001, 32, 0), (7001, 64, 0), (5003, 8, 5), (6007, 32, 16),
                                     (3001, 64, 16), (1, 3, 0), (17, 1, 0)])
-@pytest.mark.parametrize("prec", ["f64", "dd"])
+@pytest.mark.parametrize("prec", ["f64", "dd", "dd_dot2"])
 def test_gram_vs_oracle(m, k, ky, prec):
     borth = lib()
     note("gram", m, k, ky, prec)
@@ -103,6 +103,26 @@ def test_gram_dd_accuracy_large(m, k, ky):
     note("  max", rel.max(), "rms", np.sqrt(np.mean(rel ** 2)))
     assert rel.max() <= 2e-30
     assert np.sqrt(np.mean(rel ** 2)) <= 2e-31
+
+
+@pytest.mark.parametrize("kxy", [1e9, 1e12])
+def test_gram_dd_accumulations_near_span(kxy):
+    """X close to span(Y) on the paper's accuracy-experiment shape (1000 x
+    [20 | 4]): few panels are summed, so the per-panel error of the biased
+    accumulation shows.  Against the exact Gram: Dot2 stays at a few u^2
+    (measured 2.5e-32 relative to sqrt(G_ii G_jj)), the biased sums at the
+    rows x u^2 sigma level (measured 5e-31)."""
+    borth = lib()
+    for rep in range(3):
+        X, Y = synth.projected_pair(1000, 4, 20, 1.0, kxy, 7700 + rep)
+        V = np.hstack([Y, X])
+        ex_hi, ex_lo = oracle.gram_q(V)
+        d = np.sqrt(np.diag(ex_hi))
+        for prec, bound in (("dd_dot2", 2e-31), ("dd", 4e-30)):
+            ghi, glo = borth.gram(dev(X), dev(Y), prec=prec)
+            rel = np.abs((host(ghi) - ex_hi) + (host(glo) - ex_lo)) / np.outer(d, d)
+            note("near span", kxy, rep, prec, rel.max())
+            assert rel.max() <= bound
 
 
 def test_gram_split_bf16_vs_oracle():
