@@ -98,6 +98,7 @@ typedef enum {
 #define BORTH_FLAG_NO_FUSE 8u       /* iterated scheme: a separate Gram sweep in every pass */
 #define BORTH_FLAG_RANK_REVEAL 16u  /* iterated scheme, SVQB: drop null directions (see below) */
 #define BORTH_FLAG_DD_DOT2 32u      /* DD Gram sweeps accumulate with Dot2 (see above) */
+#define BORTH_FLAG_AUTO_ESCALATE 64u /* borth_orthonormalize: repeat after a breakdown (below) */
 
 typedef struct {
   int gram;       /* borth_gram_prec of pass 1 */
@@ -114,6 +115,19 @@ typedef struct {
   int failed_pass;  /* 1-based pass of a breakdown, 0 if none */
   int failed_pivot; /* 1-based Cholesky pivot (LAPACK potrf style), 0 if none */
   int passes_run;
+  /* Estimates from the factors (single-block calls; 0 in batched calls and
+   * from borth_factor):
+   *   orth_est  ||R_p - I||_F of the last pass p (SVQB: its symmetric
+   *             factor): how far that pass's input was from orthonormal
+   *             (||Q_{p-1}^T Q_{p-1} - I||_F is about twice it); when it is
+   *             far below 1 the result is orthonormal to O(k u);
+   *   kappa_est from the first pass: max R_ii / min R_ii (Cholesky; a lower
+   *             bound on kappa of the projected X) or sqrt(lambda_max /
+   *             lambda_min) of its Gram matrix (SVQB, eigenvalues lifted to
+   *             u lambda_max, or 2^-104 lambda_max in DD). */
+  double orth_est;
+  double kappa_est;
+  int escalation;   /* BORTH_FLAG_AUTO_ESCALATE: 0 none, 1 DD Gram, 2 shifted DD */
 } borth_info;
 
 /* Fills *opts with the defaults: DD Gram, Cholesky, 2 passes, automatic
@@ -173,7 +187,18 @@ borth_status borth_update(borth_ctx ctx, int64_t m, int k, borth_dtype dt, const
  * the schedule is MATERIALIZE), R: k x k (R_p ... R_1, device, may be NULL),
  * C: ky x k total coefficients (device, may be NULL).  opts may be NULL
  * (defaults).  info (host) may be NULL; non-NULL synchronizes.  Returns the
- * numerical status when it synchronizes, else BORTH_OK once enqueued. */
+ * numerical status when it synchronizes, else BORTH_OK once enqueued.
+ *
+ * BORTH_FLAG_AUTO_ESCALATE (binary64 X, Q not aliasing X; synchronizes):
+ * after a breakdown the call is repeated, first with the DD Gram (if the
+ * binary64 one broke down), then with the DD Gram, a first-pass shift of
+ * 11 (m k + k (k + 1)) 2^-104 trace(M) and three passes (shifted CholQR3
+ * with a DD Gram; the shift keeps the Cholesky of the first pass away from
+ * breakdown up to about kappa = 1e20).  info->escalation tells which
+ * attempt succeeded; R and C are those of the last attempt.
+ *
+ * The environment variable BORTH_LOG=1 prints one line per call to stderr
+ * (shape, options and, when the call synchronizes, status and estimates). */
 borth_status borth_orthonormalize(borth_ctx ctx, int64_t m, int k, borth_dtype dt,
                                   const void* X, int64_t ldx, const double* Y, int64_t ldy,
                                   int ky, double* Q, int64_t ldq, double* R, double* C,

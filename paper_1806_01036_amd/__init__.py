@@ -29,7 +29,7 @@ GRAM = {"f64": 0, "dd": 1, "split": 2, "dd_dot2": 3}
 FACT = {"chol": 0, "svqb": 1}
 SCHED = {"auto": 0, "materialize": 1, "recompute": 2}
 FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH, FLAG_NO_FUSE, FLAG_RANK_REVEAL = 1, 2, 4, 8, 16
-FLAG_DD_DOT2 = 32
+FLAG_DD_DOT2, FLAG_AUTO_ESCALATE = 32, 64
 OK, ERR_ARG, ERR_HIP, ERR_NOMEM, BREAKDOWN, NONFINITE, UNSUPPORTED = range(7)
 
 
@@ -49,6 +49,14 @@ class Info:
     failed_pass: int
     failed_pivot: int
     passes_run: int
+    orth_est: float = 0.0   # ||R_p - I||_F of the last pass
+    kappa_est: float = 0.0  # condition estimate from the first pass's factor
+    escalation: int = 0     # escalate=True: 0 none, 1 DD Gram, 2 shifted DD
+
+
+def _info(i):
+    return Info(i.status, i.failed_pass, i.failed_pivot, i.passes_run, i.orth_est, i.kappa_est,
+                i.escalation)
 
 
 def _torch():
@@ -102,7 +110,7 @@ class Context:
     def info(self) -> Info:
         inf = _lib.borth_info()
         self.check(self.lib.borth_get_info(self.h, ctypes.byref(inf)))
-        return Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run)
+        return _info(inf)
 
     def autotune(self, cache_path=None, budget_ms=2000):
         p = None if cache_path is None else str(cache_path).encode()
@@ -176,7 +184,7 @@ def factor(G_hi, G_lo=None, ky=0, fact="chol", shift=0.0, ctx=None, check=True):
     st = ctx.lib.borth_factor(ctx.h, ky, k, _ptr(G_hi), _ptr(G_lo), FACT[fact], float(shift),
                               _ptr(Z), _ptr(R), _ptr(C) if ky else ctypes.c_void_p(0),
                               ctypes.byref(inf))
-    info = Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run)
+    info = _info(inf)
     if check:
         ctx.check(st)
     return Z, R, C[:ky], info
@@ -210,10 +218,12 @@ def _opts(gram, fact, passes, sched, shift, flags):
 
 
 def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto", shift=-1.0,
-                   project_once=False, graph=False, out=None, R=None, C=None, sync=True,
-                   check=True, ctx=None):
+                   project_once=False, graph=False, escalate=False, out=None, R=None, C=None,
+                   sync=True, check=True, ctx=None):
     """X = Y C + Q R with Q^T Q = I and Y^T Q = 0.  Returns (Q, R, C, Info);
-    Info is None when ``sync`` is False (the call is then fully asynchronous)."""
+    Info is None when ``sync`` is False (the call is then fully asynchronous).
+    ``escalate``: after a breakdown, repeat with the DD Gram, then with a
+    shifted DD first pass and three passes (synchronizes)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
     m, k = X.shape
@@ -223,14 +233,15 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
     R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
     if ky and C is None:
         C = torch.empty((ky, k), dtype=torch.float64, device=dev)
-    flags = (FLAG_PROJECT_ONCE if project_once else 0) | (FLAG_GRAPH if graph else 0)
+    flags = ((FLAG_PROJECT_ONCE if project_once else 0) | (FLAG_GRAPH if graph else 0)
+             | (FLAG_AUTO_ESCALATE if escalate else 0))
     o = _opts(gram, fact, passes, sched, shift, flags)
     inf = _lib.borth_info()
     st = ctx.lib.borth_orthonormalize(ctx.h, m, k, _dt(X), _ptr(X), _ld(X), _ptr(Y),
                                       _ld(Y) if ky else 0, ky, _ptr(Q), _ld(Q), _ptr(R),
                                       _ptr(C) if ky else ctypes.c_void_p(0), ctypes.byref(o),
                                       ctypes.byref(inf) if sync else None)
-    info = Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run) if sync else None
+    info = _info(inf) if sync else None
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)
     return Q, R, (C if ky else None), info
@@ -285,7 +296,7 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
         ctx.check(st)
     return (Q, R, (C if ky else None),
             IterInfo(bool(it.converged), it.passes_run, it.c_norm, it.r_dev, it.rank),
-            Info(inf.status, inf.failed_pass, inf.failed_pivot, inf.passes_run))
+            _info(inf))
 
 
 def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0,
@@ -328,7 +339,7 @@ def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0
     infs = (_lib.borth_info * len(blocks))()
     st = ctx.lib.borth_batch_orthonormalize(ctx.h, len(blocks), arr, ctypes.byref(o),
                                             infs if sync else None)
-    infos = [Info(i.status, i.failed_pass, i.failed_pivot, i.passes_run) for i in infs] \
+    infos = [_info(i) for i in infs] \
         if sync else [None] * len(blocks)
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)

@@ -26,7 +26,8 @@ class borth_opts(ctypes.Structure):
 
 class borth_info(ctypes.Structure):
     _fields_ = [("status", _int), ("failed_pass", _int), ("failed_pivot", _int),
-                ("passes_run", _int)]
+                ("passes_run", _int), ("orth_est", _dbl), ("kappa_est", _dbl),
+                ("escalation", _int)]
 
 
 class borth_block(ctypes.Structure):

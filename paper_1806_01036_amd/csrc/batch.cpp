@@ -582,7 +582,17 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
     borth_status r = run_plan(c, P, c->stream);
     if (r) return r;
   }
-  if (!infos && !(o.flags & BORTH_FLAG_SYNC)) return BORTH_OK;
+  c->last_est = false;
+  const bool log = [] {
+    const char* e = std::getenv("BORTH_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  if (!infos && !(o.flags & BORTH_FLAG_SYNC)) {
+    if (log)
+      std::fprintf(stderr, "borth: batch nblocks=%d gram=%d fact=%d passes=%d flags=%u (async)\n",
+                   nblocks, o.gram, o.fact, o.passes, o.flags);
+    return BORTH_OK;
+  }
   HIPCHK(c, hipMemcpyAsync(P->h_status, P->status, sizeof(int) * 4 * (size_t)nblocks,
                            hipMemcpyDeviceToHost, c->stream),
          "status readback");
@@ -595,9 +605,15 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
       infos[b].failed_pass = h[1];
       infos[b].failed_pivot = h[2];
       infos[b].passes_run = h[3];
+      infos[b].orth_est = 0.0;
+      infos[b].kappa_est = 0.0;
+      infos[b].escalation = 0;
     }
     if (h[0] != 0 && first == BORTH_OK) first = (borth_status)h[0];
   }
+  if (log)
+    std::fprintf(stderr, "borth: batch nblocks=%d gram=%d fact=%d passes=%d flags=%u -> status=%d\n",
+                 nblocks, o.gram, o.fact, o.passes, o.flags, (int)first);
   return first;
 }
 

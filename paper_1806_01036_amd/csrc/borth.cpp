@@ -185,6 +185,8 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     f.Rtot = ws + W.rtot;
     f.Ctot = ws + W.ctot;
     f.status = c->status;
+    f.conv = ws + W.cu;  // the last pass's ||R_p - I|| stays (orth_est)
+    f.kappa = pass == 0 ? ws + W.cu + 2 : nullptr;
     f.R_out = last ? a.R : nullptr;
     f.C_out = (last && hasy) ? a.C : nullptr;
     if (dd_update && pass == 0) {
@@ -309,17 +311,39 @@ int64_t partial_need(int ky, int k, int gmode) {
   return kMaxSweepWG * e;
 }
 
+// Status words (and, when the last call left them, the estimates: ||R_p -
+// I||_F of its last pass and the first pass's condition estimate, in the
+// spare k x k area of the workspace).
 borth_status read_status(borth_ctx c, borth_info* info) {
   HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream),
          "status readback");
+  double est[3] = {0.0, 0.0, 0.0};
+  if (c->last_est)
+    HIPCHK(c, hipMemcpyAsync(est, c->ws + ws_layout().cu, sizeof(est), hipMemcpyDeviceToHost, c->stream),
+           "estimates readback");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   if (info) {
     info->status = c->h_status[0];
     info->failed_pass = c->h_status[1];
     info->failed_pivot = c->h_status[2];
     info->passes_run = c->h_status[3];
+    info->orth_est = est[1];
+    info->kappa_est = est[2];
+    info->escalation = 0;
   }
   return (borth_status)c->h_status[0];
+}
+
+borth_status ortho_enqueue(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
+                           int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
+                           int64_t ldq, double* R, double* C, const borth_opts& o);
+
+bool log_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("BORTH_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  return on;
 }
 
 }  // namespace
@@ -451,6 +475,7 @@ borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const 
   c->cur = c->stream;
   const WsLayout W = ws_layout();
   HIPCHK(c, launch_fill_int(c->status, 4, 0, c->stream), "fill");
+  c->last_est = false;
   FactorArgs f;
   memset(&f, 0, sizeof(f));
   f.ky = ky;
@@ -537,9 +562,58 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
     return BORTH_ERR_UNSUPPORTED;
   }
   if (o.sched == BORTH_SCHED_RECOMPUTE && (dt != BORTH_F64 || o.passes != 2)) return fail_arg(c, "recompute needs binary64 X and 2 passes");
+  const bool escalate = (o.flags & BORTH_FLAG_AUTO_ESCALATE) != 0;
+  if (escalate && (dt != BORTH_F64 || (const void*)Q == X))
+    return fail_arg(c, "automatic escalation needs binary64 X and Q distinct from X");
   hipSetDevice(c->device);
+  borth_status r = ortho_enqueue(c, m, k, dt, X, ldx, Y, ldy, ky, Q, ldq, R, C, o);
+  if (r) return r;
+  const bool sync = info || escalate || (o.flags & BORTH_FLAG_SYNC);
+  borth_info local;
+  borth_info* inf = info ? info : &local;
+  borth_status st = BORTH_OK;
+  int level = 0;
+  if (sync) {
+    st = read_status(c, inf);
+    // escalation: DD Gram, then DD Gram with a first-pass shift and three passes
+    while (escalate && st == BORTH_BREAKDOWN && level < 2) {
+      borth_opts o2 = o;
+      o2.flags &= ~BORTH_FLAG_AUTO_ESCALATE;
+      o2.gram = BORTH_GRAM_DD;
+      level = o.gram == BORTH_GRAM_DD ? 2 : level + 1;
+      if (level == 2) {
+        if (ky > 16 && !(o.flags & BORTH_FLAG_PROJECT_ONCE)) break;  // fused Gram limit
+        o2.shift = 11.0 * ((double)m * k + (double)k * (k + 1)) * std::ldexp(1.0, -104);
+        o2.passes = 3;
+        o2.sched = BORTH_SCHED_MATERIALIZE;
+      }
+      r = ortho_enqueue(c, m, k, dt, X, ldx, Y, ldy, ky, Q, ldq, R, C, o2);
+      if (r) return r;
+      st = read_status(c, inf);
+    }
+    inf->escalation = level;
+  }
+  if (log_enabled()) {
+    std::fprintf(stderr, "borth: orthonormalize m=%lld k=%d ky=%d dt=%d gram=%d fact=%d passes=%d "
+                 "sched=%d shift=%g flags=%u", (long long)m, k, ky, (int)dt, o.gram, o.fact,
+                 o.passes, o.sched, o.shift, o.flags);
+    if (sync)
+      std::fprintf(stderr, " -> status=%d passes_run=%d orth_est=%.3e kappa_est=%.3e escalation=%d",
+                   inf->status, inf->passes_run, inf->orth_est, inf->kappa_est, inf->escalation);
+    std::fprintf(stderr, "\n");
+  }
+  return sync ? st : BORTH_OK;
+}
+
+namespace {
+// One orthonormalization enqueued on the context's stream (captured into a
+// cached hipGraph with BORTH_FLAG_GRAPH); arguments already validated.
+borth_status ortho_enqueue(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
+                           int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
+                           int64_t ldq, double* R, double* C, const borth_opts& o) {
   borth_status r = ensure(c, &c->part, &c->part_cap, partial_need(ky, k, o.gram));
   if (r) return r;
+  c->last_est = true;
   OrthoCall a{m, k, ky, dt, X, ldx, Y, ldy, Q, ldq, R, C, o};
   if (o.flags & BORTH_FLAG_GRAPH) {
     GraphKey key;
@@ -574,11 +648,9 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
     r = enqueue_ortho(c, a);
     if (r) return r;
   }
-  if (info || (o.flags & BORTH_FLAG_SYNC)) return read_status(c, info);
   return BORTH_OK;
 }
 
-namespace {
 // The iterated scheme, in the inner product of B = diag(bw) (bw = null: B = I).
 borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t ldx,
                        const double* Y, int64_t ldy, int ky, const double* bw, double* Q,
@@ -609,6 +681,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
   // status[5]: the stop word (0 = running; else the number of passes made)
   HIPCHK(c, launch_fill_int(c->status, 6, 0, c->stream), "fill");
   int* stop = c->status + 5;
+  c->last_est = true;
   it->converged = 0;
   it->passes_run = 0;
   it->c_norm = it->r_dev = 0.0;
@@ -669,6 +742,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     f.Ctot = ws + W.ctot;
     f.status = c->status;
     f.conv = conv;
+    f.kappa = p == 0 ? conv + 2 : nullptr;
     f.rank_reveal = rank_reveal ? 1 : 0;
     f.stop = stop;
     f.stop_eps = eps;
@@ -735,7 +809,15 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     HIPCHK(c, hipMemcpyAsync(C, ws + W.ctot, sizeof(double) * ky * k, hipMemcpyDeviceToDevice,
                              c->stream),
            "copy C");
-  return read_status(c, info);
+  borth_info local;
+  const borth_status st = read_status(c, info ? info : &local);
+  if (log_enabled())
+    std::fprintf(stderr, "borth: orthonormalize_iter m=%lld k=%d ky=%d weighted=%d gram=%d fact=%d "
+                 "eps=%g max_iter=%d flags=%u -> status=%d converged=%d passes_run=%d c_norm=%.3e "
+                 "r_dev=%.3e rank=%d kappa_est=%.3e\n", (long long)m, k, ky, bw ? 1 : 0, o.gram,
+                 o.fact, eps, max_iter, o.flags, (int)st, it->converged, it->passes_run, it->c_norm,
+                 it->r_dev, it->rank, (info ? info : &local)->kappa_est);
+  return st;
 }
 }  // namespace
 

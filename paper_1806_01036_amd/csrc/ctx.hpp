@@ -45,6 +45,7 @@ struct borth_ctx_s {
   uint64_t tune_generation = 0;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
   bool capturing = false;
+  bool last_est = false;             // the last call left estimates in the workspace
   hipStream_t cur = nullptr;         // stream the current enqueue targets
 };
 

@@ -457,6 +457,34 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
       if (a.stop && sqrt(sc) <= a.stop_eps && sqrt(sr) <= a.stop_eps) a.stop[0] = a.pass + 1;
     }
   }
+  if (a.kappa) {
+    // max R_ii / min R_ii: a lower bound on the condition number of the
+    // projected block (each R_ii is a distance to a span of other columns)
+    double dmx = 0.0, dmn = __builtin_inf();
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        const int i = ti + T * p, l = tj + T * q;
+        if (i < k && l == i) {
+          const double d = fabs(x[p][q].hi);
+          dmx = fmax(dmx, d);
+          dmn = fmin(dmn, d);
+        }
+      }
+    __syncthreads();
+    s_r1[0][tid] = dmx;
+    s_r1[1][tid] = dmn;
+    __syncthreads();
+    if (tid == 0) {
+      double mx = 0.0, mn = __builtin_inf();
+      for (int t = 0; t < NT; ++t) {
+        mx = fmax(mx, s_r1[0][t]);
+        mn = fmin(mn, s_r1[1][t]);
+      }
+      a.kappa[0] = mx / mn;
+    }
+  }
   if (tid == 0) a.status[3] = a.pass + 1;
 }
 
@@ -612,11 +640,14 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     double lmax = 0.0;
     for (int i = 0; i < k; ++i) lmax = fmax(lmax, sM[i * LD + i]);
     const double floor_ = lmax * 2.220446049250313e-16;
+    double lmin = lmax;
     for (int i = 0; i < k; ++i) {
       double l = sM[i * LD + i];
       if (!(l > floor_)) l = floor_;
       lam[i] = l;
+      lmin = fmin(lmin, l);
     }
+    if (a.kappa) a.kappa[0] = sqrt(lmax / lmin);
     int r = 0;
     if (a.rank_reveal) {
       const double thr = lmax * k * 0x1p-52;
@@ -945,12 +976,15 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
     double lmax = 0.0;
     for (int i = 0; i < k; ++i) lmax = fmax(lmax, sMh[i * LD + i]);
     const double floor_ = lmax * 0x1p-104;
+    double lmin = lmax;
     for (int i = 0; i < k; ++i) {
       dd_t l = ldm(sMh, sMl, i, i);
       if (!(l.hi > floor_)) l = dd_from(floor_);
       lh[i] = l.hi;
       ll[i] = l.lo;
+      lmin = fmin(lmin, l.hi);
     }
+    if (a.kappa) a.kappa[0] = sqrt(lmax / lmin);
     int r = 0;
     if (a.rank_reveal) {
       const double thr = lmax * k * 0x1p-104;

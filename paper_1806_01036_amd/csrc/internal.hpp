@@ -143,6 +143,9 @@ struct FactorArgs {
   double* Z_out;            // optional unpadded Z (k x k)
   double* Rp_out;           // optional this-pass R (k x k)
   double* conv;             // optional: ||C_p||_F and ||R_p - I||_F of this pass
+  // optional: a condition estimate of the projected block, max R_ii / min R_ii
+  // (Cholesky) or sqrt(lambda_max / lambda_min) of M (SVQB, lifted eigenvalues)
+  double* kappa;
   // DD update (Cholesky in DD only): the low words of Z_p and of the
   // projection coefficients, which are then D = 2C - S C (C corrected to
   // first order for Y^T Y != I) instead of C, in C_p and in the totals.

@@ -69,3 +69,31 @@ def test_no_oracle_in_product():
         text = f.read_text()
         assert "import oracle" not in text and "from oracle" not in text, f
         assert "liboracle" not in text and "oracle.c" not in text, f
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    """The ctypes mirrors of the header's structs have the C layout (gcc)."""
+    import shutil
+    import subprocess
+    from paper_1806_01036_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = {"borth_opts": _lib.borth_opts, "borth_info": _lib.borth_info,
+               "borth_block": _lib.borth_block, "borth_iter_info": _lib.borth_iter_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "borth.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", f"-I{ROOT / 'include'}", str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(out[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)

@@ -1,0 +1,125 @@
+"""GPU tests of what a call reports besides its result: the estimates in
+borth_info (orth_est, kappa_est), the automatic escalation after a
+breakdown, and the BORTH_LOG trace.  Exact values on the Hadamard family
+(every factor is exact there), properties elsewhere."""
+import os
+import subprocess
+import sys
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import U64, dev, host, lib, note
+
+pytestmark = pytest.mark.gpu
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+@pytest.mark.parametrize("gram,fact", [("f64", "chol"), ("dd", "chol"), ("f64", "svqb"),
+                                       ("dd", "svqb")])
+def test_estimates_exact_on_hadamard(gram, fact):
+    """X = H diag(2^e): R_1 = diag(2^e) exactly, so kappa_est = 2^(max e - min
+    e) and, after one pass, orth_est = ||diag(2^e) - I||_F; a second pass
+    sees Q_1 = H exactly: orth_est = 0."""
+    borth = lib()
+    exps = [0, -3, 7, -9, 11, -5, 2, -12] if fact == "svqb" else [0, -3, 7, -20, 11, -35, 2, -50]
+    X = synth.hadamard_scaled(7, exps)
+    d = np.ldexp(1.0, exps)
+    _, _, _, i1 = borth.orthonormalize(dev(X), gram=gram, fact=fact, passes=1)
+    note("hadamard estimates", gram, fact, i1)
+    assert i1.kappa_est == 2.0 ** (max(exps) - min(exps))
+    assert abs(i1.orth_est - np.linalg.norm(d - 1.0)) <= 4 * U64 * np.linalg.norm(d)
+    _, _, _, i2 = borth.orthonormalize(dev(X), gram=gram, fact=fact, passes=2)
+    assert i2.orth_est == 0.0 and i2.kappa_est == i1.kappa_est and i2.escalation == 0
+
+
+@pytest.mark.parametrize("fact", ["chol", "svqb"])
+def test_estimates_against_the_oracle(fact):
+    """kappa(X) = 1e6: the Cholesky diagonal ratio is a lower bound on kappa
+    (R_ii lies between sigma_min and sigma_max), the SVQB estimate is
+    sqrt(lambda_max / lambda_min) of the Gram (accurate to u kappa^2 here);
+    orth_est of CholQR2 is ||R_2 - I||_F of the exact Cholesky of Q_1^T Q_1."""
+    borth = lib()
+    k, kappa = 8, 1e6
+    X = synth.svd_matrix(20000, k, kappa, 6100)
+    _, _, _, inf = borth.orthonormalize(dev(X), gram="f64", fact=fact, passes=2)
+    note("estimates", fact, inf)
+    if fact == "chol":
+        assert kappa / 1e3 <= inf.kappa_est <= kappa * (1 + 1e-6)
+    else:
+        assert abs(inf.kappa_est / kappa - 1) <= 1e-3
+    # the second pass's input, recomputed by one pass of the same kind
+    Q1, _, _, _ = borth.orthonormalize(dev(X), gram="f64", fact=fact, passes=1)
+    hi, lo = oracle.gram_q(host(Q1))
+    G = hi + lo
+    if fact == "chol":
+        dev2 = np.linalg.norm(np.linalg.cholesky(G).T - np.eye(k))
+    else:
+        w, V = np.linalg.eigh(G)
+        dev2 = np.linalg.norm(V @ np.diag(np.sqrt(w)) @ V.T - np.eye(k))
+    note("  orth_est", inf.orth_est, "reference", dev2)
+    assert 1e-12 <= dev2 and abs(inf.orth_est - dev2) <= 0.05 * dev2
+
+
+def test_escalation_to_dd():
+    """Exact Gram [[1, 1], [1, 1 + 2^-80]] (Hadamard columns, one tilted by
+    2^-40): the binary64 Gram holds [[1, 1], [1, 1]] and its Cholesky breaks
+    down at pivot 2; the DD retry returns the exact Q within a few ulps."""
+    borth = lib()
+    X = synth.hadamard_near_parallel(7, 4, 40)
+    H = synth.hadamard_columns(7, range(1, 5))
+    _, _, _, inf0 = borth.orthonormalize(dev(X), gram="f64", passes=2, check=False)
+    note("no escalation", inf0)
+    assert inf0.status == 4 and inf0.escalation == 0
+    Q, R, _, inf = borth.orthonormalize(dev(X), gram="f64", passes=2, escalate=True, check=False)
+    note("escalation", inf)
+    assert inf.status == 0 and inf.escalation == 1
+    assert np.max(np.abs(host(Q) - H)) <= 8 * U64 * np.abs(H).max()
+
+
+def test_escalation_shifted_on_dependent_columns():
+    """Two equal columns: the DD Cholesky breaks down; the shifted DD first
+    pass factors M + s I, and the two binary64 passes after it turn Q_1 into
+    an orthonormal Q with X = Q R, R carrying the dependency as a diagonal
+    entry at the rounding level."""
+    borth = lib()
+    X = synth.svd_matrix(5000, 6, 10.0, 6300)
+    X[:, 3] = X[:, 1]
+    _, _, _, inf0 = borth.orthonormalize(dev(X), gram="dd", passes=2, check=False)
+    assert inf0.status == 4
+    Q, R, _, inf = borth.orthonormalize(dev(X), gram="dd", passes=2, escalate=True, check=False)
+    note("shifted", inf)
+    assert inf.escalation == 2 and inf.status == 0 and inf.passes_run == 3
+    met = oracle.metrics(host(Q), X, host(R))
+    note("  metrics", met)
+    assert met["omega"] <= 1e-13 and met["rho"] <= 1e-13
+    d = np.abs(np.diag(host(R)))
+    assert d.min() <= 1e-8 * d.max()
+
+
+def test_escalation_rejects_in_place_and_fp32():
+    borth = lib()
+    X = dev(synth.svd_matrix(3000, 4, 10.0, 6400))
+    with pytest.raises(Exception):
+        borth.orthonormalize(X, out=X, sched="materialize", escalate=True)
+    with pytest.raises(Exception):
+        borth.orthonormalize(X.float(), gram="split", escalate=True)
+
+
+def test_log_line():
+    """BORTH_LOG=1 prints one line per call with the status and estimates."""
+    code = ("import sys; sys.path.insert(0, %r); import torch, synth; "
+            "import paper_1806_01036_amd as b; "
+            "X = torch.from_numpy(synth.hadamard_scaled(5, [0, 3, -2])).cuda(); "
+            "b.orthonormalize(X, gram='dd', passes=2)" % str(ROOT))
+    env = dict(os.environ, BORTH_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("borth: orthonormalize")]
+    note("log", lines)
+    assert len(lines) == 1 and "status=0" in lines[0] and "kappa_est=3.200e+01" in lines[0]
