@@ -45,7 +45,7 @@ DD_GRAM_OPS = 4.0
 # those sources change.
 DD_GRAM_TRAFFIC = {"bytes": 1.0337e9,
                    "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
-                   "sha256": "1c5f71acdd06def5c003cf884b4233fd321cb17863db1bf016dc1ee58ff86f76"}
+                   "sha256": "065b577ce22a043a4e36accf04b3f34221c4c6097092018ea18ef194fbb1fbac"}
 
 
 def measured_traffic(rec):

@@ -24,6 +24,33 @@ namespace {
 
 constexpr int NTF = 256;
 
+// Two values per thread reduced over the workgroup (sums, or max of x and
+// min of y): a shuffle tree inside each wave, then the waves' results in
+// wave order by thread 0, whose x and y hold the result.  NT is a multiple
+// of 64; sh holds 2 NT / 64 doubles.  Deterministic.
+template <int NT, bool MAXMIN>
+__device__ __forceinline__ void wg_reduce2(double& x, double& y, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double xo = __shfl_xor(x, o), yo = __shfl_xor(y, o);
+    x = MAXMIN ? fmax(x, xo) : x + xo;
+    y = MAXMIN ? fmin(y, yo) : y + yo;
+  }
+  constexpr int NW = NT / 64;
+  const int w = (int)threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = x;
+    sh[NW + w] = y;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = 1; i < NW; ++i) {
+      x = MAXMIN ? fmax(x, sh[i]) : x + sh[i];
+      y = MAXMIN ? fmin(y, sh[NW + i]) : y + sh[NW + i];
+    }
+}
+
 __device__ __forceinline__ dd_t ld_g(const double* hi, const double* lo, int idx) {
   return dd_make(hi[idx], lo ? lo[idx] : 0.0);
 }
@@ -441,16 +468,9 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
       const double v = a.G_hi[(e / k) * W + ky + e % k];
       cc = __builtin_fma(v, v, cc);
     }
-    __syncthreads();
-    s_r1[0][tid] = rr;
-    s_r1[1][tid] = cc;
-    __syncthreads();
+    wg_reduce2<NT, false>(rr, cc, s_r1[0]);
     if (tid == 0) {
-      double sr = 0.0, sc = 0.0;
-      for (int t = 0; t < NT; ++t) {
-        sr += s_r1[0][t];
-        sc += s_r1[1][t];
-      }
+      const double sr = rr, sc = cc;
       a.conv[0] = sqrt(sc);
       a.conv[1] = sqrt(sr);
       // iterated scheme: this pass is the last one when both norms are small
@@ -472,18 +492,8 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
           dmn = fmin(dmn, d);
         }
       }
-    __syncthreads();
-    s_r1[0][tid] = dmx;
-    s_r1[1][tid] = dmn;
-    __syncthreads();
-    if (tid == 0) {
-      double mx = 0.0, mn = __builtin_inf();
-      for (int t = 0; t < NT; ++t) {
-        mx = fmax(mx, s_r1[0][t]);
-        mn = fmin(mn, s_r1[1][t]);
-      }
-      a.kappa[0] = mx / mn;
-    }
+    wg_reduce2<NT, true>(dmx, dmn, s_r1[0]);
+    if (tid == 0) a.kappa[0] = dmx / dmn;
   }
   if (tid == 0) a.status[3] = a.pass + 1;
 }
@@ -745,16 +755,9 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
       const double v = a.G_hi[(e / k) * W + ky + e % k];
       cc = __builtin_fma(v, v, cc);
     }
-    __syncthreads();
-    sV[tid] = rr;
-    sV[NTF + tid] = cc;
-    __syncthreads();
+    wg_reduce2<NTF, false>(rr, cc, sV);
     if (tid == 0) {
-      double sr = 0.0, sc = 0.0;
-      for (int t = 0; t < NTF; ++t) {
-        sr += sV[t];
-        sc += sV[NTF + t];
-      }
+      const double sr = rr, sc = cc;
       a.conv[0] = sqrt(sc);
       a.conv[1] = sqrt(sr);
       // iterated scheme: this pass is the last one when both norms are small
@@ -1120,16 +1123,9 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
       const double v = a.G_hi[(e / k) * W + ky + e % k];
       cc = __builtin_fma(v, v, cc);
     }
-    __syncthreads();
-    sVh[tid] = rr;
-    sVh[NTF + tid] = cc;
-    __syncthreads();
+    wg_reduce2<NTF, false>(rr, cc, sVh);
     if (tid == 0) {
-      double sr = 0.0, sc = 0.0;
-      for (int t = 0; t < NTF; ++t) {
-        sr += sVh[t];
-        sc += sVh[NTF + t];
-      }
+      const double sr = rr, sc = cc;
       a.conv[0] = sqrt(sc);
       a.conv[1] = sqrt(sr);
       // iterated scheme: this pass is the last one when both norms are small
