@@ -298,9 +298,11 @@ borth_status borth_batch_orthonormalize(borth_ctx ctx, int nblocks, const borth_
 borth_status borth_autotune(borth_ctx ctx, const char* cache_path, int budget_ms);
 borth_status borth_autotune_load(borth_ctx ctx, const char* cache_path);
 
-/* Average duration (ms) of the last call's dominant kernel launches, taken
- * from HIP events on the context's stream when profiling is enabled with
- * borth_set_profiling(ctx, 1).  kind: 0 = first-pass Gram sweep,
+/* Average duration (ms) of the dominant kernel launches since profiling was
+ * enabled, taken from HIP events on the context's stream.
+ * borth_set_profiling(ctx, mask) times the first-pass Gram sweeps (mask bit
+ * 0) and the update sweeps (bit 1); 0 turns timing off.  Each timed launch
+ * adds two event records to the stream.  kind: 0 = first-pass Gram sweep,
  * 1 = update sweeps; returns the number of timed launches in *count. */
 borth_status borth_set_profiling(borth_ctx ctx, int on);
 borth_status borth_kernel_time(borth_ctx ctx, int kind, double* avg_ms, int* count);

@@ -98,8 +98,11 @@ class Context:
             self.lib.borth_destroy(self.h)
             self.h = None
 
-    def set_profiling(self, on: bool):
-        self.check(self.lib.borth_set_profiling(self.h, int(bool(on))))
+    def set_profiling(self, on, kinds=(0, 1)):
+        """Time the launches of ``kinds`` (0: first-pass Gram sweeps, 1:
+        update sweeps) with HIP events; ``on=False`` stops."""
+        mask = sum(1 << k for k in kinds) if on else 0
+        self.check(self.lib.borth_set_profiling(self.h, mask))
 
     def kernel_time(self, kind: int):
         avg = ctypes.c_double()

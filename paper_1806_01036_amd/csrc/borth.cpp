@@ -848,7 +848,7 @@ borth_status borth_set_profiling(borth_ctx c, int on) {
     for (auto& p : c->ev_used[k]) c->ev_free.push_back(p);
     c->ev_used[k].clear();
   }
-  c->prof = on != 0;
+  c->prof = on & 3;
   return BORTH_OK;
 }
 

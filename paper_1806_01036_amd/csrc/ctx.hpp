@@ -34,7 +34,7 @@ struct borth_ctx_s {
   std::map<GraphKey, hipGraphExec_t> graphs;
   uint64_t ws_generation = 0;
   // profiling
-  bool prof = false;
+  int prof = 0;  // mask of timed kinds: 1 Gram sweeps, 2 update sweeps
   std::vector<TimedPair> ev_free;
   std::vector<TimedPair> ev_used[2];
   // autotune table: key (mode, kp, ky>0) -> tune
@@ -87,7 +87,7 @@ inline borth::TuneGram lookup(const std::map<std::tuple<int, int, int>, borth::T
 // Profiling: HIP events around the dominant launches (kind 0 Gram sweeps,
 // kind 1 update sweeps) on the stream they run on; skipped under capture.
 inline void prof_begin(borth_ctx c, int kind) {
-  if (!c->prof || c->capturing) return;
+  if (!(c->prof & (1 << kind)) || c->capturing) return;
   TimedPair p;
   if (!c->ev_free.empty()) {
     p = c->ev_free.back();
@@ -100,7 +100,7 @@ inline void prof_begin(borth_ctx c, int kind) {
   c->ev_used[kind].push_back(p);
 }
 inline void prof_end(borth_ctx c, int kind) {
-  if (!c->prof || c->capturing) return;
+  if (!(c->prof & (1 << kind)) || c->capturing) return;
   hipEventRecord(c->ev_used[kind].back().b, c->cur);
 }
 
