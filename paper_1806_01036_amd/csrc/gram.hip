@@ -374,6 +374,81 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
 }
 
 // ---------------------------------------------------------------------------
+// binary64 Gram of a narrow block (padded width WP <= 8, no weights): one row
+// per lane and step, UR rows in flight per lane, all WP (WP + 1) / 2 products
+// of a row in registers.  The tile kernel would give each thread a 4x4 tile
+// and two rows per panel here, and the MFMA kernel would leave most lanes of
+// a 16-column operand empty; both stay far from the HBM stream.  The
+// workgroup's sums are combined in a fixed order (shuffle tree in each wave,
+// then the waves in order) into one partial in the tile layout.
+template <int WP, int KYP>
+__global__ void __launch_bounds__(256) gram_rows_kernel(GramSeg g) {
+  const Src& s = g.s;
+  if (stopped(s.stop, s.pass)) return;
+  const GramLayout& L = g.L;
+  constexpr int NPR = WP * (WP + 1) / 2, UR = WP <= 4 ? 8 : 4;
+  double acc[NPR];
+#pragma unroll
+  for (int x = 0; x < NPR; ++x) acc[x] = 0.0;
+  const int64_t nthr = (int64_t)g.nwg * 256;
+  const int ky = L.ky, k = L.k;
+  const double BORTH_GLOBAL* Yg = gmem(s.Y);
+  const double BORTH_GLOBAL* Xg = gmem((const double*)s.X);
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < s.m; r += UR * nthr) {
+    // unconditional loads: row clamped to m - 1, column to the last valid
+    // one; the zeros (past m, padding columns) are selected afterwards
+    double v[UR][WP];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const int64_t row = r + u * nthr;
+      const int64_t rc = row < s.m ? row : s.m - 1;
+#pragma unroll
+      for (int c = 0; c < WP; ++c) {
+        const bool isy = c < KYP;
+        const int j = isy ? c : c - KYP;
+        const int lim = isy ? ky : k;
+        const double x = isy ? Yg[rc * s.ldy + (j < ky ? j : ky - 1)]
+                             : Xg[rc * s.ldx + (j < k ? j : k - 1)];
+        v[u][c] = (row < s.m && j < lim) ? x : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      int x = 0;
+#pragma unroll
+      for (int i = 0; i < WP; ++i)
+#pragma unroll
+        for (int j = i; j < WP; ++j, ++x) acc[x] = __builtin_fma(v[u][i], v[u][j], acc[x]);
+    }
+  }
+  __shared__ double red[4][NPR];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int x = 0; x < NPR; ++x) {
+    double a = acc[x];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) red[w][x] = a;
+  }
+  __syncthreads();
+  // the partial: tiles (ti <= tj) of 16 entries; the lower half of a diagonal
+  // tile holds the mirror entry
+  double BORTH_GLOBAL* out = gmem(g.part) + (int64_t)blockIdx.x * L.E;
+  for (int e = threadIdx.x; e < L.E; e += 256) {
+    int ti, tj;
+    decode_tile(e / 16, L, ti, tj);
+    int i = 4 * ti + (e % 16) / 4, j = 4 * tj + e % 4;
+    if (i > j) {
+      const int t = i;
+      i = j;
+      j = t;
+    }
+    const int x = i * WP - i * (i - 1) / 2 + (j - i);
+    out[e] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // binary64 MFMA kernel: T = padded width / 16 column blocks.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -670,10 +745,10 @@ hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int g
   } while (0)
   if (kind == 0) {
     switch (NT_or_T) {
-      case 1: BORTH_MFMA(1, 4); break;
-      case 2: BORTH_MFMA(2, 4); break;
+      case 1: BORTH_MFMA(1, 16); break;
+      case 2: BORTH_MFMA(2, 8); break;
       case 3: BORTH_MFMA(3, 2); break;
-      case 4: BORTH_MFMA(4, 2); break;
+      case 4: BORTH_MFMA(4, 4); break;
       case 5: BORTH_MFMA(5, 2); break;
       default: return hipErrorInvalidValue;
     }
@@ -721,6 +796,29 @@ int gram_tiles_resident(int mode, int NT, size_t shmem) {
 hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* partials,
                        int64_t cap, int* nwg_out, const TuneGram& tune, hipStream_t st) {
   if (s.bw && s.x_f32) return hipErrorInvalidValue;
+  if (mode == 0 && !s.bw && !s.x_f32 && L.ty == 0 && L.Wp <= 8) {
+    // narrow binary64 block: the row kernel, a few rows per lane in flight
+    const int64_t want = (s.m + 256 * 4 * 4 - 1) / (256 * 4 * 4);  // >= 4 trips per lane
+    int nwg = tune.nwg > 0 ? tune.nwg : 1024;
+    if (nwg > want) nwg = (int)(want > 0 ? want : 1);
+    if ((int64_t)nwg * L.E > cap) return hipErrorInvalidValue;
+    GramSeg g;
+    g.s = s;
+    g.L = L;
+    g.part = partials;
+    g.nunits = s.m;
+    g.P = g.S = 0;
+    g.wg0 = 0;
+    g.nwg = nwg;
+    *nwg_out = nwg;
+    if (L.Wp == 4)
+      hipLaunchKernelGGL((gram_rows_kernel<4, 0>), dim3(nwg), dim3(256), 0, st, g);
+    else if (L.kyp == 0)
+      hipLaunchKernelGGL((gram_rows_kernel<8, 0>), dim3(nwg), dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((gram_rows_kernel<8, 4>), dim3(nwg), dim3(256), 0, st, g);
+    return hipGetLastError();
+  }
   const int kind = gram_kind(L, mode, s.bw != nullptr);
   const int NT = kind == 0 ? 256 : gram_tiles_threads(L);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;

@@ -123,3 +123,23 @@ def test_log_line():
     lines = [l for l in r.stderr.splitlines() if l.startswith("borth: orthonormalize")]
     note("log", lines)
     assert len(lines) == 1 and "status=0" in lines[0] and "kappa_est=3.200e+01" in lines[0]
+
+
+def test_profiling_mask():
+    """Event timing per kernel kind: only the kinds in the mask are timed."""
+    borth = lib()
+    ctx = borth.default_context()
+    X = dev(synth.svd_matrix(100_000, 16, 1e3, 6500))
+    ctx.set_profiling(True, kinds=(0,))
+    for _ in range(3):
+        borth.orthonormalize(X, gram="dd", passes=2, ctx=ctx)
+    g_ms, g_n = ctx.kernel_time(0)
+    u_ms, u_n = ctx.kernel_time(1)
+    ctx.set_profiling(False)
+    assert g_n == 3 and g_ms > 0.0 and u_n == 0
+    ctx.set_profiling(True)
+    borth.orthonormalize(X, gram="dd", passes=2, ctx=ctx)
+    g_ms, g_n = ctx.kernel_time(0)
+    u_ms, u_n = ctx.kernel_time(1)
+    ctx.set_profiling(False)
+    assert g_n == 1 and u_n == 2 and u_ms > 0.0
