@@ -45,7 +45,7 @@ DD_GRAM_OPS = 4.0
 # those sources change.
 DD_GRAM_TRAFFIC = {"bytes": 1.0337e9,
                    "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
-                   "sha256": "065b577ce22a043a4e36accf04b3f34221c4c6097092018ea18ef194fbb1fbac"}
+                   "sha256": "15773e820d5d240db982b8c78048235e6690a2d2915921e3f738511a33103c12"}
 
 
 def measured_traffic(rec):
