@@ -457,6 +457,19 @@ def _orth_levels(borth, Q, Y, k, ky):
     return om, omy
 
 
+def _orth_levels_dd(torch, borth, Qh, Ql, Y, k, ky):
+    """The same levels for a DD result Qh + Ql, from the library's Dot2 DD Gram
+    of [Y | Qh | Ql], its blocks combined so that the low words count."""
+    ghi, glo = borth.gram(torch.cat([Qh, Ql], dim=1), A=Y, prec="dd_dot2")
+    hi, lo = ghi.cpu().numpy(), glo.cpu().numpy()
+    H, L = slice(ky, ky + k), slice(ky + k, ky + 2 * k)
+    D = (((hi[H, H] - np.eye(k)) + lo[H, H]) + ((hi[H, L] + hi[L, H]) + (lo[H, L] + lo[L, H]))
+         + hi[L, L])
+    om = float(np.linalg.norm(D))
+    omy = float(np.linalg.norm((hi[:ky, H] + hi[:ky, L]) + (lo[:ky, H] + lo[:ky, L]))) if ky else 0.0
+    return om, omy
+
+
 def run_fig7(args, torch, borth, synth):
     """One two-phase pass (projection against Y, then orthonormalization) on
     the shape of the paper's accuracy experiment (Fig. 7): n = 1000 rows,
@@ -464,7 +477,8 @@ def run_fig7(args, torch, borth, synth):
     kappa(X, Y) at kappa(X) in {1, 1e3}; right: ||Q^T Q - I|| against kappa(X)
     at kappa(X, Y) = kappa(X).  Variants: binary64 Gram with SVQB; DD Gram
     (biased accumulation) with DD SVQB or DD Cholesky and DD update; the
-    latter with the Dot2 accumulation."""
+    latter with the Dot2 accumulation, rounded to binary64 or returned in DD
+    (Q + Q_lo, measured as such)."""
     n, ky, k = 1000, 20, 4
     variants = {"f64_svqb": ("f64", "svqb"), "dd_svqb": ("dd", "svqb"), "dd_chol": ("dd", "chol"),
                 "dd_chol_dot2": ("dd_dot2", "chol")}
@@ -480,6 +494,14 @@ def run_fig7(args, torch, borth, synth):
                      omega_y=omy)
             log(r)
             rows.append(r)
+        # the DD result itself (Q + Q_lo), Dot2 accumulation
+        Q, Ql, R, C, info = borth.orthonormalize_dd(X, Y, dot2=True, check=False)
+        torch.cuda.synchronize()
+        om, omy = _orth_levels_dd(torch, borth, Q, Ql, Y, k, ky)
+        r = dict(kappa_x=kx, kappa_xy=kxy, variant="dd_chol_dot2_ddq", status=info.status,
+                 omega=om, omega_y=omy)
+        log(r)
+        rows.append(r)
 
     for kx in (1.0, 1e3):
         for e in range(0, 19, 3):

@@ -213,6 +213,21 @@ typedef struct {
   int rank;       /* numerical rank r of the last pass (k unless RANK_REVEAL) */
 } borth_iter_info;
 
+/* One project / orthonormalize pass with a double-double result (Sec. 4.2:
+ * kernels that return DD results; the DD variant of Fig. 7): the DD Gram of
+ * [Y | X], the DD factor (opts->fact, Cholesky or SVQB, with the corrected
+ * projection coefficients) and the DD update of the narrow path, rounded
+ * once into Q + Q_lo: Q (binary64, m x k, ldq) holds the rounded result and
+ * Q_lo its DD low word (same layout), |Q_lo| <= ulp(Q)/2.  k <= 8.  The
+ * other options are fixed (DD Gram, one pass, no shift); opts->flags may
+ * carry BORTH_FLAG_SYNC and BORTH_FLAG_DD_DOT2.  R and C: binary64 words of
+ * the factors.  Q and Q_lo must not alias X or each other.  Q alone equals
+ * what borth_orthonormalize returns for the same one DD pass. */
+borth_status borth_orthonormalize_dd(borth_ctx ctx, int64_t m, int k, const double* X,
+                                     int64_t ldx, const double* Y, int64_t ldy, int ky,
+                                     double* Q, double* Q_lo, int64_t ldq, double* R, double* C,
+                                     const borth_opts* opts, borth_info* info);
+
 /* Iterated two-phase scheme (Sec. 4.2: phase I and phase II alternated until
  * the block no longer changes): pass j projects the current block S_j (X,
  * then Q) against Y and orthonormalizes it, S_{j+1} = (S_j - Y C_j) Z_j, and

@@ -19,7 +19,8 @@ from . import _lib
 
 __all__ = [
     "BorthError", "Breakdown", "Context", "Info", "default_context", "gram", "factor",
-    "update", "orthonormalize", "orthonormalize_iter", "batch_orthonormalize", "GRAM", "FACT",
+    "update", "orthonormalize", "orthonormalize_dd", "orthonormalize_iter",
+    "batch_orthonormalize", "GRAM", "FACT",
     "SCHED",
 ]
 
@@ -248,6 +249,33 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)
     return Q, R, (C if ky else None), info
+
+
+def orthonormalize_dd(X, Y=None, *, fact="chol", dot2=False, out=None, out_lo=None, R=None,
+                      C=None, check=True, ctx=None):
+    """One DD pass (k <= 8) returning the result in double-double:
+    (Q, Q_lo, R, C, Info) with Q + Q_lo the DD Q (borth_orthonormalize_dd)."""
+    torch = _torch()
+    ctx = ctx or default_context(X.device.index)
+    m, k = X.shape
+    ky = 0 if Y is None else Y.shape[1]
+    dev = X.device
+    Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
+    Ql = out_lo if out_lo is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
+    if _ld(Ql) != _ld(Q):
+        raise ValueError("Q and Q_lo need the same leading dimension")
+    R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
+    if ky and C is None:
+        C = torch.empty((ky, k), dtype=torch.float64, device=dev)
+    o = _opts("dd_dot2" if dot2 else "dd", fact, 1, "materialize", 0.0, 0)
+    inf = _lib.borth_info()
+    st = ctx.lib.borth_orthonormalize_dd(ctx.h, m, k, _ptr(X), _ld(X), _ptr(Y),
+                                         _ld(Y) if ky else 0, ky, _ptr(Q), _ptr(Ql), _ld(Q),
+                                         _ptr(R), _ptr(C) if ky else None, ctypes.byref(o),
+                                         ctypes.byref(inf))
+    if check or st not in (BREAKDOWN, NONFINITE):
+        ctx.check(st)
+    return Q, Ql, R, (C if ky else None), _info(inf)
 
 
 @dataclass

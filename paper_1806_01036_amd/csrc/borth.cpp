@@ -120,6 +120,7 @@ struct OrthoCall {
   double* R;
   double* C;
   borth_opts o;
+  double* Qlo;  // one DD pass on a narrow block: the result's low words, or null
 };
 
 borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
@@ -220,6 +221,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     u.dense = a.o.fact == BORTH_SVQB;
     u.Q = a.Q;
     u.ldq = a.ldq;
+    if (dd_update) u.Qlo = a.Qlo;
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 0, kp, hasy), st), "update");
     prof_end(c, 1);
@@ -336,7 +338,8 @@ borth_status read_status(borth_ctx c, borth_info* info) {
 
 borth_status ortho_enqueue(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
                            int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
-                           int64_t ldq, double* R, double* C, const borth_opts& o);
+                           int64_t ldq, double* R, double* C, const borth_opts& o,
+                           double* Qlo = nullptr);
 
 bool log_enabled() {
   static const bool on = [] {
@@ -610,11 +613,11 @@ namespace {
 // cached hipGraph with BORTH_FLAG_GRAPH); arguments already validated.
 borth_status ortho_enqueue(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
                            int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
-                           int64_t ldq, double* R, double* C, const borth_opts& o) {
+                           int64_t ldq, double* R, double* C, const borth_opts& o, double* Qlo) {
   borth_status r = ensure(c, &c->part, &c->part_cap, partial_need(ky, k, o.gram));
   if (r) return r;
   c->last_est = true;
-  OrthoCall a{m, k, ky, dt, X, ldx, Y, ldy, Q, ldq, R, C, o};
+  OrthoCall a{m, k, ky, dt, X, ldx, Y, ldy, Q, ldq, R, C, o, Qlo};
   if (o.flags & BORTH_FLAG_GRAPH) {
     GraphKey key;
     key.v = {m, k, ky, (int64_t)dt, (int64_t)(intptr_t)X, ldx, (int64_t)(intptr_t)Y, ldy,
@@ -820,6 +823,40 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
   return st;
 }
 }  // namespace
+
+borth_status borth_orthonormalize_dd(borth_ctx c, int64_t m, int k, const double* X,
+                                     int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
+                                     double* Q_lo, int64_t ldq, double* R, double* C,
+                                     const borth_opts* opts, borth_info* info) {
+  if (!c) return BORTH_ERR_ARG;
+  borth_opts o;
+  if (opts) o = *opts; else borth_default_opts(&o);
+  if (k < 1 || k > 8 || ky < 0 || ky > 64 || m < (int64_t)k + ky) return fail_arg(c, "shape (k <= 8)");
+  if (!X || !Q || !Q_lo || ldx < k || ldq < k) return fail_arg(c, "X/Q/Q_lo");
+  if (ky > 0 && (!Y || ldy < ky)) return fail_arg(c, "Y");
+  if ((const void*)Q == (const void*)X || (const void*)Q_lo == (const void*)X || Q_lo == Q)
+    return fail_arg(c, "Q and Q_lo must not alias X or each other");
+  if (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB) return fail_arg(c, "opts.fact");
+  o.gram = BORTH_GRAM_DD;
+  o.passes = 1;
+  o.sched = BORTH_SCHED_MATERIALIZE;
+  o.shift = 0.0;
+  o.flags &= (BORTH_FLAG_SYNC | BORTH_FLAG_DD_DOT2);
+  hipSetDevice(c->device);
+  borth_status r = ortho_enqueue(c, m, k, BORTH_F64, X, ldx, Y, ldy, ky, Q, ldq, R, C, o, Q_lo);
+  if (r) return r;
+  const bool sync = info || (o.flags & BORTH_FLAG_SYNC);
+  borth_info local;
+  borth_info* inf = info ? info : &local;
+  const borth_status st = sync ? read_status(c, inf) : BORTH_OK;
+  if (log_enabled()) {
+    std::fprintf(stderr, "borth: orthonormalize_dd m=%lld k=%d ky=%d fact=%d flags=%u", (long long)m,
+                 k, ky, o.fact, o.flags);
+    if (sync) std::fprintf(stderr, " -> status=%d kappa_est=%.3e", inf->status, inf->kappa_est);
+    std::fprintf(stderr, "\n");
+  }
+  return st;
+}
 
 borth_status borth_orthonormalize_iter(borth_ctx c, int64_t m, int k, const double* X,
                                        int64_t ldx, const double* Y, int64_t ldy, int ky,

@@ -180,6 +180,7 @@ struct UpdateArgs {
   int two_stage;
   int dense;                           // Z dense (SVQB)
   double* Q; int64_t ldq;
+  double* Qlo;                         // narrow DD update: low words of Q (ldq), or null
   double* partials; int64_t partial_cap_doubles;
   int gram_xcols;                      // narrow fused Gram: [Y | T]^T T only
   int gram_dd;                         //   ... in DD
@@ -203,6 +204,7 @@ struct UpdDev {
   int dense;
   double* Q;
   int64_t ldq;
+  double* Qlo;  // narrow DD update: the DD result's low words (ldq), or null
   double* part;
   int64_t npanels;
   const double* C1;  // stage coefficients (ky x K C, K x K Z, zero padded)

@@ -62,6 +62,7 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.zbase = 0;
   d.Q = a.Q;
   d.ldq = a.ldq;
+  d.Qlo = a.Qlo;
   d.part = a.partials;
   const int PR = upd::upd_rows(K);
   d.npanels = (a.src.m + PR - 1) / PR;
@@ -75,7 +76,8 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.stop = a.src.stop;
   d.pass = a.src.pass;
   if (a.bw && !(a.partials && a.gram_xcols)) return hipErrorInvalidValue;
-  // DD arithmetic exists in the narrow kernel only
+  // DD arithmetic exists in the narrow kernel only (and with it DD results)
+  if (a.Qlo && !(a.C1lo && a.Z1lo)) return hipErrorInvalidValue;
   if ((a.C1lo || a.Z1lo) && (a.two_stage || a.src.x_f32 || !update_narrow_ok(L.k, L.ky, K)))
     return hipErrorInvalidValue;
   if (!a.partials && !a.two_stage && !a.src.x_f32 && a.Q && update_narrow_ok(L.k, L.ky, K)) {

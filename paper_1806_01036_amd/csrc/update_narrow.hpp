@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
   // T = S - Y C (one fused multiply-add per product term, S first), Q = T Z;
   // with the fused Gram, T joins the panel and is accumulated column-wise.
   auto compute_store = [&](const double* xs, double ws, int64_t row0, int nrows) {
-    double qv[KN];
+    double qv[KN], qlo[KN];
     if (!pdd) {
       double t[KN];
 #pragma unroll
@@ -254,13 +254,20 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
             dot2_step(s, e, ts[l], zh);
             e = __builtin_fma(ts[l], Zlg[l * kp + j], __builtin_fma(te[l], zh, e));
           }
-        qv[j] = s + e;
+        const dd_t q = two_sum(s, e);
+        qv[j] = q.hi;
+        qlo[j] = q.lo;
       }
     }
     if (lane < nrows) {
 #pragma unroll
       for (int j = 0; j < KN; ++j)
         if (j < k) Qg[(row0 + lane) * a.ldq + j] = qv[j];
+      // DD result requested: its low words (qv holds the rounded sum)
+      if (pdd && a.Qlo)
+#pragma unroll
+        for (int j = 0; j < KN; ++j)
+          if (j < k) a.Qlo[(row0 + lane) * a.ldq + j] = qlo[j];
     }
     if (GR) {
       // rows past m contribute nothing: their T is zero (their Y is finite)
