@@ -218,15 +218,19 @@ typedef struct {
  * [Y | X], the DD factor (opts->fact, Cholesky or SVQB, with the corrected
  * projection coefficients) and the DD update of the narrow path, rounded
  * once into Q + Q_lo: Q (binary64, m x k, ldq) holds the rounded result and
- * Q_lo its DD low word (same layout), |Q_lo| <= ulp(Q)/2.  k <= 8.  The
- * other options are fixed (DD Gram, one pass, no shift); opts->flags may
- * carry BORTH_FLAG_SYNC and BORTH_FLAG_DD_DOT2.  R and C: binary64 words of
- * the factors.  Q and Q_lo must not alias X or each other.  Q alone equals
- * what borth_orthonormalize returns for the same one DD pass. */
+ * Q_lo its DD low word (same layout), |Q_lo| <= ulp(Q)/2.  k <= 8.  X_lo
+ * (may be NULL, same layout as X) makes the input DD as well, X + X_lo: the
+ * DD Gram then also sweeps [X | X_lo] and [Y | X_lo] and combines the
+ * blocks (ky + k <= 64), and the update starts from X + X_lo.  The other
+ * options are fixed (DD Gram, one pass, no shift); opts->flags may carry
+ * BORTH_FLAG_SYNC and BORTH_FLAG_DD_DOT2.  R and C: binary64 words of the
+ * factors.  Q and Q_lo must not alias X, X_lo or each other.  Without X_lo,
+ * Q alone equals what borth_orthonormalize returns for the same DD pass. */
 borth_status borth_orthonormalize_dd(borth_ctx ctx, int64_t m, int k, const double* X,
-                                     int64_t ldx, const double* Y, int64_t ldy, int ky,
-                                     double* Q, double* Q_lo, int64_t ldq, double* R, double* C,
-                                     const borth_opts* opts, borth_info* info);
+                                     const double* X_lo, int64_t ldx, const double* Y,
+                                     int64_t ldy, int ky, double* Q, double* Q_lo, int64_t ldq,
+                                     double* R, double* C, const borth_opts* opts,
+                                     borth_info* info);
 
 /* Iterated two-phase scheme (Sec. 4.2: phase I and phase II alternated until
  * the block no longer changes): pass j projects the current block S_j (X,

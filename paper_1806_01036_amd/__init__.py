@@ -251,10 +251,11 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
     return Q, R, (C if ky else None), info
 
 
-def orthonormalize_dd(X, Y=None, *, fact="chol", dot2=False, out=None, out_lo=None, R=None,
-                      C=None, check=True, ctx=None):
+def orthonormalize_dd(X, Y=None, *, X_lo=None, fact="chol", dot2=False, out=None, out_lo=None,
+                      R=None, C=None, check=True, ctx=None):
     """One DD pass (k <= 8) returning the result in double-double:
-    (Q, Q_lo, R, C, Info) with Q + Q_lo the DD Q (borth_orthonormalize_dd)."""
+    (Q, Q_lo, R, C, Info) with Q + Q_lo the DD Q (borth_orthonormalize_dd).
+    ``X_lo``: low words of a DD input X + X_lo (same shape and strides)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
     m, k = X.shape
@@ -264,12 +265,14 @@ def orthonormalize_dd(X, Y=None, *, fact="chol", dot2=False, out=None, out_lo=No
     Ql = out_lo if out_lo is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
     if _ld(Ql) != _ld(Q):
         raise ValueError("Q and Q_lo need the same leading dimension")
+    if X_lo is not None and (X_lo.shape != X.shape or _ld(X_lo) != _ld(X)):
+        raise ValueError("X_lo needs the shape and leading dimension of X")
     R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
     if ky and C is None:
         C = torch.empty((ky, k), dtype=torch.float64, device=dev)
     o = _opts("dd_dot2" if dot2 else "dd", fact, 1, "materialize", 0.0, 0)
     inf = _lib.borth_info()
-    st = ctx.lib.borth_orthonormalize_dd(ctx.h, m, k, _ptr(X), _ld(X), _ptr(Y),
+    st = ctx.lib.borth_orthonormalize_dd(ctx.h, m, k, _ptr(X), _ptr(X_lo), _ld(X), _ptr(Y),
                                          _ld(Y) if ky else 0, ky, _ptr(Q), _ptr(Ql), _ld(Q),
                                          _ptr(R), _ptr(C) if ky else None, ctypes.byref(o),
                                          ctypes.byref(inf))

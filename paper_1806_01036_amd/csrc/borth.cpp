@@ -120,7 +120,8 @@ struct OrthoCall {
   double* R;
   double* C;
   borth_opts o;
-  double* Qlo;  // one DD pass on a narrow block: the result's low words, or null
+  double* Qlo;        // one DD pass on a narrow block: the result's low words, or null
+  const double* Xlo;  // ... and the low words of a DD input X, or null
 };
 
 borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
@@ -164,6 +165,24 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     prof_end(c, 0);
     HIPCHK(c, launch_reduce(L1, dd ? 1 : 0, c->part, nwg, ws + W.g_hi, dd ? ws + W.g_lo : nullptr, st),
            "reduce");
+    if (a.Xlo) {
+      // DD input X = X + X_lo: the Grams of [X | X_lo] and [Y | X_lo] as well,
+      // combined with the one above into the DD Gram of [Y | X + X_lo]
+      Src sb{a.X ? (const double*)a.X : nullptr, a.ldx, a.Xlo, a.ldx, 0, a.m};
+      sb.dot2 = s1.dot2;
+      const GramLayout Lb = make_layout(a.k, a.k, 4);
+      HIPCHK(c, launch_gram(sb, Lb, 1, c->part, c->part_cap, &nwg, TuneGram{}, st), "gram (X, X_lo)");
+      HIPCHK(c, launch_reduce(Lb, 1, c->part, nwg, ws + W.zp[1], ws + W.zp[2], st), "reduce");
+      if (hasy) {
+        Src sc{a.Y, a.ldy, a.Xlo, a.ldx, 0, a.m};
+        sc.dot2 = s1.dot2;
+        HIPCHK(c, launch_gram(sc, L1, 1, c->part, c->part_cap, &nwg, TuneGram{}, st), "gram (Y, X_lo)");
+        HIPCHK(c, launch_reduce(L1, 1, c->part, nwg, ws + W.cp[1], ws + W.cp[2], st), "reduce");
+      }
+      HIPCHK(c, launch_gram_dd_combine(a.ky, a.k, ws + W.g_hi, ws + W.g_lo, ws + W.zp[1],
+                                       ws + W.zp[2], ws + W.cp[1], ws + W.cp[2], st),
+             "combine");
+    }
   }
   // One DD pass on a narrow block: the update runs in DD as well (the
   // factor then also gives the low words of Z and C).
@@ -221,7 +240,10 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     u.dense = a.o.fact == BORTH_SVQB;
     u.Q = a.Q;
     u.ldq = a.ldq;
-    if (dd_update) u.Qlo = a.Qlo;
+    if (dd_update) {
+      u.Qlo = a.Qlo;
+      u.Xlo = a.Xlo;
+    }
     prof_begin(c, 1);
     HIPCHK(c, launch_update(u, Lu, lookup(c->tune_upd, 0, kp, hasy), st), "update");
     prof_end(c, 1);
@@ -339,7 +361,7 @@ borth_status read_status(borth_ctx c, borth_info* info) {
 borth_status ortho_enqueue(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
                            int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
                            int64_t ldq, double* R, double* C, const borth_opts& o,
-                           double* Qlo = nullptr);
+                           double* Qlo = nullptr, const double* Xlo = nullptr);
 
 bool log_enabled() {
   static const bool on = [] {
@@ -613,11 +635,12 @@ namespace {
 // cached hipGraph with BORTH_FLAG_GRAPH); arguments already validated.
 borth_status ortho_enqueue(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
                            int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
-                           int64_t ldq, double* R, double* C, const borth_opts& o, double* Qlo) {
+                           int64_t ldq, double* R, double* C, const borth_opts& o, double* Qlo,
+                           const double* Xlo) {
   borth_status r = ensure(c, &c->part, &c->part_cap, partial_need(ky, k, o.gram));
   if (r) return r;
   c->last_est = true;
-  OrthoCall a{m, k, ky, dt, X, ldx, Y, ldy, Q, ldq, R, C, o, Qlo};
+  OrthoCall a{m, k, ky, dt, X, ldx, Y, ldy, Q, ldq, R, C, o, Qlo, Xlo};
   if (o.flags & BORTH_FLAG_GRAPH) {
     GraphKey key;
     key.v = {m, k, ky, (int64_t)dt, (int64_t)(intptr_t)X, ldx, (int64_t)(intptr_t)Y, ldy,
@@ -825,17 +848,19 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
 }  // namespace
 
 borth_status borth_orthonormalize_dd(borth_ctx c, int64_t m, int k, const double* X,
-                                     int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
-                                     double* Q_lo, int64_t ldq, double* R, double* C,
-                                     const borth_opts* opts, borth_info* info) {
+                                     const double* X_lo, int64_t ldx, const double* Y, int64_t ldy,
+                                     int ky, double* Q, double* Q_lo, int64_t ldq, double* R,
+                                     double* C, const borth_opts* opts, borth_info* info) {
   if (!c) return BORTH_ERR_ARG;
   borth_opts o;
   if (opts) o = *opts; else borth_default_opts(&o);
   if (k < 1 || k > 8 || ky < 0 || ky > 64 || m < (int64_t)k + ky) return fail_arg(c, "shape (k <= 8)");
   if (!X || !Q || !Q_lo || ldx < k || ldq < k) return fail_arg(c, "X/Q/Q_lo");
   if (ky > 0 && (!Y || ldy < ky)) return fail_arg(c, "Y");
-  if ((const void*)Q == (const void*)X || (const void*)Q_lo == (const void*)X || Q_lo == Q)
-    return fail_arg(c, "Q and Q_lo must not alias X or each other");
+  if ((const void*)Q == (const void*)X || (const void*)Q_lo == (const void*)X || Q_lo == Q ||
+      (X_lo && ((const void*)X_lo == (const void*)Q || (const void*)X_lo == (const void*)Q_lo)))
+    return fail_arg(c, "Q and Q_lo must not alias X, X_lo or each other");
+  if (X_lo && ky + k > 64) return fail_arg(c, "a DD input needs ky + k <= 64");
   if (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB) return fail_arg(c, "opts.fact");
   o.gram = BORTH_GRAM_DD;
   o.passes = 1;
@@ -843,7 +868,12 @@ borth_status borth_orthonormalize_dd(borth_ctx c, int64_t m, int k, const double
   o.shift = 0.0;
   o.flags &= (BORTH_FLAG_SYNC | BORTH_FLAG_DD_DOT2);
   hipSetDevice(c->device);
-  borth_status r = ortho_enqueue(c, m, k, BORTH_F64, X, ldx, Y, ldy, ky, Q, ldq, R, C, o, Q_lo);
+  if (X_lo) {  // partial sums of the [X | X_lo] sweep
+    const borth_status re = ensure(c, &c->part, &c->part_cap,
+                                   kMaxSweepWG * (int64_t)make_layout(k, k, 4).E * 2);
+    if (re) return re;
+  }
+  borth_status r = ortho_enqueue(c, m, k, BORTH_F64, X, ldx, Y, ldy, ky, Q, ldq, R, C, o, Q_lo, X_lo);
   if (r) return r;
   const bool sync = info || (o.flags & BORTH_FLAG_SYNC);
   borth_info local;

@@ -861,6 +861,38 @@ hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, 
   return launch_reduce_segs(mode, reduce_blocks(L.E), 1, r, nullptr, st);
 }
 
+// DD Gram of [Y | X] for X = X_hi + X_lo (both binary64 words given), from
+// the DD Grams A of [Y | X_hi], B of [X_hi | X_lo] and C of [Y | X_lo]
+// (unpadded, row stride = width): G_YY = A_YY, G_YX = A_YX + C_YX and
+// G_XX = B_hh + B_hl + B_lh + B_ll, DD additions, written over A.
+__global__ void gram_dd_combine_kernel(int ky, int k, double* Ahi, double* Alo,
+                                       const double* Bhi, const double* Blo, const double* Chi,
+                                       const double* Clo) {
+  const int W = ky + k, e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= W * W) return;
+  const int i = e / W, j = e % W;
+  if (i < ky && j < ky) return;
+  dd_t v;
+  if (i >= ky && j >= ky) {
+    const int a = i - ky, b = j - ky, WB = 2 * k;
+    auto g = [&](int r, int c) { return dd_make(Bhi[r * WB + c], Blo[r * WB + c]); };
+    v = dd_add(dd_add(g(a, b), g(a, k + b)), dd_add(g(k + a, b), g(k + a, k + b)));
+  } else {
+    v = dd_add(dd_make(Ahi[e], Alo[e]), dd_make(Chi[e], Clo[e]));
+  }
+  Ahi[e] = v.hi;
+  Alo[e] = v.lo;
+}
+
+hipError_t launch_gram_dd_combine(int ky, int k, double* Ahi, double* Alo, const double* Bhi,
+                                  const double* Blo, const double* Chi, const double* Clo,
+                                  hipStream_t st) {
+  const int n = (ky + k) * (ky + k);
+  hipLaunchKernelGGL(gram_dd_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, st, ky, k, Ahi,
+                     Alo, Bhi, Blo, Chi, Clo);
+  return hipGetLastError();
+}
+
 __global__ void fill_int_kernel(int* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

@@ -118,6 +118,11 @@ struct ReduceSeg {
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
                          double* G_hi, double* G_lo, hipStream_t st, const int* stop = nullptr,
                          int pass = 0);
+// DD Gram of [Y | X] with X = X_hi + X_lo: from the DD Grams A of [Y | X_hi],
+// B of [X_hi | X_lo] and C of [Y | X_lo] (unpadded), written over A.
+hipError_t launch_gram_dd_combine(int ky, int k, double* Ahi, double* Alo, const double* Bhi,
+                                  const double* Blo, const double* Chi, const double* Clo,
+                                  hipStream_t st);
 // Blocks (grid.x) of the reduction of a Gram with E entries.
 int reduce_blocks(int E);
 // nseg segments (grid.y); nb = the largest reduce_blocks(L.E) among them.
@@ -181,6 +186,7 @@ struct UpdateArgs {
   int dense;                           // Z dense (SVQB)
   double* Q; int64_t ldq;
   double* Qlo;                         // narrow DD update: low words of Q (ldq), or null
+  const double* Xlo;                   // narrow DD update: low words of X (ldx), or null
   double* partials; int64_t partial_cap_doubles;
   int gram_xcols;                      // narrow fused Gram: [Y | T]^T T only
   int gram_dd;                         //   ... in DD
@@ -205,6 +211,7 @@ struct UpdDev {
   double* Q;
   int64_t ldq;
   double* Qlo;  // narrow DD update: the DD result's low words (ldq), or null
+  const double* Xlo;  // narrow DD update: low words of a DD input X (ldx), or null
   double* part;
   int64_t npanels;
   const double* C1;  // stage coefficients (ky x K C, K x K Z, zero padded)

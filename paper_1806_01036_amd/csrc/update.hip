@@ -63,6 +63,7 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.Q = a.Q;
   d.ldq = a.ldq;
   d.Qlo = a.Qlo;
+  d.Xlo = a.Xlo;
   d.part = a.partials;
   const int PR = upd::upd_rows(K);
   d.npanels = (a.src.m + PR - 1) / PR;
@@ -77,7 +78,7 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.pass = a.src.pass;
   if (a.bw && !(a.partials && a.gram_xcols)) return hipErrorInvalidValue;
   // DD arithmetic exists in the narrow kernel only (and with it DD results)
-  if (a.Qlo && !(a.C1lo && a.Z1lo)) return hipErrorInvalidValue;
+  if ((a.Qlo || a.Xlo) && !(a.C1lo && a.Z1lo)) return hipErrorInvalidValue;
   if ((a.C1lo || a.Z1lo) && (a.two_stage || a.src.x_f32 || !update_narrow_ok(L.k, L.ky, K)))
     return hipErrorInvalidValue;
   if (!a.partials && !a.two_stage && !a.src.x_f32 && a.Q && update_narrow_ok(L.k, L.ky, K)) {

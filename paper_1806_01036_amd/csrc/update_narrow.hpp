@@ -230,7 +230,8 @@ __global__ void __launch_bounds__(64) narrow_kernel(UpdDev a, int kp, GramLayout
 #pragma unroll
       for (int j = 0; j < KN; ++j) {
         ts[j] = xs[j];
-        te[j] = 0.0;
+        // a DD input X: its low word starts the error term
+        te[j] = (a.Xlo && lane < nrows && j < k) ? a.Xlo[(row0 + lane) * a.ldx + j] : 0.0;
       }
       if (KYB > 0) {
         const double* yrow = pan + lane * SP;

@@ -84,3 +84,25 @@ def test_dd_result_argument_checks():
     X4 = dev(synth.svd_matrix(2000, 4, 10.0, 7961))
     with pytest.raises(Exception):  # Q_lo aliasing X
         borth.orthonormalize_dd(X4, out_lo=X4)
+
+
+@pytest.mark.parametrize("ky", [20, 0])
+def test_dd_input(ky):
+    """A DD input X + X_lo (|X_lo| up to ulp(X)/2): the result is orthonormal
+    at the DD level only if both the Gram (its [X | X_lo] and [Y | X_lo]
+    blocks) and the update see X_lo -- leaving it out of either would leave
+    an error of about |X_lo| / |X| ~ 1e-16 in omega or omega_Y."""
+    borth = lib()
+    X, Y = synth.projected_pair(N, K, KY, 10.0, 10.0, 7970)
+    rng = np.random.default_rng(7971)
+    Xl = (rng.random(X.shape) - 0.5) * np.spacing(np.abs(X))
+    Yd = dev(Y) if ky else None
+    Q, Ql, R, C, info = borth.orthonormalize_dd(dev(X), Yd, X_lo=dev(Xl), dot2=True)
+    assert info.status == 0
+    om, omy = dd_levels(host(Q), host(Ql), Y if ky else None)
+    note("dd input", ky, om, omy)
+    assert om <= 1e-27 and omy <= 1e-27
+    # the same X without its low words gives a different DD result
+    Q0, Ql0, _, _, _ = borth.orthonormalize_dd(dev(X), Yd, dot2=True)
+    d = np.max(np.abs((host(Q) - host(Q0)) + (host(Ql) - host(Ql0))))
+    assert 1e-20 < d < 1e-14
