@@ -45,7 +45,7 @@ DD_GRAM_OPS = 4.0
 # those sources change.
 DD_GRAM_TRAFFIC = {"bytes": 1.0337e9,
                    "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
-                   "sha256": "15773e820d5d240db982b8c78048235e6690a2d2915921e3f738511a33103c12"}
+                   "sha256": "f82c05898bbd52adf5d908b1486ad6e1b0a0f8561e5d70cca29d05fe40e67c98"}
 
 
 def measured_traffic(rec):
