@@ -106,7 +106,8 @@ typedef struct {
   int passes;     /* 1, 2 (default) or 3 */
   int sched;      /* borth_sched */
   double shift;   /* first-pass Cholesky shift, relative: M + shift * trace(M) I.
-                     < 0: automatic (2^-13 for the split mode, 0 otherwise). */
+                     < 0: automatic (2^-13 for the split mode, 0 otherwise);
+                     NaN or infinite: BORTH_ERR_ARG. */
   unsigned flags; /* BORTH_FLAG_* */
 } borth_opts;
 
@@ -162,7 +163,8 @@ borth_status borth_gram(borth_ctx ctx, int64_t m, int ka, const double* A, int64
  * Z^T M Z = I): from the Gram matrix G of [Y | X] (W x W,
  * W = ky + k, hi and optional lo words), form
  *     C = G_YX,  M = G_XX - 2 C^T C + C^T G_YY C  (= Xt^T Xt exactly),
- * add shift * trace(M) to the diagonal if shift > 0, and factor M in DD
+ * add shift * trace(M) to the diagonal if shift > 0 (a NaN or infinite
+ * shift is BORTH_ERR_ARG), and factor M in DD
  * (G_lo != NULL) or binary64: Cholesky M = R^T R, Z = R^{-1} (upper), or SVQB
  * Z = M^{-1/2}, R = M^{1/2} (Jacobi in the same precision; eigenvalues below
  * 2^-52 lambda_max, DD: 2^-104 lambda_max, lifted to that floor).  Outputs (device, may be NULL):

@@ -486,7 +486,7 @@ GraphKey batch_key(borth_ctx c, int nb, const borth_block* B, const borth_opts& 
   k.v.push_back(o.gram);
   k.v.push_back(o.fact);
   k.v.push_back(o.passes);
-  k.v.push_back((int64_t)(o.shift * 1e18));
+  k.v.push_back(key_bits(o.shift));
   k.v.push_back((int64_t)(o.flags & ~(unsigned)BORTH_FLAG_SYNC));
   k.v.push_back((int64_t)c->tune_generation);
   for (int b = 0; b < nb; ++b) {
@@ -517,6 +517,7 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
   if (nblocks < 0 || (nblocks > 0 && !blocks)) return fail_arg(c, "blocks");
   if (nblocks == 0) return BORTH_OK;
   if (o.passes < 1 || o.passes > 3) return fail_arg(c, "passes");
+  if (!std::isfinite(o.shift)) return fail_arg(c, "shift");
   if (o.gram != BORTH_GRAM_F64 && o.gram != BORTH_GRAM_DD) {
     if (o.gram == BORTH_GRAM_SPLIT_BF16) {
       c->err = "the batched path takes binary64 blocks (no split-BF16 mode)";
@@ -559,8 +560,9 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
       if (!c->cap_stream)
         HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
       HIPCHK(c, hipStreamSynchronize(c->stream), "sync before capture");
+      const hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (eb != hipSuccess) return fail_hip(c, eb, "hipStreamBeginCapture");
       c->capturing = true;
-      HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
       borth_status r = run_plan(c, P, c->cap_stream);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(c->cap_stream, &g);

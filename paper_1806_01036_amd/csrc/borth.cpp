@@ -496,6 +496,7 @@ borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const 
   if (!c) return BORTH_ERR_ARG;
   if (k < 1 || k > 64 || ky < 0 || ky > 64 || !G_hi) return fail_arg(c, "shape");
   if (fact != BORTH_CHOL && fact != BORTH_SVQB) return fail_arg(c, "fact");
+  if (!std::isfinite(shift)) return fail_arg(c, "shift");
   hipSetDevice(c->device);
   c->cur = c->stream;
   const WsLayout W = ws_layout();
@@ -574,6 +575,7 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
   if (!X || !Q || ldx < k || ldq < k) return fail_arg(c, "X/Q");
   if (ky > 0 && (!Y || ldy < ky)) return fail_arg(c, "Y");
   if (o.passes < 1 || o.passes > 3) return fail_arg(c, "passes");
+  if (!std::isfinite(o.shift)) return fail_arg(c, "shift");
   if (o.gram < 0 || o.gram > 2 || (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB)) return fail_arg(c, "opts");
   if (o.gram == BORTH_GRAM_SPLIT_BF16 && (dt != BORTH_F32 || ky > 0))
     return fail_arg(c, "split mode needs fp32 X and no locked basis");
@@ -645,16 +647,17 @@ borth_status ortho_enqueue(borth_ctx c, int64_t m, int k, borth_dtype dt, const 
     GraphKey key;
     key.v = {m, k, ky, (int64_t)dt, (int64_t)(intptr_t)X, ldx, (int64_t)(intptr_t)Y, ldy,
              (int64_t)(intptr_t)Q, ldq, (int64_t)(intptr_t)R, (int64_t)(intptr_t)C, o.gram, o.fact,
-             o.passes, o.sched, (int64_t)(o.shift * 1e18), (int64_t)o.flags,
+             o.passes, o.sched, key_bits(o.shift), (int64_t)o.flags,
              (int64_t)c->ws_generation};
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
       if (!c->cap_stream)
         HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
       HIPCHK(c, hipStreamSynchronize(c->stream), "sync before capture");
+      const hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (eb != hipSuccess) return fail_hip(c, eb, "hipStreamBeginCapture");
       c->capturing = true;
       c->cur = c->cap_stream;
-      HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
       r = enqueue_ortho(c, a);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(c->cap_stream, &g);

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <map>
 #include <string>
 #include <tuple>
@@ -14,6 +15,14 @@ struct GraphKey {
   std::vector<int64_t> v;
   bool operator<(const GraphKey& o) const { return v < o.v; }
 };
+
+// A double as a cache-key entry: its bit pattern (defined for every value,
+// unlike a scaled integer conversion).
+inline int64_t key_bits(double x) {
+  int64_t b;
+  std::memcpy(&b, &x, sizeof b);
+  return b;
+}
 
 struct TimedPair {
   hipEvent_t a, b;

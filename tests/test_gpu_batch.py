@@ -195,6 +195,8 @@ def test_batch_argument_errors():
         borth.batch_orthonormalize([{"X": X, "Y": dev(np.zeros((100, 20)))}])  # ky > 16
     with pytest.raises(borth.BorthError):
         borth.batch_orthonormalize([{"X": dev(np.zeros((100, 8), np.float32))}], gram="split")
+    with pytest.raises(borth.BorthError):
+        borth.batch_orthonormalize([{"X": X}], shift=float("nan"))
 
 
 def test_autotune_roundtrip(tmp_path):

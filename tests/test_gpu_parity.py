@@ -539,6 +539,11 @@ def test_edges():
         borth.orthonormalize(dev(np.zeros((3, 5))))  # m < k
     with pytest.raises(borth.BorthError):
         borth.orthonormalize(dev(np.zeros((300, 65))))  # k > 64
+    for bad in (float("nan"), float("inf")):
+        with pytest.raises(borth.BorthError):
+            borth.orthonormalize(dev(np.eye(300, 6)), shift=bad)
+        with pytest.raises(borth.BorthError):
+            borth.factor(dev(np.eye(6)), shift=bad)
 
 
 def test_deterministic_and_graph_replay():
