@@ -44,6 +44,14 @@ class Breakdown(BorthError):
     pass
 
 
+class ArgumentError(BorthError, ValueError):
+    """An argument the binding rejects before calling the library (the
+    library's own checks report the same status, ERR_ARG)."""
+
+    def __init__(self, msg):
+        super().__init__(ERR_ARG, msg)
+
+
 @dataclass
 class Info:
     status: int
@@ -145,8 +153,38 @@ def _ld(t):
     if t is None:
         return 0
     if t.dim() != 2 or t.stride(1) != 1:
-        raise ValueError("matrices must be 2-D with unit column stride")
+        raise ArgumentError("matrices must be 2-D with unit column stride")
     return t.stride(0)
+
+
+def _mat(t, name, ctx, rows=None, cols=None, f32=False, packed=False):
+    """Check a matrix before its pointer goes to the library, which can
+    check nothing about device memory: a 2-D tensor on the context's device,
+    float64 (or float32 where ``f32``), unit column stride, leading dimension
+    >= columns, the expected shape; ``packed``: a contiguous rows x cols
+    array (R, C, Z and the Gram matrices have no leading dimension)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dim() != 2:
+        raise ArgumentError(f"{name}: a 2-D tensor is required")
+    if t.device.type != "cuda" or t.device.index != ctx.device:
+        raise ArgumentError(f"{name}: must be on cuda:{ctx.device}, got {t.device}")
+    if not (t.dtype == torch.float64 or (f32 and t.dtype == torch.float32)):
+        raise ArgumentError(f"{name}: float64{' or float32' if f32 else ''} required, got {t.dtype}")
+    if (rows is not None and t.shape[0] != rows) or (cols is not None and t.shape[1] != cols):
+        raise ArgumentError(f"{name}: shape {tuple(t.shape)}, expected ({rows}, {cols})")
+    if packed:
+        if not t.is_contiguous():
+            raise ArgumentError(f"{name}: must be contiguous")
+    elif t.shape[1] > 1 and t.stride(1) != 1 or t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ArgumentError(f"{name}: rows must be contiguous (unit column stride, ld >= columns)")
+    return t
+
+
+def _outs(ctx, Q, R, C, m, k, ky):
+    _mat(Q, "out", ctx, m, k)
+    _mat(R, "R", ctx, k, k, packed=True)
+    if ky:
+        _mat(C, "C", ctx, ky, k, packed=True)
 
 
 def _dt(t):
@@ -155,14 +193,17 @@ def _dt(t):
         return 0
     if t.dtype == torch.float32:
         return 1
-    raise TypeError("float64 or float32 tensors only")
+    raise ArgumentError("float64 or float32 tensors only")
 
 
 def gram(B, A=None, prec="f64", ctx=None):
     """G = [A | B]^T [A | B] (hi, lo); lo is None unless prec is 'dd' or 'dd_dot2'."""
     torch = _torch()
     ctx = ctx or default_context(B.device.index)
+    _mat(B, "B", ctx, f32=True)
     m, kb = B.shape
+    if A is not None:
+        _mat(A, "A", ctx, rows=m)
     ka = 0 if A is None else A.shape[1]
     W = ka + kb
     ghi = torch.empty((W, W), dtype=torch.float64, device=B.device)
@@ -179,6 +220,9 @@ def factor(G_hi, G_lo=None, ky=0, fact="chol", shift=0.0, ctx=None, check=True):
     torch = _torch()
     ctx = ctx or default_context(G_hi.device.index)
     W = G_hi.shape[0]
+    _mat(G_hi, "G_hi", ctx, W, W, packed=True)
+    if G_lo is not None:
+        _mat(G_lo, "G_lo", ctx, W, W, packed=True)
     k = W - ky
     dev = G_hi.device
     Z = torch.zeros((k, k), dtype=torch.float64, device=dev)
@@ -198,9 +242,17 @@ def update(X, Z, Y=None, C=None, dense=False, out=None, ctx=None):
     """Q = (X - Y C) Z (binary64 result)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
+    _mat(X, "X", ctx, f32=True)
     m, k = X.shape
+    _mat(Z, "Z", ctx, k, k, packed=True)
     ky = 0 if Y is None else Y.shape[1]
+    if ky:
+        _mat(Y, "Y", ctx, rows=m)
+        if C is None:
+            raise ArgumentError("C is required with Y")
+        _mat(C, "C", ctx, ky, k, packed=True)
     Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=X.device)
+    _mat(Q, "out", ctx, m, k)
     ctx.check(ctx.lib.borth_update(ctx.h, m, k, _dt(X), _ptr(X), _ld(X), _ptr(Y),
                                    _ld(Y) if ky else 0, ky, _ptr(C), _ptr(Z), int(bool(dense)),
                                    _ptr(Q), _ld(Q)))
@@ -230,13 +282,17 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
     shifted DD first pass and three passes (synchronizes)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
+    _mat(X, "X", ctx, f32=True)
     m, k = X.shape
     ky = 0 if Y is None else Y.shape[1]
+    if ky:
+        _mat(Y, "Y", ctx, rows=m)
     dev = X.device
     Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
     R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
     if ky and C is None:
         C = torch.empty((ky, k), dtype=torch.float64, device=dev)
+    _outs(ctx, Q, R, C, m, k, ky)
     flags = ((FLAG_PROJECT_ONCE if project_once else 0) | (FLAG_GRAPH if graph else 0)
              | (FLAG_AUTO_ESCALATE if escalate else 0))
     o = _opts(gram, fact, passes, sched, shift, flags)
@@ -258,18 +314,25 @@ def orthonormalize_dd(X, Y=None, *, X_lo=None, fact="chol", dot2=False, out=None
     ``X_lo``: low words of a DD input X + X_lo (same shape and strides)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
+    _mat(X, "X", ctx)
     m, k = X.shape
     ky = 0 if Y is None else Y.shape[1]
+    if ky:
+        _mat(Y, "Y", ctx, rows=m)
     dev = X.device
     Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
     Ql = out_lo if out_lo is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
+    _mat(Ql, "out_lo", ctx, m, k)
+    if X_lo is not None:
+        _mat(X_lo, "X_lo", ctx, m, k)
     if _ld(Ql) != _ld(Q):
-        raise ValueError("Q and Q_lo need the same leading dimension")
+        raise ArgumentError("Q and Q_lo need the same leading dimension")
     if X_lo is not None and (X_lo.shape != X.shape or _ld(X_lo) != _ld(X)):
-        raise ValueError("X_lo needs the shape and leading dimension of X")
+        raise ArgumentError("X_lo needs the shape and leading dimension of X")
     R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
     if ky and C is None:
         C = torch.empty((ky, k), dtype=torch.float64, device=dev)
+    _outs(ctx, Q, R, C, m, k, ky)
     o = _opts("dd_dot2" if dot2 else "dd", fact, 1, "materialize", 0.0, 0)
     inf = _lib.borth_info()
     st = ctx.lib.borth_orthonormalize_dd(ctx.h, m, k, _ptr(X), _ptr(X_lo), _ld(X), _ptr(Y),
@@ -303,13 +366,17 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
     Returns (Q, R, C, IterInfo, Info)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
+    _mat(X, "X", ctx, f32=True)
     m, k = X.shape
     ky = 0 if Y is None else Y.shape[1]
+    if ky:
+        _mat(Y, "Y", ctx, rows=m)
     dev = X.device
     Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
     R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
     if ky and C is None:
         C = torch.empty((ky, k), dtype=torch.float64, device=dev)
+    _outs(ctx, Q, R, C, m, k, ky)
     o = _opts(gram, fact, 1, "materialize", 0.0,
               (0 if fuse else FLAG_NO_FUSE) | (FLAG_RANK_REVEAL if rank_reveal else 0))
     it = _lib.borth_iter_info()
@@ -320,8 +387,9 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
             _ptr(R), _ptr(C) if ky else None, ctypes.byref(o), float(eps), int(max_iter),
             ctypes.byref(it), ctypes.byref(inf))
     else:
-        if B.dim() != 1 or B.shape[0] != m or B.dtype != torch.float64 or not B.is_contiguous():
-            raise ValueError("B must be a contiguous float64 vector of m weights")
+        if (B.dim() != 1 or B.shape[0] != m or B.dtype != torch.float64 or not B.is_contiguous()
+                or B.device.type != "cuda" or B.device.index != ctx.device):
+            raise ArgumentError(f"B must be a contiguous float64 vector of m weights on cuda:{ctx.device}")
         st = ctx.lib.borth_orthonormalize_iter_b(
             ctx.h, m, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y) if ky else 0, ky, _ptr(B), _ptr(Q),
             _ld(Q), _ptr(R), _ptr(C) if ky else None, ctypes.byref(o), float(eps), int(max_iter),
@@ -349,10 +417,12 @@ def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0
     arr = (_lib.borth_block * len(blocks))()
     outs = []
     for i, b in enumerate(blocks):
-        X = b["X"]
+        X = _mat(b["X"], f"blocks[{i}].X", ctx)
         Y = b.get("Y")
         m, k = X.shape
         ky = 0 if Y is None else Y.shape[1]
+        if ky:
+            _mat(Y, f"blocks[{i}].Y", ctx, rows=m)
         Q = b.get("Q")
         if Q is None:
             Q = torch.empty((m, k), dtype=torch.float64, device=X.device)
@@ -362,6 +432,10 @@ def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0
         Ct = b.get("C")
         if ky and Ct is None:
             Ct = torch.empty((ky, k), dtype=torch.float64, device=X.device)
+        _mat(Q, f"blocks[{i}].Q", ctx, m, k)
+        _mat(Rt, f"blocks[{i}].R", ctx, k, k, packed=True)
+        if ky:
+            _mat(Ct, f"blocks[{i}].C", ctx, ky, k, packed=True)
         e = arr[i]
         e.m, e.k, e.X, e.ldx = m, k, X.data_ptr(), _ld(X)
         e.Y, e.ldy, e.ky = (Y.data_ptr() if ky else None), (_ld(Y) if ky else 0), ky

@@ -97,3 +97,20 @@ def test_struct_layouts_match_binding(tmp_path):
         assert int(out[name]) == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert int(out[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
+
+
+def test_binding_rejects_host_and_malformed_tensors():
+    """The binding's tensor checks run before any pointer reaches the
+    library (which cannot check device memory): host tensors, wrong ranks
+    and non-tensors are refused on the CPU already."""
+    import types
+    import torch
+    import paper_1806_01036_amd as borth
+    ctx = types.SimpleNamespace(device=0)
+    for bad in (torch.zeros((10, 3), dtype=torch.float64), torch.zeros(10, dtype=torch.float64),
+                [[1.0, 2.0]], None):
+        with pytest.raises(borth.ArgumentError):
+            borth._mat(bad, "X", ctx)
+    err = borth.ArgumentError("x")
+    assert isinstance(err, ValueError) and isinstance(err, borth.BorthError)
+    assert err.status == borth.ERR_ARG

@@ -544,6 +544,22 @@ def test_edges():
             borth.orthonormalize(dev(np.eye(300, 6)), shift=bad)
         with pytest.raises(borth.BorthError):
             borth.factor(dev(np.eye(6)), shift=bad)
+    # tensors the binding rejects before any pointer reaches the library
+    Xd = dev(np.eye(300, 6))
+    bad_calls = [
+        lambda: borth.orthonormalize(torch.zeros((300, 6), dtype=torch.float64)),  # host tensor
+        lambda: borth.orthonormalize(Xd, out=dev(np.zeros((299, 6)))),  # short Q
+        lambda: borth.orthonormalize(Xd, R=dev(np.zeros((6, 5)))),  # wrong R shape
+        lambda: borth.orthonormalize(Xd, R=dev(np.zeros((6, 12)))[:, :6]),  # strided R
+        lambda: borth.orthonormalize(Xd, dev(np.zeros((200, 2)))),  # Y rows != m
+        lambda: borth.orthonormalize(Xd.to(torch.float16)),  # dtype
+        lambda: borth.update(Xd, dev(np.eye(5))),  # Z shape
+        lambda: borth.gram(Xd, dev(np.zeros((100, 2)))),  # A rows != m
+        lambda: borth.batch_orthonormalize([{"X": Xd, "R": dev(np.zeros((5, 5)))}]),
+    ]
+    for i, call in enumerate(bad_calls):
+        with pytest.raises(borth.ArgumentError):
+            call()
 
 
 def test_deterministic_and_graph_replay():
