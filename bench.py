@@ -156,6 +156,14 @@ def run_c3(args, torch, borth, synth):
                              ctx=ctx)
     tf2 = timed(torch, step_f2, args.steps, args.warmup)
 
+    # streaming probes on the same X: a plain read (torch's sum reduction,
+    # 8 m k bytes) and a plain copy (8 m k read + 8 m k written)
+    acc = torch.empty((), dtype=torch.float64, device="cuda")
+    t_read = timed(torch, lambda: torch.sum(Xd, dim=(0, 1), out=acc), 20, 5)
+    t_copy = timed(torch, lambda: Qp.copy_(Xd), 20, 5)
+    read_gbs = 8.0 * m * k / t_read / 1e9
+    copy_gbs = 16.0 * m * k / t_copy / 1e9
+
     bytes_step = 32.0 * m * k
     gbs = bytes_step / t / 1e9 if om <= 1e-14 else 0.0
     # dominant kernel: the DD Gram sweep, bound by the FP64 vector ALUs.
@@ -179,6 +187,8 @@ def run_c3(args, torch, borth, synth):
                                "(U diag(sigma) V^T, seed 302)",
                    "m": m, "k": k, "kappa": kappa, "passes": 2, "gram": "dd"},
         "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+        "stream_probe": {"read_GBs": round(read_gbs, 1), "copy_GBs": round(copy_gbs, 1),
+                         "value_over_read_probe": round(gbs / read_gbs, 4)},
         "omega": om,
         "rho": rho,
         "plain_fp64_cholqr": {"ms_per_step": round(tp * 1e3, 4),
