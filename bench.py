@@ -85,6 +85,32 @@ def timed(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def step_stats(torch, fn, n=20):
+    """Per-step times (ms) of n more steps, each bracketed by its own pair of
+    events on the library's stream: median, min and 90th percentile."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"median": round(ms[n // 2], 4), "min": round(ms[0], 4),
+            "p90": round(ms[int(0.9 * (n - 1))], 4)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_cholqr2(X, dd, target_s=10.0):
     import oracle
     m = X.shape[0]
@@ -99,7 +125,7 @@ def cpu_baseline_cholqr2(X, dd, target_s=10.0):
         dt = time.perf_counter() - t0
     k = X.shape[1]
     return dict(value=32.0 * rows * k / dt / 1e9, unit="GB/s", cores=oracle.num_threads(),
-                kind="oracle",
+                kind="oracle", cpu_model=cpu_model(),
                 sample=f"oracle step-by-step {'DD' if dd else 'binary64'} CholQR2 on the first "
                        f"{rows} rows of the same X ({dt:.1f} s)")
 
@@ -136,6 +162,7 @@ def run_c3(args, torch, borth, synth):
     timed(torch, step, 5, 0)
     upd_ms, upd_n = ctx.kernel_time(1)
     ctx.set_profiling(False)
+    per_step = step_stats(torch, step)
     om = omega_dd(borth, Q)
     rho = rho_gpu(torch, Xd, Q, R)
     log(f"DD CholQR2: {t*1e3:.3f} ms/step omega={om:.2e} rho={rho:.2e} "
@@ -187,6 +214,7 @@ def run_c3(args, torch, borth, synth):
                                "(U diag(sigma) V^T, seed 302)",
                    "m": m, "k": k, "kappa": kappa, "passes": 2, "gram": "dd"},
         "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+        "step_ms": per_step,
         "stream_probe": {"read_GBs": round(read_gbs, 1), "copy_GBs": round(copy_gbs, 1),
                          "value_over_read_probe": round(gbs / read_gbs, 4)},
         "omega": om,
