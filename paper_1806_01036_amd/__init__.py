@@ -153,7 +153,8 @@ def _ld(t):
     if t is None:
         return 0
     if t.dim() != 2 or t.stride(1) != 1:
-        raise ArgumentError("matrices must be 2-D with unit column stride")
+        raise ArgumentError("matrices must be 2-D and row-major (unit column stride; "
+                            "use .contiguous())")
     return t.stride(0)
 
 
@@ -176,7 +177,8 @@ def _mat(t, name, ctx, rows=None, cols=None, f32=False, packed=False):
         if not t.is_contiguous():
             raise ArgumentError(f"{name}: must be contiguous")
     elif t.shape[1] > 1 and t.stride(1) != 1 or t.shape[0] > 1 and t.stride(0) < t.shape[1]:
-        raise ArgumentError(f"{name}: rows must be contiguous (unit column stride, ld >= columns)")
+        raise ArgumentError(f"{name}: must be row-major (unit column stride, ld >= columns; "
+                            "use .contiguous())")
     return t
 
 

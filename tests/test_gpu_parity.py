@@ -556,6 +556,7 @@ def test_edges():
         lambda: borth.update(Xd, dev(np.eye(5))),  # Z shape
         lambda: borth.gram(Xd, dev(np.zeros((100, 2)))),  # A rows != m
         lambda: borth.batch_orthonormalize([{"X": Xd, "R": dev(np.zeros((5, 5)))}]),
+        lambda: borth.orthonormalize(Xd, dev(np.zeros((2, 300))).t()),  # column-major Y
     ]
     for i, call in enumerate(bad_calls):
         with pytest.raises(borth.ArgumentError):
