@@ -315,7 +315,10 @@ borth_status borth_batch_orthonormalize(borth_ctx ctx, int nblocks, const borth_
 /* Times the tile/launch-shape candidates of the Gram and update kernels on
  * synthetic data resident on the device (~budget_ms in total), keeps the
  * fastest per (mode, width) in the context, and writes them as JSON to
- * cache_path (if not NULL).  borth_autotune_load reads such a file. */
+ * cache_path (if not NULL), with the device it was measured on
+ * (architecture, compute units, HIP runtime version).  borth_autotune_load
+ * reads such a file; one made on another device or runtime is refused with
+ * BORTH_ERR_ARG. */
 borth_status borth_autotune(borth_ctx ctx, const char* cache_path, int budget_ms);
 borth_status borth_autotune_load(borth_ctx ctx, const char* cache_path);
 

@@ -507,6 +507,22 @@ void batch_free_all(borth_ctx c) {
   c->plans.clear();
 }
 
+// The device a tuning belongs to: architecture, compute units and HIP runtime
+// version (a cache made elsewhere is refused on load).
+static std::string tune_device_key(borth_ctx c) {
+  hipDeviceProp_t p;
+  std::string arch = "unknown";
+  int cus = 0, rt = 0;
+  if (hipGetDeviceProperties(&p, c->device) == hipSuccess) {
+    arch = p.gcnArchName;
+    cus = p.multiProcessorCount;
+  }
+  hipRuntimeGetVersion(&rt);
+  for (char& ch : arch)
+    if (ch == '"' || ch == '\\') ch = '_';
+  return arch + "/" + std::to_string(cus) + "cu/hip" + std::to_string(rt);
+}
+
 extern "C" {
 
 borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_block* blocks,
@@ -752,7 +768,8 @@ borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) 
       c->err = std::string("cannot write ") + cache_path;
       return BORTH_ERR_ARG;
     }
-    std::fprintf(f, "{\"version\": 1, \"rows\": %lld, \"entries\": [\n", (long long)m);
+    std::fprintf(f, "{\"version\": 2, \"device\": \"%s\", \"rows\": %lld, \"entries\": [\n",
+                 tune_device_key(c).c_str(), (long long)m);
     for (size_t i = 0; i < found.size(); ++i) {
       const TuneEntry& t = found[i];
       std::fprintf(f, "{\"op\": \"%s\", \"mode\": %d, \"kp\": %d, \"hasy\": %d, \"nwg\": %d, \"ms\": %.6f}%s\n",
@@ -775,7 +792,19 @@ borth_status borth_autotune_load(borth_ctx c, const char* cache_path) {
   char line[512];
   int n = 0;
   std::vector<TuneEntry> got;
+  const std::string here = tune_device_key(c);
   while (std::fgets(line, sizeof(line), f)) {
+    if (const char* dp = std::strstr(line, "\"device\": \"")) {
+      dp += std::strlen("\"device\": \"");
+      const char* de = std::strchr(dp, '"');
+      const std::string made(dp, de ? (size_t)(de - dp) : std::strlen(dp));
+      if (made != here) {
+        std::fclose(f);
+        c->err = "autotune cache made on " + made + ", this device is " + here;
+        return BORTH_ERR_ARG;
+      }
+      continue;
+    }
     char op[16] = {0};
     TuneEntry t;
     t.rows = 0;

@@ -6,6 +6,8 @@ projection repeated, Sec. 4.2), results must not depend on the other blocks
 (a breakdown stays in its block), graph replays and in-place runs are
 bitwise identical to the eager run, and the autotune table round-trips.
 """
+import re
+
 import numpy as np
 import pytest
 
@@ -212,6 +214,12 @@ def test_autotune_roundtrip(tmp_path):
         bad.write_text("{}\n")
         with pytest.raises(borth.BorthError):
             ctx.autotune_load(bad)
+        # the cache names the device it was tuned on; another device's is refused
+        assert '"device": "gfx950' in txt
+        other = tmp_path / "other.json"
+        other.write_text(re.sub(r'"device": "[^"]*"', '"device": "gfx942:sramecc+:xnack-/304cu/hip1"', txt))
+        with pytest.raises(borth.BorthError, match="autotune cache made on"):
+            ctx.autotune_load(other)
         # the tuned shapes still give correct results (single and batched)
         X = synth.svd_matrix(30000, 32, 1e10, 77)
         Q, R, _, info = borth.orthonormalize(dev(X), gram="dd", ctx=ctx)
