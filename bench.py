@@ -123,11 +123,20 @@ def cpu_baseline_cholqr2(X, dd, target_s=10.0):
         t0 = time.perf_counter()
         oracle.cholqr_steps(X[:rows], dd_first=dd, passes=2)
         dt = time.perf_counter() - t0
+    # the whole block takes less than the target: repeat it (at most 10 runs)
+    reps = 1
+    if dt < target_s and rows == m:
+        reps = int(min(10, np.ceil(target_s / max(dt, 1e-3))))
+        if reps > 1:
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                oracle.cholqr_steps(X, dd_first=dd, passes=2)
+            dt = time.perf_counter() - t0
     k = X.shape[1]
-    return dict(value=32.0 * rows * k / dt / 1e9, unit="GB/s", cores=oracle.num_threads(),
+    return dict(value=32.0 * rows * k * reps / dt / 1e9, unit="GB/s", cores=oracle.num_threads(),
                 kind="oracle", cpu_model=cpu_model(),
                 sample=f"oracle step-by-step {'DD' if dd else 'binary64'} CholQR2 on the first "
-                       f"{rows} rows of the same X ({dt:.1f} s)")
+                       f"{rows} rows of the same X, {reps} run(s) ({dt:.1f} s)")
 
 
 def run_c3(args, torch, borth, synth):
