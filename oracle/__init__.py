@@ -225,10 +225,12 @@ def qr_q(X, Y=None, want_gram=False):
 
 
 def cholqr_steps(X, Y=None, *, dd_first=False, passes=2, project_each_pass=True,
-                 dd_corrected=False):
+                 dd_corrected=False, exact_gram=False):
     """O2: the paper's two-phase steps, first pass in DD if ``dd_first``
     (``dd_corrected``: with the projection coefficients D = 2C - S C, S = Y^T Y,
     which remove the part in span(Y) to second order in ||S - I||).
+    ``exact_gram`` (binary64 first pass only): that pass is given the
+    binary128 Gram matrix rounded once to binary64 instead of a binary64 sum.
 
     Returns dict(Q, R_hi, R_lo, C_hi, C_lo, info) with X = Y C + Q R;
     info = 100*(pass+1) + pivot on Cholesky breakdown, else 0."""
@@ -242,7 +244,8 @@ def cholqr_steps(X, Y=None, *, dd_first=False, passes=2, project_each_pass=True,
     chi = np.zeros((max(ky, 1), k))
     clo = np.zeros((max(ky, 1), k))
     info = _load().or_cholqr_steps(m, k, _p(X), k, ky, _p(Yc), max(ky, 1),
-                                   int(bool(dd_first)), int(bool(dd_corrected)), int(passes),
+                                   2 if (exact_gram and not dd_first) else int(bool(dd_first)),
+                                   int(bool(dd_corrected)), int(passes),
                                    int(bool(project_each_pass)), _p(Q), k, _p(rhi),
                                    _p(rlo), _p(chi), _p(clo))
     return dict(Q=Q, R_hi=rhi, R_lo=rlo, C_hi=chi[:ky], C_lo=clo[:ky], info=info)

@@ -602,7 +602,7 @@ static void trinv_dd(int k, const dd* r, dd* z) {
  * M = Xt^T Xt, M = R^T R, Z = R^{-1}, Q = Xt Z.  X may alias Q. */
 static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
                     const double* Y, int64_t ldy, double* Q, int64_t ldq,
-                    double* R, double* C) {
+                    double* R, double* C, int exact_gram) {
   double* xt = (double*)malloc(sizeof(double) * ((size_t)m * k + 1));
   if (ky > 0) gram_f64(m, ky, Y, ldy, k, X, ldx, C);
 #pragma omp parallel for schedule(static)
@@ -612,7 +612,14 @@ static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
       for (int l = 0; l < ky; ++l) v -= Y[r * ldy + l] * C[(size_t)l * k + j];
       xt[(size_t)r * k + j] = v;
     }
-  gram_f64(m, k, xt, k, k, xt, k, R);
+  /* exact_gram: M is the binary128 Gram matrix of Xt rounded once to
+   * binary64 -- the most accurate M a binary64 pass can be given, so the
+   * pass's orthogonality loss is then due to the Cholesky factor and the
+   * update alone. */
+  if (exact_gram)
+    or_gram_q(m, k, xt, k, k, xt, k, R, NULL);
+  else
+    gram_f64(m, k, xt, k, k, xt, k, R);
   const int info = chol_f64(k, R);
   if (info) { free(xt); return info; }
   double* z = (double*)malloc(sizeof(double) * (size_t)k * k + 8);
@@ -718,8 +725,9 @@ static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
 
 /* O2 driver: `passes` repetitions of (phase I if ky > 0 and (pass == 0 or
  * project_each_pass), then phase II).  The first pass runs in DD when dd_first
- * is set (with the corrected coefficients of pass_dd when dd_corrected is
- * set), later passes in binary64 -- the iterated two-phase scheme of
+ * is 1 (with the corrected coefficients of pass_dd when dd_corrected is
+ * set), in binary64 with the exactly rounded Gram matrix when dd_first is 2,
+ * later passes in binary64 -- the iterated two-phase scheme of
  * Sec. 4.2 cut to `passes` iterations (passes = 2 is CholQR2).
  * Outputs: Q (m x k), R = R_p ... R_1 (k x k, hi/lo), C = total projection
  * coefficients (ky x k, hi/lo) with X = Y C + Q R.  Returns 0, or
@@ -745,10 +753,10 @@ int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
   for (int p = 0; p < passes && !status; ++p) {
     const int kyp = (ky > 0 && (p == 0 || project_each_pass)) ? ky : 0;
     int info;
-    if (p == 0 && dd_first) {
+    if (p == 0 && dd_first == 1) {
       info = pass_dd(m, k, cur, k, kyp, Y, ldy, cur, k, rp, cp, dd_corrected);
     } else {
-      info = pass_f64(m, k, cur, k, kyp, Y, ldy, cur, k, rf, cf);
+      info = pass_f64(m, k, cur, k, kyp, Y, ldy, cur, k, rf, cf, p == 0 && dd_first == 2);
       for (size_t e = 0; e < n; ++e) rp[e] = dd_from(rf[e]);
       for (size_t e = 0; e < (size_t)kyp * k; ++e) cp[e] = dd_from(cf[e]);
     }

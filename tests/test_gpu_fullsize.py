@@ -1,0 +1,174 @@
+"""Parity at the workloads' full sizes, judged by the CPU oracle.
+
+The smaller parity tests cover every kernel element by element; these run
+the configurations the measurements are quoted on, at their real shapes and
+launch configurations, and judge the outputs with the oracle's binary128-
+accurate measures (orthogonality loss omega = ||Q^T Q - I||_F, residual
+rho = ||X - Y C - Q R||_F / ||X||_F, omega_Y = ||Y^T Q||_F) and, where the
+oracle can afford it, its exact Gram matrix:
+
+* 4,000,000 x 32 binary64, kappa in {1e8, 1e12, 1e15}: DD-Gram CholQR2
+  reaches omega, rho <= 1e-14; the binary64 CholQR2 comparator on the same
+  input breaks down or stays far from orthogonal at kappa >= 1e12; at
+  kappa = 1e12 the DD Gram sweep (many panels per workgroup) against the
+  exact Gram matrix;
+* 10,000,000 x {32, 64} binary64, kappa = 1e6: binary64 CholQR2;
+* 16,777,216 x 64 fp32, kappa = 1e6: the split-BF16 Gram (stage 1) against
+  the exact Gram of the widened X, then omega after one and two binary64
+  passes (stages 2 and 3) and rho;
+* the eight tallest blocks of the 256-block batch, at full height with their
+  16-column locked bases, in one batched call.
+
+Inputs are drawn on the device with the seeded generator of the same recipe
+(synth.*_device) and copied to the host for the oracle.  The oracle's
+measures run on the host's cores (a few seconds to a minute per case).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import U64, host, lib, note, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def _svd_x(m, k, kappa, seed, dtype=None):
+    key = (m, k, kappa, seed, dtype)
+    if key not in _cache:
+        _cache.clear()  # one large input at a time
+        torch = torch_gpu()
+        note(f"generate X {m} x {k} kappa={kappa:g} seed={seed}")
+        Xd = synth.svd_matrix_device(m, k, kappa, seed, dtype=dtype)
+        torch.cuda.synchronize()
+        _cache[key] = (Xd, host(Xd))
+    return _cache[key]
+
+
+def _metrics(Q, X, R, Y=None, C=None):
+    met = oracle.metrics(host(Q), X, host(R), Y, C)
+    note("  oracle metrics", {k: float(v) for k, v in met.items()})
+    return met
+
+
+@pytest.mark.parametrize("kappa,seed", [(1e8, 301), (1e12, 302), (1e15, 303)])
+def test_c3_dd_cholqr2_full(kappa, seed):
+    borth = lib()
+    torch = torch_gpu()
+    m, k = 4_000_000, 32
+    Xd, X = _svd_x(m, k, kappa, seed)
+    note(f"DD CholQR2 {m} x {k} kappa={kappa:g}")
+    Q, R, _, info = borth.orthonormalize(Xd, gram="dd", passes=2)
+    assert info.status == 0, info
+    met = _metrics(Q, X, R)
+    assert met["omega"] <= 1e-14 and met["rho"] <= 1e-14, met
+    del Q
+    note(f"binary64 CholQR2 {m} x {k} kappa={kappa:g}")
+    Qf, Rf, _, inf = borth.orthonormalize(Xd, gram="f64", passes=2, check=False)
+    torch.cuda.synchronize()
+    if inf.status == 0:
+        mf = _metrics(Qf, X, Rf)
+        if kappa >= 1e12:
+            assert mf["omega"] > 1e-14, mf
+    else:
+        note("  binary64 CholQR2 status", inf.status, "pass", inf.failed_pass,
+             "pivot", inf.failed_pivot)
+        assert kappa >= 1e8 and inf.status == 4
+    del Qf
+
+
+def test_c3_dd_gram_full_vs_exact():
+    """The DD Gram sweep of the 4,000,000 x 32 headline input in its timed
+    launch configuration (each workgroup folds many row panels) against the
+    binary128 Gram matrix: max |dG_ij| <= 2e-30 sqrt(G_ii G_jj), normwise
+    <= 1e-28."""
+    borth = lib()
+    Xd, X = _svd_x(4_000_000, 32, 1e12, 302)
+    note("DD Gram 4,000,000 x 32")
+    ghi, glo = borth.gram(Xd, prec="dd")
+    ex_hi, ex_lo = oracle.gram_q(X)
+    err = np.abs((host(ghi) - ex_hi) + (host(glo) - ex_lo))
+    d = np.sqrt(np.diag(ex_hi))
+    rel = err / np.outer(d, d)
+    note("  max", rel.max(), "normwise", np.linalg.norm(err) / np.linalg.norm(ex_hi))
+    assert rel.max() <= 2e-30
+    assert np.linalg.norm(err) <= 1e-28 * np.linalg.norm(ex_hi)
+
+
+@pytest.mark.parametrize("k", [32, 64])
+def test_c2_f64_cholqr2_full(k):
+    borth = lib()
+    m = 10_000_000
+    Xd, X = _svd_x(m, k, 1e6, 200 + k)
+    note(f"binary64 CholQR2 {m} x {k}")
+    Q, R, _, info = borth.orthonormalize(Xd, gram="f64", passes=2)
+    assert info.status == 0, info
+    met = _metrics(Q, X, R)
+    assert met["omega"] <= 1e-14 and met["rho"] <= 1e-14, met
+
+
+def _c4():
+    import torch
+    return _svd_x(16_777_216, 64, 1e6, 401, dtype=torch.float32)
+
+
+def test_c4_split_gram_full():
+    """Stage 1: the split-BF16 Gram matrix of the fp32 X against the exact
+    Gram matrix of its binary64 widening (oracle Dot2 sums, error ~u^2):
+    elementwise within 4 * 2^-16 (|X|^T |X|)_ij, as the two-term split
+    leaves the lo*lo term and the remainder below bf16."""
+    borth = lib()
+    Xd, X32 = _c4()
+    X = X32.astype(np.float64)
+    note("split Gram 16,777,216 x 64")
+    ghi, _ = borth.gram(Xd, prec="split")
+    ex_hi, ex_lo = oracle.gram_dot2(X)
+    g = host(ghi)
+    absg = np.abs(X).T @ np.abs(X)
+    rel = np.abs((g - ex_hi) - ex_lo) / absg
+    note("  max elementwise", rel.max(), "normwise",
+         np.linalg.norm((g - ex_hi) - ex_lo) / np.linalg.norm(ex_hi))
+    assert rel.max() <= 4 * 2.0 ** -16
+
+
+@pytest.mark.parametrize("passes", [2, 3])
+def test_c4_split_refinement_full(passes):
+    """Stages 2 and 3: after the shifted split pass, one binary64 pass leaves
+    omega_1 ~ kappa(Q_1)^2 u (kappa(Q_1) about sqrt(shift) / sigma_min:
+    gated at 1e-6), a second one omega_2 <= 1e-14; rho <= 1e-14 for both."""
+    borth = lib()
+    Xd, X32 = _c4()
+    note(f"split + {passes - 1} binary64 pass(es), 16,777,216 x 64")
+    Q, R, _, info = borth.orthonormalize(Xd, gram="split", passes=passes)
+    assert info.status == 0, info
+    met = _metrics(Q, X32.astype(np.float64), R)
+    assert met["rho"] <= 1e-14, met
+    assert met["omega"] <= (1e-6 if passes == 2 else 1e-14), met
+
+
+def test_c5_tallest_blocks_full():
+    """The eight tallest blocks of the 256-block batch (rows up to 1e6,
+    widths from {8, 16, 32, 64}, kappa log-uniform in [1e3, 1e10]) with
+    their 16-column locked bases, one batched DD CholQR2 call (P,C,P,C):
+    per block omega, rho and omega_Y <= 1e-14."""
+    borth = lib()
+    torch = torch_gpu()
+    table = synth.batch_table(256, seed=5000)
+    tall = sorted(table, key=lambda t: -t["m"])[:8]
+    ky = 16
+    blocks, hostb = [], []
+    for t in tall:
+        note(f"block m={t['m']} k={t['k']} kappa={t['kappa']:.3g} seed={t['seed']}")
+        X = synth.svd_matrix_device(t["m"], t["k"], t["kappa"], t["seed"])
+        Y = synth.locked_basis_device(t["m"], ky, t["seed"] + 100_000)
+        blocks.append({"X": X, "Y": Y})
+    torch.cuda.synchronize()
+    note("batched DD CholQR2 of 8 full-height blocks")
+    outs, infos = borth.batch_orthonormalize(blocks, gram="dd", passes=2)
+    for t, b, (Q, R, C), inf in zip(tall, blocks, outs, infos):
+        assert inf.status == 0, (t, inf)
+        met = oracle.metrics(host(Q), host(b["X"]), host(R), host(b["Y"]), host(C))
+        note("  block", t["m"], t["k"], {k: float(v) for k, v in met.items()})
+        assert met["omega"] <= 1e-14 and met["rho"] <= 1e-14 and met["omega_y"] <= 1e-14, (t, met)

@@ -408,26 +408,39 @@ def _check_qr(X, Q, R, Y=None, C=None, omega=1e-14, rho=1e-14):
 
 
 def test_cholqr_plain_c1_shape():
-    """Plain CholQR at the 20000 x 8, kappa = 1e4 workload: orthogonality
-    loss follows c kappa^2 u (Stathopoulos and Wu), rho ~ u.  The constant c
-    depends on the summation order of the Gram matrix, so the GPU and the
-    oracle's binary64 steps are both checked against the law (level band and
-    kappa^2 slope between kappa = 1e3 and 1e4), not against each other."""
+    """Plain binary64 CholQR at the 20000 x 8 workload (kappa = 1e4, and
+    1e3 for the slope), against the oracle.  One pass loses about
+    c kappa^2 times the relative rounding error of the Gram matrix plus that
+    of the Cholesky factor (the published c kappa^2 u law).  The oracle
+    brackets the loss by two binary64 passes that differ only in the Gram
+    matrix: summed in binary64 over row blocks in order, and the binary128
+    Gram matrix rounded once.  The GPU's Gram matrix (short chains combined
+    by fixed trees) must be at least as accurate as the oracle's binary64
+    sum, and its loss must lie in that bracket widened by 4 on each side."""
     borth = lib()
-    om = {}
-    for kappa in (1e3, 1e4):
-        X = synth.svd_matrix(20000, 8, kappa, 101)
-        Q, R, _, info = borth.orthonormalize(dev(X), gram="f64", passes=1)
-        assert info.status == 0
-        met = _check_qr(X, host(Q), host(R), omega=1.0)
-        o2 = oracle.cholqr_steps(X, dd_first=False, passes=1)
-        m2 = oracle.metrics(o2["Q"], X, o2["R_hi"])
-        law = kappa ** 2 * U64
-        note(" plain CholQR kappa", kappa, "gpu", met["omega"], "oracle", m2["omega"], "k^2u", law)
-        for w in (met["omega"], m2["omega"]):
-            assert 1e-2 * law <= w <= 1e2 * law
-        om[kappa] = met["omega"]
-    assert 10 <= om[1e4] / om[1e3] <= 1000  # kappa^2 predicts 100
+    for seed in (101, 102, 103):
+        om = {}
+        for kappa in (1e3, 1e4):
+            X = synth.svd_matrix(20000, 8, kappa, seed)
+            note("plain CholQR", seed, kappa)
+            Q, R, _, info = borth.orthonormalize(dev(X), gram="f64", passes=1)
+            assert info.status == 0
+            met = _check_qr(X, host(Q), host(R), omega=1.0)
+            o_f = oracle.cholqr_steps(X, passes=1)
+            o_e = oracle.cholqr_steps(X, passes=1, exact_gram=True)
+            om_f = oracle.metrics(o_f["Q"], X, o_f["R_hi"])["omega"]
+            om_e = oracle.metrics(o_e["Q"], X, o_e["R_hi"])["omega"]
+            ghi, _ = borth.gram(dev(X), prec="f64")
+            ex_hi, ex_lo = oracle.gram_q(X)
+            nrm = np.linalg.norm(ex_hi)
+            e_gpu = np.linalg.norm((host(ghi) - ex_hi) - ex_lo) / nrm
+            e_o2 = np.linalg.norm((oracle.gram_f64(X) - ex_hi) - ex_lo) / nrm
+            note("  omega gpu", met["omega"], "oracle binary64 Gram", om_f,
+                 "oracle rounded exact Gram", om_e, "Gram error gpu", e_gpu, "oracle", e_o2)
+            assert e_gpu <= max(2.0 * e_o2, U64)
+            assert om_e / 4 <= met["omega"] <= 4 * om_f
+            om[kappa] = met["omega"]
+        assert 10 <= om[1e4] / om[1e3] <= 1000  # kappa^2 predicts 100
     X = synth.svd_matrix(20000, 8, 1e4, 101)
     Q, R, _, info = borth.orthonormalize(dev(X), gram="f64", passes=1)
     o1 = oracle.qr_q(X)

@@ -372,6 +372,47 @@ def test_cholqr2_reaches_unit_roundoff():
         assert met["omega"] <= 1e-14 and met["rho"] <= 1e-14, (kappa, dd, met)
 
 
+def test_exact_gram_pass_first_row_exact_rational():
+    """The binary64 pass given the exactly rounded Gram matrix: its first
+    Cholesky row is R_00 = sqrt(fl(G_00)) and R_0j = fl(G_0j) / R_00, each
+    correctly rounded, with fl(G) the exact rational Gram rounded once."""
+    rng = np.random.default_rng(44)
+    X = _rand_exp_matrix(rng, 300, 4, spread=6)
+    s = oracle.cholqr_steps(X, passes=1, exact_gram=True)
+    assert s["info"] == 0
+    G = gram_exact(X)
+    g = np.array([[float(G[i][j]) for j in range(4)] for i in range(4)])  # round once
+    r00 = np.sqrt(g[0, 0])
+    want = np.array([r00] + [g[0, j] / r00 for j in range(1, 4)])
+    assert np.array_equal(s["R_hi"][0], want)
+    # planted mistake: one ulp off in any entry of the first row is caught
+    bad = want.copy()
+    bad[2] = np.nextafter(bad[2], np.inf)
+    assert not np.array_equal(bad, want)
+
+
+def test_exact_gram_pass_hadamard_and_law():
+    """With the exactly rounded Gram matrix the binary64 pass is exact on the
+    scaled Hadamard family, and its loss still follows c kappa^2 u but sits
+    below the binary64-summed pass's (the Gram matrix's rounding error is
+    one of the two terms of that loss; the Cholesky factor's is the other)."""
+    exps = [0, -3, 7, -20, 11, -35]
+    X = synth.hadamard_scaled(5, exps)
+    s = oracle.cholqr_steps(X, passes=1, exact_gram=True)
+    assert np.array_equal(s["Q"], synth.hadamard_columns(5, range(1, 7)))
+    assert np.array_equal(s["R_hi"], np.diag(np.ldexp(1.0, exps)))
+    ratios = []
+    for seed in (101, 102, 103):
+        X = synth.svd_matrix(20000, 8, 1e4, seed)
+        e = oracle.cholqr_steps(X, passes=1, exact_gram=True)
+        f = oracle.cholqr_steps(X, passes=1)
+        oe = oracle.metrics(e["Q"], X, e["R_hi"])["omega"]
+        of = oracle.metrics(f["Q"], X, f["R_hi"])["omega"]
+        assert 1e-4 * 1e8 * U64 <= oe <= 1e2 * 1e8 * U64
+        ratios.append(of / oe)
+    assert np.median(ratios) >= 2.0, ratios
+
+
 def test_dd_first_pass_law():
     """A DD pass loses ~ c kappa^2 u_dd (u_dd ~ 2^-106) on top of the binary64
     output rounding floor."""
