@@ -206,6 +206,27 @@ borth_status borth_orthonormalize(borth_ctx ctx, int64_t m, int k, borth_dtype d
                                   int ky, double* Q, int64_t ldq, double* R, double* C,
                                   const borth_opts* opts, borth_info* info);
 
+/* borth_orthonormalize without allocation, for callers that cannot allocate
+ * device memory in the call: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Arguments, results and status
+ * as borth_orthonormalize, except that opts->flags must not hold
+ * BORTH_FLAG_GRAPH or BORTH_FLAG_AUTO_ESCALATE (BORTH_ERR_ARG).  Every
+ * workspace of the call (status words, k x k factors, per-workgroup Gram
+ * partials) lives in one file-scope device array of the library, 32 MiB per
+ * device, held from the first borth_create on that device until the process
+ * ends; a shape whose Gram partials would not fit (only possible with
+ * autotuned workgroup counts) is refused with BORTH_ERR_ARG before anything
+ * is enqueued.  The call allocates nothing (no hipMalloc, hipFree, events or
+ * graphs); the caller passes X, Y, Q, R, C.  All calls on one device share
+ * that array and keep the last call's contents: calls that overlap on one
+ * GPU (other streams, other contexts, other host threads) race.  The status
+ * of an asynchronous call is read only through info or BORTH_FLAG_SYNC
+ * (borth_get_info reports the context's own calls). */
+borth_status borth_orthonormalize_noalloc(borth_ctx ctx, int64_t m, int k, borth_dtype dt,
+                                          const void* X, int64_t ldx, const double* Y,
+                                          int64_t ldy, int ky, double* Q, int64_t ldq, double* R,
+                                          double* C, const borth_opts* opts, borth_info* info);
+
 /* Outcome of the iterated scheme (borth_orthonormalize_iter). */
 typedef struct {
   int converged;  /* 1 if the stop test held after passes_run passes */

@@ -19,7 +19,8 @@ from . import _lib
 
 __all__ = [
     "BorthError", "Breakdown", "Context", "Info", "default_context", "gram", "factor",
-    "update", "orthonormalize", "orthonormalize_dd", "orthonormalize_iter",
+    "update", "orthonormalize", "orthonormalize_noalloc", "orthonormalize_dd",
+    "orthonormalize_iter",
     "batch_orthonormalize", "GRAM", "FACT",
     "SCHED",
 ]
@@ -303,6 +304,39 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
                                       _ld(Y) if ky else 0, ky, _ptr(Q), _ld(Q), _ptr(R),
                                       _ptr(C) if ky else ctypes.c_void_p(0), ctypes.byref(o),
                                       ctypes.byref(inf) if sync else None)
+    info = _info(inf) if sync else None
+    if check or st not in (BREAKDOWN, NONFINITE):
+        ctx.check(st)
+    return Q, R, (C if ky else None), info
+
+
+def orthonormalize_noalloc(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
+                           shift=-1.0, project_once=False, out=None, R=None, C=None, sync=True,
+                           check=True, ctx=None):
+    """borth_orthonormalize_noalloc: the same result as ``orthonormalize``
+    with every workspace of the call in the library's per-device scratch
+    array (the library allocates nothing in the call).  Calls that overlap
+    on one GPU share that array and race.  Q, R and C must be given or are
+    allocated here by torch, before the library is called."""
+    torch = _torch()
+    ctx = ctx or default_context(X.device.index)
+    _mat(X, "X", ctx, f32=True)
+    m, k = X.shape
+    ky = 0 if Y is None else Y.shape[1]
+    if ky:
+        _mat(Y, "Y", ctx, rows=m)
+    dev = X.device
+    Q = out if out is not None else torch.empty((m, k), dtype=torch.float64, device=dev)
+    R = R if R is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
+    if ky and C is None:
+        C = torch.empty((ky, k), dtype=torch.float64, device=dev)
+    _outs(ctx, Q, R, C, m, k, ky)
+    o = _opts(gram, fact, passes, sched, shift, FLAG_PROJECT_ONCE if project_once else 0)
+    inf = _lib.borth_info()
+    st = ctx.lib.borth_orthonormalize_noalloc(
+        ctx.h, m, k, _dt(X), _ptr(X), _ld(X), _ptr(Y), _ld(Y) if ky else 0, ky, _ptr(Q), _ld(Q),
+        _ptr(R), _ptr(C) if ky else ctypes.c_void_p(0), ctypes.byref(o),
+        ctypes.byref(inf) if sync else None)
     info = _info(inf) if sync else None
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)

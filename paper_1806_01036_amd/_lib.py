@@ -57,6 +57,9 @@ EXPORTS = {
     "borth_orthonormalize": ([_vp, _i64, _int, _int, _vp, _i64, _vp, _i64, _int, _vp, _i64,
                               _vp, _vp, ctypes.POINTER(borth_opts),
                               ctypes.POINTER(borth_info)], _int),
+    "borth_orthonormalize_noalloc": ([_vp, _i64, _int, _int, _vp, _i64, _vp, _i64, _int, _vp,
+                                      _i64, _vp, _vp, ctypes.POINTER(borth_opts),
+                                      ctypes.POINTER(borth_info)], _int),
     "borth_orthonormalize_dd": ([_vp, _i64, _int, _vp, _vp, _i64, _vp, _i64, _int, _vp, _vp, _i64,
                                  _vp, _vp, ctypes.POINTER(borth_opts), ctypes.POINTER(borth_info)],
                                 _int),

@@ -408,6 +408,9 @@ borth_status borth_create(borth_ctx* out, int device, void* stream) {
     borth_destroy(c);
     return BORTH_ERR_NOMEM;
   }
+  // device address of this device's scratch array (allocation-free entry point)
+  const hipError_t es = noalloc_setup(device);
+  if (es != hipSuccess) c->noalloc_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(es);
   *out = c;
   return BORTH_OK;
 }
@@ -564,13 +567,14 @@ borth_status borth_update(borth_ctx c, int64_t m, int k, borth_dtype dt, const v
   return BORTH_OK;
 }
 
-borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
-                                  int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
-                                  int64_t ldq, double* R, double* C, const borth_opts* opts,
-                                  borth_info* info) {
-  if (!c) return BORTH_ERR_ARG;
-  borth_opts o;
-  if (opts) o = *opts; else borth_default_opts(&o);
+}  // extern "C"
+
+namespace {
+// Argument checks shared by borth_orthonormalize and its allocation-free
+// variant (nothing is enqueued before they pass).
+borth_status check_ortho_args(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
+                              int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
+                              int64_t ldq, const borth_opts& o) {
   if (k < 1 || k > 64 || ky < 0 || ky > 64 || m < (int64_t)k + ky) return fail_arg(c, "shape");
   if (!X || !Q || ldx < k || ldq < k) return fail_arg(c, "X/Q");
   if (ky > 0 && (!Y || ldy < ky)) return fail_arg(c, "Y");
@@ -592,6 +596,24 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
   const bool escalate = (o.flags & BORTH_FLAG_AUTO_ESCALATE) != 0;
   if (escalate && (dt != BORTH_F64 || (const void*)Q == X))
     return fail_arg(c, "automatic escalation needs binary64 X and Q distinct from X");
+  return BORTH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt, const void* X,
+                                  int64_t ldx, const double* Y, int64_t ldy, int ky, double* Q,
+                                  int64_t ldq, double* R, double* C, const borth_opts* opts,
+                                  borth_info* info) {
+  if (!c) return BORTH_ERR_ARG;
+  borth_opts o;
+  if (opts) o = *opts; else borth_default_opts(&o);
+  {
+    const borth_status ra = check_ortho_args(c, m, k, dt, X, ldx, Y, ldy, ky, Q, ldq, o);
+    if (ra) return ra;
+  }
+  const bool escalate = (o.flags & BORTH_FLAG_AUTO_ESCALATE) != 0;
   hipSetDevice(c->device);
   borth_status r = ortho_enqueue(c, m, k, dt, X, ldx, Y, ldy, ky, Q, ldq, R, C, o);
   if (r) return r;
@@ -630,6 +652,114 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
     std::fprintf(stderr, "\n");
   }
   return sync ? st : BORTH_OK;
+}
+
+namespace {
+// Upper bound (doubles) of the Gram partials one borth_orthonormalize call
+// writes, from the workgroup counts its sweeps choose (autotuned or default;
+// the DD tile sweep without a tuned count fits its grid to the space given).
+int64_t noalloc_partial_need(borth_ctx c, int ky, int k, const borth_opts& o) {
+  const int kp = pow2pad(k);
+  const bool hasy = ky > 0;
+  const bool dd = o.gram == BORTH_GRAM_DD;
+  auto wg = [](const TuneGram& t) { return (int64_t)(t.nwg > 0 ? t.nwg : 1024); };
+  int64_t need = 0;
+  if (o.gram == BORTH_GRAM_SPLIT_BF16) {
+    need = wg(lookup(c->tune_gram, 2, kp, 0)) * make_layout(0, k, 4).E;
+  } else {
+    const GramLayout L1 = make_layout(ky, k, 4);
+    const TuneGram t = lookup(c->tune_gram, dd ? 1 : 0, kp, hasy);
+    const bool rows = !dd && L1.ty == 0 && L1.Wp <= 8;
+    if (!rows && gram_kind(L1, dd ? 1 : 0) == 1 && t.nwg <= 0)
+      need = (int64_t)L1.E * (dd ? 2 : 1);
+    else
+      need = wg(t) * L1.E * (dd ? 2 : 1);
+  }
+  if (o.passes > 1) {
+    const bool later_proj = hasy && !(o.flags & BORTH_FLAG_PROJECT_ONCE);
+    const GramLayout G = update_gram_layout(ky, k, kp, later_proj);
+    const int64_t u = wg(lookup(c->tune_upd, 1, kp, hasy)) * G.E;
+    if (u > need) need = u;
+  }
+  return need;
+}
+}  // namespace
+
+extern "C" borth_status borth_orthonormalize_noalloc(borth_ctx c, int64_t m, int k,
+                                                     borth_dtype dt, const void* X, int64_t ldx,
+                                                     const double* Y, int64_t ldy, int ky,
+                                                     double* Q, int64_t ldq, double* R, double* C,
+                                                     const borth_opts* opts, borth_info* info) {
+  if (!c) return BORTH_ERR_ARG;
+  borth_opts o;
+  if (opts) o = *opts; else borth_default_opts(&o);
+  {
+    const borth_status ra = check_ortho_args(c, m, k, dt, X, ldx, Y, ldy, ky, Q, ldq, o);
+    if (ra) return ra;
+  }
+  if (o.flags & (BORTH_FLAG_GRAPH | BORTH_FLAG_AUTO_ESCALATE))
+    return fail_arg(c, "the allocation-free call takes neither BORTH_FLAG_GRAPH nor "
+                       "BORTH_FLAG_AUTO_ESCALATE");
+  double* sp = noalloc_scratch(c->device);
+  if (!sp) {
+    c->err = "device scratch address unavailable: " + c->noalloc_err;
+    return BORTH_ERR_HIP;
+  }
+  // scratch: [status words (64 ints)][k x k workspace][Gram partials]
+  const WsLayout W = ws_layout();
+  const int64_t ws_off = 32;
+  const int64_t part_off = ws_off + ((W.total + 31) / 32) * 32;
+  const int64_t part_cap = kNoallocScratchDoubles - part_off;
+  const int64_t need = noalloc_partial_need(c, ky, k, o);
+  if (need > part_cap) {
+    c->err = "allocation-free call: this shape's Gram partials need " + std::to_string(need) +
+             " doubles, the device scratch holds " + std::to_string(part_cap);
+    return BORTH_ERR_ARG;
+  }
+  hipSetDevice(c->device);
+  // the regular launch sequence with the context's buffers replaced by the
+  // scratch for the duration of the enqueue (no profiling events: creating
+  // them could allocate)
+  double* const save_part = c->part;
+  const int64_t save_part_cap = c->part_cap;
+  double* const save_ws = c->ws;
+  const int64_t save_ws_cap = c->ws_cap;
+  int* const save_status = c->status;
+  const int save_prof = c->prof;
+  c->part = sp + part_off;
+  c->part_cap = part_cap;
+  c->ws = sp + ws_off;
+  c->ws_cap = W.total;
+  c->status = (int*)sp;
+  c->prof = 0;
+  c->cur = c->stream;
+  const OrthoCall a{m, k, ky, dt, X, ldx, Y, ldy, Q, ldq, R, C, o, nullptr, nullptr};
+  const borth_status r = enqueue_ortho(c, a);
+  c->part = save_part;
+  c->part_cap = save_part_cap;
+  c->ws = save_ws;
+  c->ws_cap = save_ws_cap;
+  c->status = save_status;
+  c->prof = save_prof;
+  if (r) return r;
+  const bool sync = info || (o.flags & BORTH_FLAG_SYNC);
+  if (!sync) return BORTH_OK;
+  int hs[4] = {0, 0, 0, 0};
+  double est[3] = {0.0, 0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(hs, sp, sizeof(hs), hipMemcpyDeviceToHost, c->stream), "status readback");
+  HIPCHK(c, hipMemcpyAsync(est, sp + ws_off + W.cu, sizeof(est), hipMemcpyDeviceToHost, c->stream),
+         "estimates readback");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (info) {
+    info->status = hs[0];
+    info->failed_pass = hs[1];
+    info->failed_pivot = hs[2];
+    info->passes_run = hs[3];
+    info->orth_est = est[1];
+    info->kappa_est = est[2];
+    info->escalation = 0;
+  }
+  return (borth_status)hs[0];
 }
 
 namespace {

@@ -10,6 +10,7 @@
 
 #include "../../include/borth.h"
 #include "internal.hpp"
+#include "noalloc.hpp"
 
 struct GraphKey {
   std::vector<int64_t> v;
@@ -56,6 +57,7 @@ struct borth_ctx_s {
   bool capturing = false;
   bool last_est = false;             // the last call left estimates in the workspace
   hipStream_t cur = nullptr;         // stream the current enqueue targets
+  std::string noalloc_err;           // set if the scratch address could not be taken
 };
 
 inline borth_status fail_hip(borth_ctx c, hipError_t e, const char* where) {
