@@ -175,7 +175,12 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
   for (int b = 0; b < nb; ++b) {
     L1[b] = make_layout(B[b].ky, B[b].k, 4);
     const int kind = gram_kind(L1[b], gmode);
-    const int arg = kind == 0 ? (L1[b].Wp + 15) / 16 : gram_tiles_threads(L1[b]);
+    int arg = kind == 0 ? (L1[b].Wp + 15) / 16 : gram_tiles_threads(L1[b]);
+    if (kind == 1) {
+      Src s{B[b].Y, B[b].ldy, B[b].X, B[b].ldx, 0, B[b].m};
+      s.dot2 = (o.flags & BORTH_FLAG_DD_DOT2) ? 1 : 0;
+      if (gram_dma_ok(s, L1[b], gmode, arg)) arg = kGramDmaArg;
+    }
     ggroups[{kind, arg}].push_back(b);
   }
   struct PendingGram {
@@ -185,12 +190,13 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
   std::vector<PendingGram> pend;
   for (auto& kv : ggroups) {
     const int kind = kv.first.first, arg = kv.first.second;
-    const int NT = kind == 0 ? 256 : arg;
+    const int NT = kind == 0 || arg == kGramDmaArg ? 256 : arg;
     std::vector<int64_t> rows;
     std::vector<int> cap;
     int kpmax = 4, hasy = 0;
     for (int b : kv.second) {
       Src s{B[b].Y, B[b].ldy, B[b].X, B[b].ldx, 0, B[b].m};
+      s.dot2 = (o.flags & BORTH_FLAG_DD_DOT2) ? 1 : 0;
       rows.push_back(B[b].m);
       cap.push_back(gram_max_wg(s, L1[b], gmode, NT));
       kpmax = std::max(kpmax, W[b].kp);
@@ -276,7 +282,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
   // ---- Gram steps
   for (auto& g : pend) {
     const int kind = g.key.first, arg = g.key.second;
-    const int NT = kind == 0 ? 256 : arg;
+    const int NT = kind == 0 || arg == kGramDmaArg ? 256 : arg;
     std::vector<GramSeg> segs;
     std::vector<int> map;
     size_t shmem = 0;

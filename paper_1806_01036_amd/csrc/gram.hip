@@ -374,6 +374,234 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
 }
 
 // ---------------------------------------------------------------------------
+// DD Gram with biased accumulation, row panels staged by direct
+// global-to-LDS transfers (gfx950 global_load_lds_dwordx4).
+//
+// The same arithmetic as the biased path of gram_tiles_kernel (each thread
+// owns a 4x4 tile and a row phase; each panel's sums run on a power-of-two
+// bias from the panel's column maxima and are folded into a DD total at the
+// panel's end), with the panel brought in differently: every 16-byte chunk
+// of the panel's rows is copied from HBM straight into LDS by the memory
+// unit, so no registers hold the panel on its way and no instructions store
+// it.  That frees the registers the register-staged kernel spent on its
+// prefetch and lets a panel be two to three times taller, so the fold, the
+// bias set-up and the barriers are paid over more rows.  The panel's load
+// latency is covered by the other workgroup resident on the compute unit.
+//
+// Per panel: transfer (each wave issues its share of the chunks, waits for
+// them) -> barrier -> rows past m zeroed, column maxima into LDS -> barrier
+// -> tile sums on the bias, fold -> barrier.  The LDS row stride is Wp + 2
+// doubles (Wp / 2 + 1 chunks); the chunk after a row's Wp columns, and the
+// chunks of the padding columns between Y and X or after X, are filled with
+// a copy of a valid chunk of that row: they are read only into products that
+// land in padded Gram entries, which the reduction drops.
+//
+// Needs 16-byte aligned rows: X and Y 16-byte aligned, even ldx, ldy, ky and
+// k, binary64, no weights (host check gram_dma_ok).  HASY: the sweep has Y
+// columns (ky > 0), so a chunk's source may be either matrix.
+template <bool BATCH, bool HASY>
+__global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
+                                                             const GramSeg* __restrict__ tab,
+                                                             const int* __restrict__ wg2seg) {
+  extern __shared__ double lds[];
+  const GramSeg g = BATCH ? tab[wg2seg[blockIdx.x]] : one;
+  const Src& s = g.s;
+  if (stopped(s.stop, s.pass)) return;
+  const GramLayout& L = g.L;
+  const int P = g.P, S = g.S;
+  const int np = P / S;  // rows per thread and panel (P = S np, np even)
+  const int64_t npanels = g.nunits;
+  const int wg = (int)blockIdx.x - g.wg0, nwg = g.nwg;
+  const int Wp = L.Wp, stride = Wp + 2, cpr = stride / 2;
+  const int nchunks = P * cpr;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nt = L.ntiles;
+  const bool active = tid < nt * S;
+  const int t = active ? tid % nt : 0;
+  const int phase = active ? tid / nt : 0;
+  int ti, tj;
+  decode_tile(t, L, ti, tj);
+  int cb = 0;
+  while ((1 << cb) < 2 * np + 1) ++cb;
+  unsigned long long* cmx = (unsigned long long*)(lds + P * stride);
+  for (int x = tid; x < Wp; x += 256) cmx[x] = 0ull;
+
+  double acs[16], acc[16], th[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    acs[e] = 0.0;
+    acc[e] = 0.0;
+    th[e] = 0.0;
+  }
+  const double BORTH_GLOBAL* Xg = gmem((const double*)s.X);
+  const double BORTH_GLOBAL* Yg = gmem(s.Y);
+  // maxima pass: thread -> (pair of data columns, row group), 16-byte reads
+  const int mcp = Wp / 2;  // column pairs of a row
+  const int mcol = tid % mcp, mgrp = tid / mcp, ngrp = 256 / mcp;
+  // Transfer plan: chunk q = 256 i + tid of a panel lands at byte 16 q of
+  // the panel in LDS (the LDS base of one instruction is uniform per wave).
+  // Its source, relative to the panel's first row, is the same for every
+  // full panel: off[i] doubles into X, or into Y where bit i of ymask is set.
+  // Instructions i < nfull cover 256 chunks; one more covers the rest.
+  constexpr int kMaxChunks = 16;  // P cpr <= 4096 (64 KiB of LDS)
+  const int nfull = nchunks / 256, nci = (nchunks + 255) / 256;
+  int off[kMaxChunks];
+  unsigned ymask = 0u;
+  auto chunk_src = [&](int q, int& r, int& o) -> bool {
+    r = q / cpr;
+    const int col = 2 * (q - r * cpr);
+    if (HASY && col + 1 < L.ky) {
+      o = col;
+      return true;
+    }
+    o = (col >= L.kyp && col - L.kyp + 1 < L.k) ? col - L.kyp : 0;
+    return false;
+  };
+#pragma unroll
+  for (int i = 0; i < kMaxChunks; ++i) {
+    off[i] = 0;
+    const int q = 256 * i + tid;
+    if (i < nci && q < nchunks) {
+      int r, o;
+      const bool y = chunk_src(q, r, o);
+      off[i] = (int)((y ? (int64_t)r * s.ldy : (int64_t)r * s.ldx) + o);
+      if (y) ymask |= 1u << i;
+    }
+  }
+
+  for (int64_t pnl = wg; pnl < npanels; pnl += nwg) {
+    const int64_t row0 = pnl * P;
+    const int64_t rem = s.m - row0;
+    const int rows = rem < P ? (int)rem : P;
+    if (rows == P) {
+      const double BORTH_GLOBAL* xb = Xg + row0 * s.ldx;
+      const double BORTH_GLOBAL* yb = HASY ? Yg + row0 * s.ldy : xb;
+#pragma unroll
+      for (int i = 0; i < kMaxChunks; ++i) {
+        if (i < nfull) {
+          const double BORTH_GLOBAL* src = (HASY && ((ymask >> i) & 1u)) ? yb + off[i] : xb + off[i];
+          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src, (void __attribute__((address_space(3)))*)(lds + 2 * (256 * i + 64 * wave)), 16, 0, 0);
+        }
+      }
+      if (nfull < nci && 256 * nfull + tid < nchunks) {
+#pragma unroll
+        for (int i = 0; i < kMaxChunks; ++i)
+          if (i == nfull) {
+            const double BORTH_GLOBAL* src = (HASY && ((ymask >> i) & 1u)) ? yb + off[i] : xb + off[i];
+            __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src, (void __attribute__((address_space(3)))*)(lds + 2 * (256 * i + 64 * wave)), 16, 0, 0);
+          }
+      }
+    } else {
+      // last panel: source rows clamped to m - 1 (zeroed below)
+      for (int q0 = 0; q0 < nchunks; q0 += 256) {
+        const int q = q0 + tid;
+        if (q < nchunks) {
+          int r, o;
+          const bool y = chunk_src(q, r, o);
+          const int64_t row = row0 + (r < rows ? r : rows - 1);
+          const double BORTH_GLOBAL* src = y ? Yg + row * s.ldy + o : Xg + row * s.ldx + o;
+          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src, (void __attribute__((address_space(3)))*)(lds + 2 * (q0 + 64 * wave)), 16, 0, 0);
+        }
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (rows < P) {
+      // last panel: rows past m (copies of the last row) become zeros
+      for (int x = tid; x < (P - rows) * stride; x += 256) lds[rows * stride + x] = 0.0;
+    }
+    if (mgrp < ngrp) {
+      double m0 = 0.0, m1 = 0.0;
+#pragma unroll 4
+      for (int r = mgrp; r < rows; r += ngrp) {
+        const double2 v = *(const double2*)(lds + r * stride + 2 * mcol);
+        m0 = fmax(m0, fabs(v.x));
+        m1 = fmax(m1, fabs(v.y));
+      }
+      atomicMax(&cmx[2 * mcol], (unsigned long long)__double_as_longlong(m0));
+      atomicMax(&cmx[2 * mcol + 1], (unsigned long long)__double_as_longlong(m1));
+    }
+    __syncthreads();
+    if (active) {
+      int ea[4], eb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ea[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[4 * ti + i]));
+        eb[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[4 * tj + i])) + cb;
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acs[e] = __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
+      // two rows per trip: the first row's sums go to sn, the second's back
+      // into acs, so no copies are needed
+      const double* rp = lds + phase * stride;
+      const int rstep = S * stride;
+      for (int i = 0; i < np; i += 2, rp += 2 * rstep) {
+        double a0[4], b0[4], a1[4], b1[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          a0[x] = rp[4 * ti + x];
+          b0[x] = rp[4 * tj + x];
+          a1[x] = rp[rstep + 4 * ti + x];
+          b1[x] = rp[rstep + 4 * tj + x];
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const double sn = __builtin_fma(a0[e / 4], b0[e % 4], acs[e]);
+          const double d0 = sn - acs[e];  // exact
+          acc[e] = acc[e] + __builtin_fma(a0[e / 4], b0[e % 4], -d0);
+          const double s2 = __builtin_fma(a1[e / 4], b1[e % 4], sn);
+          const double d1 = s2 - sn;  // exact
+          acc[e] = acc[e] + __builtin_fma(a1[e / 4], b1[e % 4], -d1);
+          acs[e] = s2;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(ea[i]), "+v"(eb[i]));
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double h = acs[e] - __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
+        const dd_t tt = two_sum(th[e], h);
+        const dd_t n = fast_two_sum(tt.hi, acc[e] + tt.lo);
+        th[e] = n.hi;
+        acc[e] = n.lo;
+      }
+    }
+    __syncthreads();
+    for (int x = tid; x < Wp; x += 256) cmx[x] = 0ull;
+  }
+
+  const int E = L.E;
+  if (S == 1) {
+    if (!active) return;
+    double BORTH_GLOBAL* out = gmem(g.part) + (int64_t)wg * E * 2;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const dd_t v = dot2_finish(th[e], acc[e]);
+      out[2 * (t * 16 + e)] = v.hi;
+      out[2 * (t * 16 + e) + 1] = v.lo;
+    }
+    return;
+  }
+  // row phases combined in phase order in LDS, then this workgroup's partial
+  double* red = lds;
+  for (int ph = 0; ph < S; ++ph) {
+    if (active && phase == ph) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int x = t * 16 + e;
+        dd_t v = dot2_finish(th[e], acc[e]);
+        if (ph > 0) v = dd_add(dd_make(red[2 * x], red[2 * x + 1]), v);
+        red[2 * x] = v.hi;
+        red[2 * x + 1] = v.lo;
+      }
+    }
+    __syncthreads();
+  }
+  double BORTH_GLOBAL* out = gmem(g.part) + (int64_t)wg * E * 2;
+  for (int x = tid; x < E * 2; x += 256) out[x] = red[x];
+}
+
+// ---------------------------------------------------------------------------
 // binary64 Gram of a narrow block (padded width WP <= 8, no weights): one row
 // per lane and step, UR rows in flight per lane, all WP (WP + 1) / 2 products
 // of a row in registers.  The tile kernel would give each thread a 4x4 tile
@@ -684,9 +912,34 @@ static int gram_tiles_rows(const GramLayout& L, int NT, bool biased) {
   return best * RS;
 }
 
+// The DMA-staged DD sweep (gram_dd_dma_kernel): biased DD on 256 threads
+// over 16-byte aligned rows of binary64 data without weights.
+bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT) {
+  if (mode != 1 || NT != 256 || s.bw || s.dot2 || s.x_f32) return false;
+  if (L.ntiles > 256) return false;
+  if ((reinterpret_cast<uintptr_t>(s.X) & 15) || (s.ldx & 1) || (L.k & 1)) return false;
+  if (L.ky > 0 && ((reinterpret_cast<uintptr_t>(s.Y) & 15) || (s.ldy & 1) || (L.ky & 1)))
+    return false;
+  return true;
+}
+
+// LDS of one DMA-sweep workgroup (two are resident per compute unit).
+constexpr size_t kDmaLdsBytes = 64 * 1024;
+
+// Rows per panel of the DMA sweep: S phases of np rows each, np even and at
+// most 40 (the bias exponent cb then stays at 7), the tallest panel whose
+// rows (stride Wp + 2) and column maxima fit the workgroup's LDS.
+static int gram_dma_rows(const GramLayout& L, int S) {
+  const size_t stride = (size_t)L.Wp + 2;
+  int np = 40;
+  while (np > 2 && ((size_t)S * np * stride + L.Wp) * sizeof(double) > kDmaLdsBytes) np -= 2;
+  return S * np;
+}
+
 int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
   if (gram_kind(L, mode, s.bw != nullptr) == 0) return (s.m + 3) / 4;
-  const int P = gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
+  const int P = gram_dma_ok(s, L, mode, NT) ? gram_dma_rows(L, NT / L.ntiles)
+                                            : gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
   return (s.m + P - 1) / P;
 }
 
@@ -708,7 +961,16 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
   g.P = 0;
   g.S = 0;
   *shmem = 0;
-  if (gram_kind(L, mode, s.bw != nullptr) == 1) {
+  if (gram_kind(L, mode, s.bw != nullptr) == 1 && gram_dma_ok(s, L, mode, NT)) {
+    g.S = NT / L.ntiles;
+    if (g.S < 1) return false;
+    g.P = gram_dma_rows(L, g.S);
+    g.nunits = (s.m + g.P - 1) / g.P;
+    const size_t panel = ((size_t)g.P * (L.Wp + 2) + L.Wp) * sizeof(double);
+    const size_t redn = g.S > 1 ? (size_t)L.E * 2 * sizeof(double) : 0;
+    *shmem = panel > redn ? panel : redn;
+    if (*shmem > kDmaLdsBytes) return false;
+  } else if (gram_kind(L, mode, s.bw != nullptr) == 1) {
     g.S = NT / L.ntiles;
     if (g.S < 1 || NT / L.Wp < 1) return false;
     g.P = gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
@@ -754,7 +1016,25 @@ hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int g
     }
     return hipGetLastError();
   }
-  if (NT_or_T == 256) {
+  if (NT_or_T == kGramDmaArg) {
+    if (mode != 1) return hipErrorInvalidValue;
+    static std::once_flag attr;
+    std::call_once(attr, [] {
+      const void* fns[4] = {(const void*)gram_dd_dma_kernel<false, false>,
+                            (const void*)gram_dd_dma_kernel<false, true>,
+                            (const void*)gram_dd_dma_kernel<true, false>,
+                            (const void*)gram_dd_dma_kernel<true, true>};
+      for (const void* f : fns)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDmaLdsBytes);
+    });
+    // a batched launch takes the Y-capable kernel (its segments may differ)
+    if (b)
+      hipLaunchKernelGGL((gram_dd_dma_kernel<true, true>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+    else if (one.L.ky > 0)
+      hipLaunchKernelGGL((gram_dd_dma_kernel<false, true>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+    else
+      hipLaunchKernelGGL((gram_dd_dma_kernel<false, false>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+  } else if (NT_or_T == 256) {
     if (mode == 1) BORTH_TILES(true, 256); else BORTH_TILES(false, 256);
   } else if (NT_or_T == 1024) {
     if (mode == 1) BORTH_TILES(true, 1024); else BORTH_TILES(false, 1024);
@@ -781,7 +1061,9 @@ int gram_tiles_resident(int mode, int NT, size_t shmem) {
   }
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   hipError_t e;
-  if (NT == 256)
+  if (NT == kGramDmaArg)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_dd_dma_kernel<false, false>, 256, shmem);
+  else if (NT == 256)
     e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 256, false, false>, 256, shmem)
              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 256, false, false>, 256, shmem);
   else
@@ -821,6 +1103,7 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
   }
   const int kind = gram_kind(L, mode, s.bw != nullptr);
   const int NT = kind == 0 ? 256 : gram_tiles_threads(L);
+  const bool dma = kind == 1 && gram_dma_ok(s, L, mode, NT);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   if (tune.nwg <= 0 && kind == 1) {
     // ALU-bound tile kernel: two full rounds of resident workgroups (measured
@@ -828,7 +1111,7 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
     GramSeg g0;
     size_t sh0 = 0;
     if (gram_seg(s, L, mode, NT, partials, 0, 1, &g0, &sh0)) {
-      const int r = gram_tiles_resident(mode, NT, sh0);
+      const int r = gram_tiles_resident(mode, dma ? kGramDmaArg : NT, sh0);
       if (r > 0) nwg = 2 * r;
     }
     const int64_t fit = cap / ((int64_t)L.E * (mode ? 2 : 1));  // partial slots available
@@ -840,7 +1123,7 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
   GramSeg g;
   size_t shmem = 0;
   if (!gram_seg(s, L, mode, NT, partials, 0, nwg, &g, &shmem)) return hipErrorInvalidValue;
-  const int arg = kind == 0 ? (L.Wp + 15) / 16 : NT;
+  const int arg = kind == 0 ? (L.Wp + 15) / 16 : (dma ? kGramDmaArg : NT);
   *nwg_out = nwg;
   return launch_gram_segs(kind, mode, arg, shmem, nwg, g, nullptr, nullptr, st);
 }

@@ -91,10 +91,16 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
 // Pieces of launch_gram for the batched driver.
 int gram_kind(const GramLayout& L, int mode, bool weighted = false);  // 0 MFMA (binary64), 1 VALU tiles
 int gram_tiles_threads(const GramLayout& L);   // 256 or 1024
+// The tile sweep of a DD Gram staged by direct global-to-LDS transfers
+// (biased DD, 256 threads, 16-byte aligned rows); launch_gram_segs takes
+// kGramDmaArg as its thread argument for it.
+bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT);
+constexpr int kGramDmaArg = 257;
 int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT);
 bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part, int wg0,
               int nwg, GramSeg* out, size_t* shmem);
-// kind 0: NT_or_T = column blocks (Wp / 16, rounded up); kind 1: threads.
+// kind 0: NT_or_T = column blocks (Wp / 16, rounded up); kind 1: threads
+// (256 or 1024), or kGramDmaArg.
 hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int grid,
                             const GramSeg& one, const GramSeg* tab, const int* wg2seg,
                             hipStream_t st);

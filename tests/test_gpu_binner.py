@@ -69,9 +69,11 @@ def test_b_inner_identity_weights_match_plain():
     for r in (r0, r1):
         met = oracle.metrics(host(r[0]), X, host(r[1]), Y, host(r[2]))
         assert met["omega"] <= 1e-14 and met["omega_y"] <= 1e-14 and met["rho"] <= 1e-14
-    # same arithmetic up to the exact weight products (w = 1, and unit weights
-    # take the unweighted sweep's bias): equal results
-    assert np.array_equal(host(r0[0]), host(r1[0]))
+    # the same method; the weighted sweeps stage their row panels in
+    # registers and the unweighted first sweep by direct transfers to LDS,
+    # with panels of other heights, so the DD Gram matrices differ in their
+    # last bits (~1e-31 relative) and the results agree to rounding level
+    assert np.max(np.abs(host(r0[0]) - host(r1[0]))) <= 1e-14
 
 
 def test_b_inner_errors():
