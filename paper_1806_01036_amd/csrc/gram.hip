@@ -403,13 +403,15 @@ template <bool BATCH, bool HASY>
 __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
                                                              const GramSeg* __restrict__ tab,
                                                              const int* __restrict__ wg2seg) {
-  extern __shared__ double lds[];
+  // LDS: column maxima (Wp words of 8 bytes), then the panel (P rows of
+  // Wp + 2 doubles), then 1 KiB of slack
+  extern __shared__ double lds_all[];
   const GramSeg g = BATCH ? tab[wg2seg[blockIdx.x]] : one;
   const Src& s = g.s;
   if (stopped(s.stop, s.pass)) return;
   const GramLayout& L = g.L;
   const int P = g.P, S = g.S;
-  const int np = P / S;  // rows per thread and panel (P = S np, np even)
+  const int np = P / S;  // rows per thread and panel (P = S np, np a multiple of 4)
   const int64_t npanels = g.nunits;
   const int wg = (int)blockIdx.x - g.wg0, nwg = g.nwg;
   const int Wp = L.Wp, stride = Wp + 2, cpr = stride / 2;
@@ -423,8 +425,11 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   decode_tile(t, L, ti, tj);
   int cb = 0;
   while ((1 << cb) < 2 * np + 1) ++cb;
-  unsigned long long* cmx = (unsigned long long*)(lds + P * stride);
-  for (int x = tid; x < Wp; x += 256) cmx[x] = 0ull;
+  // column maxima of the panel as the high words of |x| (sign bit shifted
+  // out): their maximum has the exponent field of the column maximum
+  unsigned* cmx = (unsigned*)lds_all;
+  double* lds = lds_all + Wp;
+  for (int x = tid; x < Wp; x += 256) cmx[x] = 0u;
 
   double acs[16], acc[16], th[16];
 #pragma unroll
@@ -443,9 +448,9 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   // Its source, relative to the panel's first row, is the same for every
   // full panel: off[i] doubles into X, or into Y where bit i of ymask is set.
   // Instructions i < nfull cover 256 chunks; one more covers the rest.
-  constexpr int kMaxChunks = 16;  // P cpr <= 4096 (64 KiB of LDS)
+  constexpr int kMaxChunks = 20;  // P cpr <= 5120 (80 KiB of LDS)
   const int nfull = nchunks / 256, nci = (nchunks + 255) / 256;
-  int off[kMaxChunks];
+  unsigned off[kMaxChunks];  // bytes
   unsigned ymask = 0u;
   auto chunk_src = [&](int q, int& r, int& o) -> bool {
     r = q / cpr;
@@ -459,40 +464,34 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   };
 #pragma unroll
   for (int i = 0; i < kMaxChunks; ++i) {
-    off[i] = 0;
+    off[i] = 0u;
     const int q = 256 * i + tid;
     if (i < nci && q < nchunks) {
       int r, o;
       const bool y = chunk_src(q, r, o);
-      off[i] = (int)((y ? (int64_t)r * s.ldy : (int64_t)r * s.ldx) + o);
+      off[i] = (unsigned)(((y ? (int64_t)r * s.ldy : (int64_t)r * s.ldx) + o) * 8);
       if (y) ymask |= 1u << i;
     }
   }
-
-  for (int64_t pnl = wg; pnl < npanels; pnl += nwg) {
+  // issues the transfers of panel pnl (rows past m: the last row again)
+  auto transfer = [&](int64_t pnl) {
     const int64_t row0 = pnl * P;
     const int64_t rem = s.m - row0;
     const int rows = rem < P ? (int)rem : P;
     if (rows == P) {
-      const double BORTH_GLOBAL* xb = Xg + row0 * s.ldx;
-      const double BORTH_GLOBAL* yb = HASY ? Yg + row0 * s.ldy : xb;
+      // uniform base + per-lane 32-bit byte offset (the saddr form)
+      const char BORTH_GLOBAL* xb = (const char BORTH_GLOBAL*)(Xg + row0 * s.ldx);
+      const char BORTH_GLOBAL* yb = HASY ? (const char BORTH_GLOBAL*)(Yg + row0 * s.ldy) : xb;
 #pragma unroll
       for (int i = 0; i < kMaxChunks; ++i) {
-        if (i < nfull) {
-          const double BORTH_GLOBAL* src = (HASY && ((ymask >> i) & 1u)) ? yb + off[i] : xb + off[i];
-          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src, (void __attribute__((address_space(3)))*)(lds + 2 * (256 * i + 64 * wave)), 16, 0, 0);
+        if (i < nfull || (i == nfull && i < nci && 256 * i + tid < nchunks)) {
+          const char BORTH_GLOBAL* src = (HASY && ((ymask >> i) & 1u)) ? yb + off[i] : xb + off[i];
+          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src,
+                                           (void __attribute__((address_space(3)))*)(lds + 2 * (256 * i + 64 * wave)),
+                                           16, 0, 0);
         }
       }
-      if (nfull < nci && 256 * nfull + tid < nchunks) {
-#pragma unroll
-        for (int i = 0; i < kMaxChunks; ++i)
-          if (i == nfull) {
-            const double BORTH_GLOBAL* src = (HASY && ((ymask >> i) & 1u)) ? yb + off[i] : xb + off[i];
-            __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src, (void __attribute__((address_space(3)))*)(lds + 2 * (256 * i + 64 * wave)), 16, 0, 0);
-          }
-      }
     } else {
-      // last panel: source rows clamped to m - 1 (zeroed below)
       for (int q0 = 0; q0 < nchunks; q0 += 256) {
         const int q = q0 + tid;
         if (q < nchunks) {
@@ -500,10 +499,45 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
           const bool y = chunk_src(q, r, o);
           const int64_t row = row0 + (r < rows ? r : rows - 1);
           const double BORTH_GLOBAL* src = y ? Yg + row * s.ldy + o : Xg + row * s.ldx + o;
-          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src, (void __attribute__((address_space(3)))*)(lds + 2 * (q0 + 64 * wave)), 16, 0, 0);
+          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src,
+                                           (void __attribute__((address_space(3)))*)(lds + 2 * (q0 + 64 * wave)),
+                                           16, 0, 0);
         }
       }
     }
+  };
+  // sigma exponent of column c: E_c with M_c < 2^E_c (frexp exponent of a
+  // normal maximum; a zero or subnormal maximum takes E_c = -1022)
+  auto col_exp = [&](int c) {
+    const unsigned h = cmx[c] >> 21;  // exponent field (the shift removed the sign)
+    return (h > 0 ? (int)h : 1) - 1022;
+  };
+
+  // fold of the finished panel: its exact biased sums (acs - sigma) into
+  // the DD totals (th, acc)
+  int ea[4], eb[4];
+  auto fold = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(ea[i]), "+v"(eb[i]));
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const double h = acs[e] - __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
+      const dd_t tt = two_sum(th[e], h);
+      const dd_t n = fast_two_sum(tt.hi, acc[e] + tt.lo);
+      th[e] = n.hi;
+      acc[e] = n.lo;
+    }
+  };
+
+  bool folded = true;  // no panel's sums pending
+  for (int64_t pnl = wg; pnl < npanels; pnl += nwg) {
+    const int64_t rem = s.m - pnl * P;
+    const int rows = rem < P ? (int)rem : P;
+    // this panel's transfers fly while the previous panel's sums are folded
+    // (every thread passed the barrier after reading that panel)
+    transfer(pnl);
+    if (!folded && active) fold();
+    for (int x = tid; x < Wp; x += 256) cmx[x] = 0u;
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (rows < P) {
@@ -511,23 +545,22 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
       for (int x = tid; x < (P - rows) * stride; x += 256) lds[rows * stride + x] = 0.0;
     }
     if (mgrp < ngrp) {
-      double m0 = 0.0, m1 = 0.0;
+      unsigned m0 = 0u, m1 = 0u;
 #pragma unroll 4
       for (int r = mgrp; r < rows; r += ngrp) {
-        const double2 v = *(const double2*)(lds + r * stride + 2 * mcol);
-        m0 = fmax(m0, fabs(v.x));
-        m1 = fmax(m1, fabs(v.y));
+        const uint4 v = *(const uint4*)(lds + r * stride + 2 * mcol);
+        m0 = max(m0, v.y << 1);
+        m1 = max(m1, v.w << 1);
       }
-      atomicMax(&cmx[2 * mcol], (unsigned long long)__double_as_longlong(m0));
-      atomicMax(&cmx[2 * mcol + 1], (unsigned long long)__double_as_longlong(m1));
+      atomicMax(&cmx[2 * mcol], m0);
+      atomicMax(&cmx[2 * mcol + 1], m1);
     }
     __syncthreads();
     if (active) {
-      int ea[4], eb[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        ea[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[4 * ti + i]));
-        eb[i] = __builtin_amdgcn_frexp_exp(__longlong_as_double((long long)cmx[4 * tj + i])) + cb;
+        ea[i] = col_exp(4 * ti + i);
+        eb[i] = col_exp(4 * tj + i) + cb;
       }
 #pragma unroll
       for (int e = 0; e < 16; ++e) acs[e] = __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
@@ -555,20 +588,12 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
           acs[e] = s2;
         }
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(ea[i]), "+v"(eb[i]));
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const double h = acs[e] - __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
-        const dd_t tt = two_sum(th[e], h);
-        const dd_t n = fast_two_sum(tt.hi, acc[e] + tt.lo);
-        th[e] = n.hi;
-        acc[e] = n.lo;
-      }
     }
+    folded = false;
     __syncthreads();
-    for (int x = tid; x < Wp; x += 256) cmx[x] = 0ull;
   }
+  if (!folded && active) fold();
+  __syncthreads();
 
   const int E = L.E;
   if (S == 1) {
@@ -583,7 +608,7 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
     return;
   }
   // row phases combined in phase order in LDS, then this workgroup's partial
-  double* red = lds;
+  double* red = lds_all;
   for (int ph = 0; ph < S; ++ph) {
     if (active && phase == ph) {
 #pragma unroll
@@ -923,22 +948,29 @@ bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT) {
   return true;
 }
 
-// LDS of one DMA-sweep workgroup (two are resident per compute unit).
-constexpr size_t kDmaLdsBytes = 64 * 1024;
+// LDS of one DMA-sweep workgroup (two are resident per compute unit, which
+// has 160 KiB).
+constexpr size_t kDmaLdsBytes = 80 * 1024;
 
 // Rows per panel of the DMA sweep: S phases of np rows each, np even and at
-// most 40 (the bias exponent cb then stays at 7), the tallest panel whose
-// rows (stride Wp + 2) and column maxima fit the workgroup's LDS.
-static int gram_dma_rows(const GramLayout& L, int S) {
+// most 40 (the bias exponent cb then stays at 7), a multiple of 4 (four rows
+// per loop trip), the tallest panel whose
+// rows (stride Wp + 2) and column maxima fit the workgroup's LDS.  A
+// panel's rounding error grows about as np 2^cb ~ 2 np^2 per thread and is
+// averaged over the panels summed, so a short block (fewer than 16 panels'
+// worth of rows at the full height) takes shorter panels.
+static int gram_dma_rows(const GramLayout& L, int S, int64_t m) {
   const size_t stride = (size_t)L.Wp + 2;
   int np = 40;
-  while (np > 2 && ((size_t)S * np * stride + L.Wp) * sizeof(double) > kDmaLdsBytes) np -= 2;
+  while (np > 4 && ((size_t)S * np * stride + L.Wp) * sizeof(double) + 1024 > kDmaLdsBytes) np -= 4;
+  const int64_t short_np = m / (16 * (int64_t)S);
+  if (short_np < np) np = short_np < 4 ? 4 : (int)(short_np & ~(int64_t)3);
   return S * np;
 }
 
 int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
   if (gram_kind(L, mode, s.bw != nullptr) == 0) return (s.m + 3) / 4;
-  const int P = gram_dma_ok(s, L, mode, NT) ? gram_dma_rows(L, NT / L.ntiles)
+  const int P = gram_dma_ok(s, L, mode, NT) ? gram_dma_rows(L, NT / L.ntiles, s.m)
                                             : gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
   return (s.m + P - 1) / P;
 }
@@ -964,9 +996,11 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
   if (gram_kind(L, mode, s.bw != nullptr) == 1 && gram_dma_ok(s, L, mode, NT)) {
     g.S = NT / L.ntiles;
     if (g.S < 1) return false;
-    g.P = gram_dma_rows(L, g.S);
+    g.P = gram_dma_rows(L, g.S, s.m);
     g.nunits = (s.m + g.P - 1) / g.P;
-    const size_t panel = ((size_t)g.P * (L.Wp + 2) + L.Wp) * sizeof(double);
+    // panel rows, column maxima, and slack for the spare lanes of the last
+    // transfer instruction (a wave writes 64 chunks of 16 bytes)
+    const size_t panel = ((size_t)g.P * (L.Wp + 2) + L.Wp) * sizeof(double) + 1024;
     const size_t redn = g.S > 1 ? (size_t)L.E * 2 * sizeof(double) : 0;
     *shmem = panel > redn ? panel : redn;
     if (*shmem > kDmaLdsBytes) return false;
