@@ -194,10 +194,12 @@ borth_status borth_update(borth_ctx ctx, int64_t m, int k, borth_dtype dt, const
  * BORTH_FLAG_AUTO_ESCALATE (binary64 X, Q not aliasing X; synchronizes):
  * after a breakdown the call is repeated, first with the DD Gram (if the
  * binary64 one broke down), then with the DD Gram, a first-pass shift of
- * 11 (m k + k (k + 1)) 2^-104 trace(M) and three passes (shifted CholQR3
- * with a DD Gram; the shift keeps the Cholesky of the first pass away from
- * breakdown up to about kappa = 1e20).  info->escalation tells which
- * attempt succeeded; R and C are those of the last attempt.
+ * 11 (m k + k (k + 1)) 2^-53 trace(M) and three passes (shifted CholQR3:
+ * the shift bounds the condition number of the first pass's result by about
+ * (11 m k u)^-1/2, which the binary64 passes after it can take; an X of
+ * exact rank below k can still meet a non-positive pivot in a later pass,
+ * which is then reported).  info->escalation tells which attempt ran last;
+ * R and C are those of the last attempt.
  *
  * The environment variable BORTH_LOG=1 prints one line per call to stderr
  * (shape, options and, when the call synchronizes, status and estimates). */
@@ -351,6 +353,20 @@ borth_status borth_autotune_load(borth_ctx ctx, const char* cache_path);
  * 1 = update sweeps; returns the number of timed launches in *count. */
 borth_status borth_set_profiling(borth_ctx ctx, int on);
 borth_status borth_kernel_time(borth_ctx ctx, int kind, double* avg_ms, int* count);
+
+/* Measurement helper (not part of the method): the HBM rate a plain
+ * streaming kernel reaches on this device, the yardstick the sweeps are
+ * compared against.  kind 0 reads nbytes from src (dst receives one word per
+ * workgroup: at least 64 bytes per compute unit), kind 1 copies nbytes from
+ * src to dst, kind 2 the same with non-temporal stores.  Each thread moves
+ * 16-byte vectors, four in flight, in a grid-stride loop; grids of 2, 4, 8
+ * and 16 workgroups of 256 threads per compute unit are timed with HIP
+ * events over reps launches each (after one warm-up launch) and the fastest
+ * is returned: *best_ms per launch, *best_grid (may be NULL) its grid.
+ * src and dst: device, 16-byte aligned, nbytes a multiple of 16; the call
+ * synchronizes. */
+borth_status borth_stream_probe(borth_ctx ctx, int kind, const void* src, void* dst,
+                                int64_t nbytes, int reps, double* best_ms, int* best_grid);
 
 #ifdef __cplusplus
 }

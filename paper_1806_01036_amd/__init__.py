@@ -19,7 +19,7 @@ from . import _lib
 
 __all__ = [
     "BorthError", "Breakdown", "Context", "Info", "default_context", "gram", "factor",
-    "update", "orthonormalize", "orthonormalize_noalloc", "orthonormalize_dd",
+    "update", "orthonormalize", "orthonormalize_noalloc", "orthonormalize_dd", "stream_probe",
     "orthonormalize_iter",
     "batch_orthonormalize", "GRAM", "FACT",
     "SCHED",
@@ -308,6 +308,28 @@ def orthonormalize(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",
     if check or st not in (BREAKDOWN, NONFINITE):
         ctx.check(st)
     return Q, R, (C if ky else None), info
+
+
+def stream_probe(kind, src, dst, nbytes=None, reps=10, ctx=None):
+    """HBM streaming probe (borth_stream_probe): kind "read", "copy" or
+    "copy_nt" over ``nbytes`` (default: all of ``src``) of the device tensors
+    ``src`` and ``dst``.  Returns (ms per launch, GB/s of the bytes moved,
+    grid)."""
+    ctx = ctx or default_context(src.device.index)
+    k = {"read": 0, "copy": 1, "copy_nt": 2}[kind]
+    n = int(nbytes if nbytes is not None else src.numel() * src.element_size())
+    if not (src.is_cuda and dst.is_cuda) or n > src.numel() * src.element_size():
+        raise ArgumentError("stream_probe: device tensors, nbytes within src")
+    if k and n > dst.numel() * dst.element_size():
+        raise ArgumentError("stream_probe: dst smaller than nbytes")
+    if not k and dst.numel() * dst.element_size() < 65536:
+        raise ArgumentError("stream_probe: a read needs 64 KiB of dst for its workgroup words")
+    ms = ctypes.c_double()
+    grid = ctypes.c_int()
+    ctx.check(ctx.lib.borth_stream_probe(ctx.h, k, _ptr(src), _ptr(dst), n, int(reps),
+                                         ctypes.byref(ms), ctypes.byref(grid)))
+    moved = n * (1 if k == 0 else 2)
+    return ms.value, moved / (ms.value * 1e-3) / 1e9, grid.value
 
 
 def orthonormalize_noalloc(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",

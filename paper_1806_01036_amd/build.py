@@ -33,6 +33,7 @@ SOURCES = [
     "update_narrow.hip",
     "update_narrow_gram.hip",
     "noalloc.hip",
+    "probe.hip",
     "batch.cpp",
     "borth.cpp",
 ]

@@ -632,7 +632,10 @@ borth_status borth_orthonormalize(borth_ctx c, int64_t m, int k, borth_dtype dt,
       level = o.gram == BORTH_GRAM_DD ? 2 : level + 1;
       if (level == 2) {
         if (ky > 16 && !(o.flags & BORTH_FLAG_PROJECT_ONCE)) break;  // fused Gram limit
-        o2.shift = 11.0 * ((double)m * k + (double)k * (k + 1)) * std::ldexp(1.0, -104);
+        // the shift of shifted CholQR3 with the binary64 unit roundoff: the
+        // passes after the first are binary64 and must see a first-pass
+        // result with kappa^2 u < 1 even when X is rank deficient
+        o2.shift = 11.0 * ((double)m * k + (double)k * (k + 1)) * std::ldexp(1.0, -53);
         o2.passes = 3;
         o2.sched = BORTH_SCHED_MATERIALIZE;
       }

@@ -238,7 +238,12 @@ struct UpdClass {
   int two;     // second stage
   int gr;      // 0 no Gram, 1 Gram of T, 2 Gram of [Y | T]
   int f32;     // X stored as fp32
+  int dma = 0; // panels by direct transfers (update_dma_ok); the same for every block of a launch
 };
+// Whether an update sweep over these rows can take its panels by direct
+// global-to-LDS transfers: binary64, 16-byte aligned rows of X (and Y), even
+// ldx, ldy, k and ky, padded width 16 or 32, ky <= 16.
+bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32);
 // Narrow blocks (k <= 8, ky <= 64), single stage, no fused Gram: the VALU
 // stream kernel of update_narrow.hip.  kp: row stride of C and Z.
 bool update_narrow_ok(int k, int ky, int kp);
@@ -258,7 +263,7 @@ hipError_t launch_update_k32(const UpdClass&, int grid, const UpdDev&, const Upd
 hipError_t launch_update_k64(const UpdClass&, int grid, const UpdDev&, const UpdDev*, const int*, hipStream_t);
 hipError_t launch_update_class(const UpdClass&, int grid, const UpdDev& one, const UpdDev* tab,
                                const int* wg2seg, hipStream_t st);
-int update_waves(int K, int KYP);  // waves per workgroup of a single-stage class
+int update_waves(int K, int KYP, bool dma = false);  // waves per workgroup of a single-stage class
 int update_rows(int K);            // rows per wave panel
 // Layout of the fused Gram of an update sweep (of [Y | T] with Y padded to
 // 16 columns when with_y, else of T).

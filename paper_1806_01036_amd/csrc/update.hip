@@ -9,8 +9,16 @@
 
 namespace borth {
 
-int update_waves(int K, int KYP) { return upd::upd_waves(K, KYP); }
+int update_waves(int K, int KYP, bool dma) { return upd::upd_waves(K, KYP, 1, dma); }
 int update_rows(int K) { return upd::upd_rows(K); }
+
+bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32) {
+  if (f32 || !upd::upd_dma_class(K, KYP)) return false;
+  if ((reinterpret_cast<uintptr_t>(d.X) & 15) || (d.ldx & 1) || (d.k & 1)) return false;
+  if (d.ky > 0 && ((reinterpret_cast<uintptr_t>(d.Y) & 15) || (d.ldy & 1) || (d.ky & 1)))
+    return false;
+  return true;
+}
 
 GramLayout update_gram_layout(int ky, int k, int K, bool with_y) {
   GramLayout G;
@@ -93,7 +101,8 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
     const int64_t slots = a.partial_cap_doubles / ((int64_t)a.glayout.E * (a.gram_dd ? 2 : 1));
     return launch_update_narrow_gram(d, K, a.gram_dd, a.glayout, slots, &a.nwg, st);
   }
-  const int NW = upd::upd_waves(K, KYP, a.two_stage ? 2 : 1);
+  const bool dma = update_dma_ok(d, K, KYP, a.src.x_f32 != 0);
+  const int NW = upd::upd_waves(K, KYP, a.two_stage ? 2 : 1, dma);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   const int64_t need = (d.npanels + NW - 1) / NW;
   if (nwg > need) nwg = (int)(need > 0 ? need : 1);
@@ -107,6 +116,7 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   c.two = a.two_stage ? 1 : 0;
   c.gr = !a.partials ? 0 : (gy ? 2 : 1);
   c.f32 = a.src.x_f32;
+  c.dma = dma ? 1 : 0;
   return launch_update_class(c, nwg, d, nullptr, nullptr, st);
 }
 

@@ -53,22 +53,27 @@ __device__ __forceinline__ void wave_lds_sync() {
 // the register file next to the fused Gram accumulators, and 64-row panels
 // of [Y | X] would leave fewer than one wave per SIMD under the LDS budget.
 __host__ __device__ constexpr bool upd_zl(int K) { return K >= 64; }
-__host__ __device__ constexpr int upd_rows(int K) { return upd_zl(K) ? 16 : 64; }
+__host__ __device__ constexpr int upd_rows(int K) { return upd_zl(K) ? 16 : 32; }
 __host__ __device__ constexpr int upd_zs(int K) { return K + 2; }  // LDS row stride of Z / W
+// Panels brought in by direct global-to-LDS transfers, double-buffered per
+// wave (binary64 rows, 16-byte aligned, K <= 32 and at most 16 Y columns):
+// the next panel's rows are in flight while the current one is computed.
+__host__ __device__ constexpr bool upd_dma_class(int K, int KYP) { return K >= 16 && K <= 32 && KYP <= 16; }
 
-// LDS bytes of a workgroup with nw waves (one panel per wave, plus the
-// shared Z / W operands of each stage when they live in LDS).
-inline long upd_lds_bytes(int K, int KYP, int nw, int nst = 1) {
+// LDS bytes of a workgroup with nw waves (one panel per wave, two with the
+// transfers, plus the shared Z / W operands of each stage when they live in
+// LDS).
+inline long upd_lds_bytes(int K, int KYP, int nw, int nst = 1, bool dma = false) {
   const long zreg = upd_zl(K) ? (long)nst * (K + KYP) * upd_zs(K) : 0;
-  return 8L * (zreg + (long)nw * upd_rows(K) * (KYP + K + 2));
+  return 8L * (zreg + (long)nw * (dma ? 2 : 1) * upd_rows(K) * (KYP + K + 2));
 }
 
 // Waves per workgroup (1..8): the most resident waves per CU under the 160 KB
 // of LDS, at most 8 (2 per SIMD); larger workgroups preferred.
-inline int upd_waves(int K, int KYP, int nst = 1) {
+inline int upd_waves(int K, int KYP, int nst = 1, bool dma = false) {
   int best = 1, best_waves = 0;
   for (int nw = 1; nw <= 8; nw <<= 1) {
-    const long b = upd_lds_bytes(K, KYP, nw, nst);
+    const long b = upd_lds_bytes(K, KYP, nw, nst, dma);
     const int wgs = (int)((160L * 1024) / b);
     int waves = wgs * nw;
     if (waves > 8) waves = 8;
@@ -81,7 +86,10 @@ inline int upd_waves(int K, int KYP, int nst = 1) {
 }
 
 // GR: 0 = no Gram, 1 = Gram of T, 2 = Gram of [Y | T] (KYP = 16).
-template <int K, int KYP, bool TWO, int GR, typename ST, bool BATCH>
+// DMA: the panels come in by direct transfers into two LDS buffers per wave
+// (upd_dma_class; binary64 rows with X, Y 16-byte aligned, even ldx, ldy,
+// k and ky).
+template <int K, int KYP, bool TWO, int GR, typename ST, bool BATCH, bool DMA>
 __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* __restrict__ tab,
                                                      const int* __restrict__ wg2seg) {
   extern __shared__ double lds[];
@@ -112,7 +120,8 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   const int dense = a.dense;
   const int c16 = lane & 15, r4 = lane >> 4;
   double* zl = lds;
-  double* pan = lds + (ZL ? NST * ZST : 0) + wave * PR * S;
+  double* pan0 = lds + (ZL ? NST * ZST : 0) + wave * (DMA ? 2 : 1) * PR * S;
+  double* pan = pan0;
 
   // B operands: in registers (lane l holds Z[4 s + l / 16][16 J + l % 16] and
   // -C[4 s + l / 16][16 J + l % 16]), or for ZL rows of Z then rows of -C in
@@ -170,10 +179,50 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   const int aoff = c16 * S + r4;  // A operand: row l % 16, column l / 16
   const int doff = r4 * S + c16;  // result layout: row l / 16, column l % 16
   const int64_t npanels = (a.m + PR - 1) / PR;
+  // Direct transfers: chunk q = 64 i + lane (16 bytes) of a panel lands at
+  // byte 16 q of the wave's buffer (row q / (S / 2), columns 2 (q % (S / 2))
+  // and the next).  Chunks of padding columns and rows past m copy a valid
+  // chunk of the row (or of the last row): padding columns meet zero rows of
+  // Z and W and land in padded Gram entries; rows past m are zeroed before
+  // use.
+  constexpr int CPR = S / 2, NCH = PR * CPR, NDI = (NCH + 63) / 64;
+  auto transfer = [&](int64_t p, double* buf) {
+    const int64_t r0 = p * PR;
+    const int64_t last = a.m - 1;
+#pragma unroll
+    for (int i = 0; i < NDI; ++i) {
+      const int q = 64 * i + lane;
+      if (i + 1 < NDI || q < NCH) {
+        const int r = q / CPR, col = 2 * (q % CPR);
+        int64_t row = r0 + r;
+        row = row < last ? row : last;
+        const double BORTH_GLOBAL* src;
+        if (KYP > 0 && col < KYP)
+          src = gmem(a.Y) + row * a.ldy + (col + 1 < ky ? col : 0);
+        else
+          src = gmem((const double*)a.X) + row * a.ldx + (col - KYP + 1 < a.k ? col - KYP : 0);
+        __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src,
+                                         (void __attribute__((address_space(3)))*)(buf + 128 * i), 16, 0, 0);
+      }
+    }
+  };
+  if (DMA && pnl < npanels) transfer(pnl, pan0);
+  int cur = 0;
   while (pnl < npanels) {
     const int64_t row0 = pnl * PR;
     const int nrows = (int)(a.m - row0 < PR ? a.m - row0 : PR);
     wave_lds_sync();  // this wave's reads of its previous panel are done
+    if (DMA) {
+      pan = pan0 + cur * PR * S;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if (nrows < PR) {
+        for (int x = lane; x < (PR - nrows) * S; x += 64) pan[nrows * S + x] = 0.0;
+      }
+      wave_lds_sync();
+      // the next panel's rows fly while this one is computed
+      if (pnl + wstride < npanels) transfer(pnl + wstride, pan0 + (cur ^ 1) * PR * S);
+      cur ^= 1;
+    } else {
     // 1. [Y | S] rows -> LDS (zero outside m, ky, k).  Loads are
     // unconditional (rows clamped to m - 1, columns to 0) so that they issue
     // back to back; out-of-range values are replaced by zero afterwards.
@@ -207,6 +256,7 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
       }
     }
     wave_lds_sync();
+    }
 #pragma unroll 1
     for (int b = 0; b < PR / 16; ++b) {  // 16-row blocks
       double* pb = pan + 16 * b * S;
@@ -225,12 +275,16 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
 #pragma unroll
             for (int v = 0; v < 4; ++v)
               if (st == 0) t[J][v] = pb[doff + 4 * v * S + KYP + 16 * J];
+          // the A operands of every k-step first, so that the matrix-core
+          // chain issues back to back
+          double ay[YS > 0 ? YS : 1];
+#pragma unroll
+          for (int s = 0; s < YS; ++s) ay[s] = pb[aoff + 4 * s];
 #pragma unroll
           for (int s = 0; s < YS; ++s) {
-            const double av = pb[aoff + 4 * s];
 #pragma unroll
             for (int J = 0; J < KC; ++J)
-              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw(st, s, J), t[J], 0, 0, 0);
+              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[s], bw(st, s, J), t[J], 0, 0, 0);
           }
         }
         if (YS > 0 || st > 0) {
@@ -245,15 +299,37 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
         // 2. T = Xt Z_st
 #pragma unroll
         for (int J = 0; J < KC; ++J) t[J] = d4_t{0.0, 0.0, 0.0, 0.0};
-        // with the B operands in LDS, a partly unrolled k loop bounds the
-        // operand loads in flight (the registers are needed by the Gram)
-#pragma unroll(ZL ? 2 : KS)
-        for (int s = 0; s < KS; ++s) {
-          const double av = pb[aoff + KYP + 4 * s];
+        if (ZL) {
+          // with the B operands in LDS, a partly unrolled k loop bounds the
+          // operand loads in flight (the registers are needed by the Gram)
+#pragma unroll 2
+          for (int s = 0; s < KS; ++s) {
+            const double av = pb[aoff + KYP + 4 * s];
 #pragma unroll
-          for (int J = 0; J < KC; ++J)
-            if (dense || 4 * s <= 16 * J + 15)  // upper-triangular Z: skip zero blocks
-              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bz(st, s, J), t[J], 0, 0, 0);
+            for (int J = 0; J < KC; ++J)
+              if (dense || 4 * s <= 16 * J + 15)  // upper-triangular Z: skip zero blocks
+                t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bz(st, s, J), t[J], 0, 0, 0);
+          }
+        } else {
+          // all A operands first, then the chain: upper-triangular Z (the
+          // zero blocks skipped) or dense Z, one uniform branch
+          double ax[KS];
+#pragma unroll
+          for (int s = 0; s < KS; ++s) ax[s] = pb[aoff + KYP + 4 * s];
+          if (dense) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+              for (int J = 0; J < KC; ++J)
+                t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], bz(st, s, J), t[J], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+              for (int J = 0; J < KC; ++J)
+                if (4 * s <= 16 * J + 15)
+                  t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], bz(st, s, J), t[J], 0, 0, 0);
+          }
         }
       }
       // store T rows 16 b + l / 16 + 4 v, columns 16 J + l % 16
@@ -340,19 +416,29 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
 
 template <int K, int KYP, bool TWO, int GR, typename ST>
 hipError_t launch_upd_t(int grid, const UpdDev& one, const UpdDev* tab, const int* map,
-                        hipStream_t st) {
-  const int NW = upd_waves(K, KYP, TWO ? 2 : 1);
+                        hipStream_t st, bool dma) {
+  constexpr bool DC = upd_dma_class(K, KYP) && sizeof(ST) == 8;
+  dma = dma && DC;
+  const int NW = upd_waves(K, KYP, TWO ? 2 : 1, dma);
   constexpr int KC = (K + 15) / 16;
   constexpr int T16 = (GR == 2 ? 1 : 0) + KC;
   const size_t red = GR ? sizeof(double) * T16 * (T16 + 1) / 2 * 4 * 64 : 0;
-  const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW, TWO ? 2 : 1);
+  const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW, TWO ? 2 : 1, dma);
   const size_t shmem = lb > red ? lb : red;
-  if (tab)
-    hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, true>), dim3(grid), dim3(64 * NW), shmem,
-                       st, one, tab, map);
-  else
-    hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, false>), dim3(grid), dim3(64 * NW), shmem,
-                       st, one, tab, map);
+  if (dma) {
+    if (tab)
+      hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, true, DC>), dim3(grid), dim3(64 * NW),
+                         shmem, st, one, tab, map);
+    else
+      hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, false, DC>), dim3(grid), dim3(64 * NW),
+                         shmem, st, one, tab, map);
+  } else if (tab) {
+    hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, true, false>), dim3(grid), dim3(64 * NW),
+                       shmem, st, one, tab, map);
+  } else {
+    hipLaunchKernelGGL((update_kernel<K, KYP, TWO, GR, ST, false, false>), dim3(grid), dim3(64 * NW),
+                       shmem, st, one, tab, map);
+  }
   return hipGetLastError();
 }
 
@@ -363,31 +449,31 @@ hipError_t launch_upd_k(const UpdClass& c, int grid, const UpdDev& one, const Up
   if (grid < 1) return hipSuccess;
   if (c.f32) {
     if (c.two || c.KYP || c.gr == 2) return hipErrorInvalidValue;
-    return c.gr ? launch_upd_t<K, 0, false, 1, float>(grid, one, tab, map, st)
-                : launch_upd_t<K, 0, false, 0, float>(grid, one, tab, map, st);
+    return c.gr ? launch_upd_t<K, 0, false, 1, float>(grid, one, tab, map, st, c.dma)
+                : launch_upd_t<K, 0, false, 0, float>(grid, one, tab, map, st, c.dma);
   }
   if (c.KYP == 0) {
     if (c.gr == 2) return hipErrorInvalidValue;
     if (c.two)
-      return c.gr ? launch_upd_t<K, 0, true, 1, double>(grid, one, tab, map, st)
-                  : launch_upd_t<K, 0, true, 0, double>(grid, one, tab, map, st);
-    return c.gr ? launch_upd_t<K, 0, false, 1, double>(grid, one, tab, map, st)
-                : launch_upd_t<K, 0, false, 0, double>(grid, one, tab, map, st);
+      return c.gr ? launch_upd_t<K, 0, true, 1, double>(grid, one, tab, map, st, c.dma)
+                  : launch_upd_t<K, 0, true, 0, double>(grid, one, tab, map, st, c.dma);
+    return c.gr ? launch_upd_t<K, 0, false, 1, double>(grid, one, tab, map, st, c.dma)
+                : launch_upd_t<K, 0, false, 0, double>(grid, one, tab, map, st, c.dma);
   }
   if (c.KYP == 16) {
     if (c.two) {
-      if (c.gr == 2) return launch_upd_t<K, 16, true, 2, double>(grid, one, tab, map, st);
-      if (c.gr == 1) return launch_upd_t<K, 16, true, 1, double>(grid, one, tab, map, st);
-      return launch_upd_t<K, 16, true, 0, double>(grid, one, tab, map, st);
+      if (c.gr == 2) return launch_upd_t<K, 16, true, 2, double>(grid, one, tab, map, st, c.dma);
+      if (c.gr == 1) return launch_upd_t<K, 16, true, 1, double>(grid, one, tab, map, st, c.dma);
+      return launch_upd_t<K, 16, true, 0, double>(grid, one, tab, map, st, c.dma);
     }
-    if (c.gr == 2) return launch_upd_t<K, 16, false, 2, double>(grid, one, tab, map, st);
-    if (c.gr == 1) return launch_upd_t<K, 16, false, 1, double>(grid, one, tab, map, st);
-    return launch_upd_t<K, 16, false, 0, double>(grid, one, tab, map, st);
+    if (c.gr == 2) return launch_upd_t<K, 16, false, 2, double>(grid, one, tab, map, st, c.dma);
+    if (c.gr == 1) return launch_upd_t<K, 16, false, 1, double>(grid, one, tab, map, st, c.dma);
+    return launch_upd_t<K, 16, false, 0, double>(grid, one, tab, map, st, c.dma);
   }
   // 16 < ky <= 64: single stage; a fused Gram covers T only
   if (c.KYP != 64 || c.two || c.gr == 2) return hipErrorInvalidValue;
-  return c.gr ? launch_upd_t<K, 64, false, 1, double>(grid, one, tab, map, st)
-              : launch_upd_t<K, 64, false, 0, double>(grid, one, tab, map, st);
+  return c.gr ? launch_upd_t<K, 64, false, 1, double>(grid, one, tab, map, st, c.dma)
+              : launch_upd_t<K, 64, false, 0, double>(grid, one, tab, map, st, c.dma);
 }
 
 }  // namespace upd
