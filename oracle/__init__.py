@@ -17,6 +17,8 @@ Functions (all arrays row-major float64 numpy arrays):
 * update_q(X, Z, Y, C)    (X - Y C) Z in binary128, rounded once
 * qr_q(X, Y)              exact thin QR of (I - Y Y^T) X  (O1)
 * cholqr_steps(X, Y, ...) the paper's steps in binary64 / DD      (O2)
+* iterate(X, Y, ...)      the iterated scheme (Cholesky / SVQB)   (O2)
+* kappa_true(X, Y)        kappa from the exact Gram matrix        (O1)
 * svqb_q(M_hi, M_lo)      M^{-1/2} by binary128 Jacobi
 * metrics(Q, X, R, Y, C)  omega, rho, omega_Y, ||X||_F
 * gram_split_bf16(X32)    split-BF16 Gram model
@@ -60,6 +62,7 @@ def _load():
         lib = ctypes.CDLL(str(_LIB))
         sig = {
             "or_num_threads": ([], _int),
+            "or_set_num_threads": ([_int], None),
             "or_gram_q": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp, _dp], _int),
             "or_gram_dot2": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp, _dp], _int),
             "or_gram_f64": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _dp], _int),
@@ -73,6 +76,8 @@ def _load():
             "or_svqb_q": ([_int, _dp, _dp, _dp, _dp], _int),
             "or_cholqr_steps": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _int, _int, _int,
                                  _int, _dp, _i64, _dp, _dp, _dp, _dp], _int),
+            "or_iterate": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _int, _int, ctypes.c_double,
+                            _int, _dp, _i64, _dp, _dp, _dp, _dp, _dp], _int),
             "or_metrics": ([_i64, _int, _dp, _i64, _dp, _i64, _int, _dp, _i64, _dp,
                             _dp, _dp, _dp], _int),
             "or_gram_split_bf16": ([_i64, _int, _fp, _i64, _i64, _dp], _int),
@@ -98,6 +103,12 @@ def _p(a):
 
 def num_threads() -> int:
     return _load().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (its results do not depend on
+    the count: every sum runs over a fixed row-block partition)."""
+    _load().or_set_num_threads(int(n))
 
 
 def gram_q(A, B=None):
@@ -249,6 +260,41 @@ def cholqr_steps(X, Y=None, *, dd_first=False, passes=2, project_each_pass=True,
                                    int(bool(project_each_pass)), _p(Q), k, _p(rhi),
                                    _p(rlo), _p(chi), _p(clo))
     return dict(Q=Q, R_hi=rhi, R_lo=rlo, C_hi=chi[:ky], C_lo=clo[:ky], info=info)
+
+
+def iterate(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5):
+    """O2 iterated scheme: passes of projection against Y and Cholesky or
+    symmetric-SVQB orthonormalization (binary64, or DD Gram and factor),
+    until ||C_j||_F <= eps and ||R_j - I||_F <= eps or max_iter passes.
+
+    Returns dict(Q, R_hi, R_lo, C_hi, C_lo, passes, converged, c_norm, r_dev,
+    info) with X = Y C + Q R; info = 100*pass + pivot on a breakdown, else 0."""
+    X = _c(X)
+    m, k = X.shape
+    ky = 0 if Y is None else Y.shape[1]
+    Yc = _c(Y) if ky else np.zeros((1, 1))
+    Q = np.zeros((m, k))
+    rhi = np.zeros((k, k))
+    rlo = np.zeros((k, k))
+    chi = np.zeros((max(ky, 1), k))
+    clo = np.zeros((max(ky, 1), k))
+    out = np.zeros(4)
+    info = _load().or_iterate(m, k, _p(X), k, ky, _p(Yc), max(ky, 1), 1 if gram == "dd" else 0,
+                              1 if fact == "svqb" else 0, float(eps), int(max_iter), _p(Q), k,
+                              _p(rhi), _p(rlo), _p(chi), _p(clo), _p(out))
+    return dict(Q=Q, R_hi=rhi, R_lo=rlo, C_hi=chi[:ky], C_lo=clo[:ky], passes=int(out[0]),
+                converged=bool(out[1]), c_norm=float(out[2]), r_dev=float(out[3]), info=info)
+
+
+def kappa_true(X, Y=None):
+    """kappa of the (projected) block from its exact Gram matrix:
+    sqrt(lambda_max / lambda_min) of the binary128 Gram matrix of
+    Xt = X - Y (Y^T X), eigenvalues by binary128 Jacobi."""
+    o = qr_q(X, Y, want_gram=True)
+    _, lam, info = svqb_q(o["G_hi"], o["G_lo"])
+    if info or not lam[0] > 0:
+        return float("inf")
+    return float(np.sqrt(lam[-1] / lam[0]))
 
 
 def svqb_q(mhi, mlo=None):

@@ -57,6 +57,16 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Thread count of the following parallel regions (results do not depend on
+ * it: every sum runs over the fixed row-block partition). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static void split_q(f128 s, double* hi, double* lo) {
   double h = (double)s;
   *hi = h;
@@ -306,12 +316,12 @@ int or_qr_q(int64_t m, int k, const double* X, int64_t ldx, int ky,
  * symmetric form, the Procrustes-optimal Z of Sec. 4.2).  Eigenvalues are
  * returned in ascending order in lam (binary64).  Returns 0, or -1 if M is not
  * positive definite to binary128 working accuracy. */
-int or_svqb_q(int k, const double* mhi, const double* mlo, double* Z,
-              double* lam) {
+/* Cyclic Jacobi rotations in binary128 on the symmetric a (k x k): on return
+ * a is diagonal to working accuracy (its diagonal holds the eigenvalues) and
+ * v holds the eigenvectors as columns, a_in = v diag(a) v^T. */
+static void jacobi_q(int k, f128* a, f128* v) {
   const size_t n = (size_t)k * k;
-  f128* a = (f128*)malloc(sizeof(f128) * n + 16);
-  f128* v = (f128*)calloc(n + 1, sizeof(f128));
-  for (size_t e = 0; e < n; ++e) a[e] = join_q(mhi, mlo, e);
+  for (size_t e = 0; e < n; ++e) v[e] = 0;
   for (int i = 0; i < k; ++i) v[i * k + i] = 1;
   f128 prev_off = -1;
   for (int sweep = 0; sweep < 80; ++sweep) {
@@ -347,6 +357,15 @@ int or_svqb_q(int k, const double* mhi, const double* mlo, double* Z,
         }
       }
   }
+}
+
+int or_svqb_q(int k, const double* mhi, const double* mlo, double* Z,
+              double* lam) {
+  const size_t n = (size_t)k * k;
+  f128* a = (f128*)malloc(sizeof(f128) * n + 16);
+  f128* v = (f128*)calloc(n + 1, sizeof(f128));
+  for (size_t e = 0; e < n; ++e) a[e] = join_q(mhi, mlo, e);
+  jacobi_q(k, a, v);
   int bad = 0;
   f128* s = (f128*)malloc(sizeof(f128) * (size_t)k + 16);
   for (int i = 0; i < k; ++i) {
@@ -598,11 +617,41 @@ static void trinv_dd(int k, const dd* r, dd* z) {
   }
 }
 
+/* SVQB factor of phase II (Sec. 4.2, in the symmetric reading): the
+ * eigenpairs M = U L U^T by binary128 Jacobi, Z = U L^{-1/2} U^T = M^{-1/2}
+ * and R = U L^{1/2} U^T = M^{1/2}, so that Z^T M Z = I and M = R^T R.
+ * a: M (k x k, binary128), destroyed.  Returns 0, or 1 + the index of a
+ * non-positive eigenvalue (M not positive definite). */
+static int svqb_factor_q(int k, f128* a, f128* Z, f128* R) {
+  const size_t n = (size_t)k * k;
+  f128* v = (f128*)malloc(sizeof(f128) * n + 16);
+  jacobi_q(k, a, v);
+  int bad = 0;
+  for (int i = 0; i < k && !bad; ++i)
+    if (!(a[i * k + i] > 0)) bad = i + 1;
+  if (!bad)
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        f128 z = 0, r = 0;
+        for (int l = 0; l < k; ++l) {
+          const f128 w = v[i * k + l] * v[j * k + l];
+          z += w / sqrtq(a[l * k + l]);
+          r += w * sqrtq(a[l * k + l]);
+        }
+        Z[i * k + j] = z;
+        R[i * k + j] = r;
+      }
+  free(v);
+  return bad;
+}
+
 /* One binary64 pass (phase I then phase II):  C = Y^T X, Xt = X - Y C,
- * M = Xt^T Xt, M = R^T R, Z = R^{-1}, Q = Xt Z.  X may alias Q. */
+ * M = Xt^T Xt, then Cholesky M = R^T R, Z = R^{-1} (fact 0) or SVQB
+ * Z = M^{-1/2}, R = M^{1/2} (fact 1, factored in binary128 from the binary64
+ * M), Q = Xt Z.  X may alias Q. */
 static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
                     const double* Y, int64_t ldy, double* Q, int64_t ldq,
-                    double* R, double* C, int exact_gram) {
+                    double* R, double* C, int exact_gram, int fact) {
   double* xt = (double*)malloc(sizeof(double) * ((size_t)m * k + 1));
   if (ky > 0) gram_f64(m, ky, Y, ldy, k, X, ldx, C);
 #pragma omp parallel for schedule(static)
@@ -620,15 +669,28 @@ static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
     or_gram_q(m, k, xt, k, k, xt, k, R, NULL);
   else
     gram_f64(m, k, xt, k, k, xt, k, R);
-  const int info = chol_f64(k, R);
-  if (info) { free(xt); return info; }
   double* z = (double*)malloc(sizeof(double) * (size_t)k * k + 8);
-  trinv_f64(k, R, z);
+  if (fact == 1) {
+    const size_t n = (size_t)k * k;
+    f128* a = (f128*)malloc(sizeof(f128) * n + 16);
+    f128* zq = (f128*)malloc(sizeof(f128) * n + 16);
+    f128* rq = (f128*)malloc(sizeof(f128) * n + 16);
+    for (size_t e = 0; e < n; ++e) a[e] = (f128)R[e];
+    const int bad = svqb_factor_q(k, a, zq, rq);
+    for (size_t e = 0; e < n; ++e) { z[e] = (double)zq[e]; R[e] = (double)rq[e]; }
+    free(a); free(zq); free(rq);
+    if (bad) { free(z); free(xt); return bad; }
+  } else {
+    const int info = chol_f64(k, R);
+    if (info) { free(z); free(xt); return info; }
+    trinv_f64(k, R, z);
+  }
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < m; ++r)
     for (int j = 0; j < k; ++j) {
       double s = 0;
-      for (int i = 0; i <= j; ++i) s += xt[(size_t)r * k + i] * z[(size_t)i * k + j];
+      const int iend = fact == 1 ? k - 1 : j;  /* dense Z, or upper-triangular */
+      for (int i = 0; i <= iend; ++i) s += xt[(size_t)r * k + i] * z[(size_t)i * k + j];
       Q[r * ldq + j] = s;
     }
   free(z);
@@ -647,7 +709,7 @@ static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
  * returned coefficients.  For an exactly orthonormal Y, D = C. */
 static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
                    const double* Y, int64_t ldy, double* Q, int64_t ldq,
-                   dd* R, dd* C, int corrected) {
+                   dd* R, dd* C, int corrected, int fact) {
   const int64_t np = npart(m);
   if (ky > 0) {
     for (int l = 0; l < ky; ++l)
@@ -707,15 +769,31 @@ static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
       R[(size_t)j * k + i] = s;
     }
   free(part);
-  const int info = chol_dd(k, R);
-  if (info) { free(xt); return info; }
   dd* z = (dd*)malloc(sizeof(dd) * (n + 1));
-  trinv_dd(k, R, z);
+  if (fact == 1) {
+    /* SVQB factored in binary128 from the DD M, rounded to DD */
+    f128* a = (f128*)malloc(sizeof(f128) * n + 16);
+    f128* zq = (f128*)malloc(sizeof(f128) * n + 16);
+    f128* rq = (f128*)malloc(sizeof(f128) * n + 16);
+    for (size_t e = 0; e < n; ++e) a[e] = (f128)R[e].h + (f128)R[e].l;
+    const int bad = svqb_factor_q(k, a, zq, rq);
+    for (size_t e = 0; e < n; ++e) {
+      split_q(zq[e], &z[e].h, &z[e].l);
+      split_q(rq[e], &R[e].h, &R[e].l);
+    }
+    free(a); free(zq); free(rq);
+    if (bad) { free(z); free(xt); return bad; }
+  } else {
+    const int info = chol_dd(k, R);
+    if (info) { free(z); free(xt); return info; }
+    trinv_dd(k, R, z);
+  }
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < m; ++r)
     for (int j = 0; j < k; ++j) {
       dd s = {0, 0};
-      for (int i = 0; i <= j; ++i) s = dd_add(s, dd_mul(xt[(size_t)r * k + i], z[(size_t)i * k + j]));
+      const int iend = fact == 1 ? k - 1 : j;  /* dense Z, or upper-triangular */
+      for (int i = 0; i <= iend; ++i) s = dd_add(s, dd_mul(xt[(size_t)r * k + i], z[(size_t)i * k + j]));
       Q[r * ldq + j] = s.h + s.l;
     }
   free(z);
@@ -754,9 +832,9 @@ int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
     const int kyp = (ky > 0 && (p == 0 || project_each_pass)) ? ky : 0;
     int info;
     if (p == 0 && dd_first == 1) {
-      info = pass_dd(m, k, cur, k, kyp, Y, ldy, cur, k, rp, cp, dd_corrected);
+      info = pass_dd(m, k, cur, k, kyp, Y, ldy, cur, k, rp, cp, dd_corrected, 0);
     } else {
-      info = pass_f64(m, k, cur, k, kyp, Y, ldy, cur, k, rf, cf, p == 0 && dd_first == 2);
+      info = pass_f64(m, k, cur, k, kyp, Y, ldy, cur, k, rf, cf, p == 0 && dd_first == 2, 0);
       for (size_t e = 0; e < n; ++e) rp[e] = dd_from(rf[e]);
       for (size_t e = 0; e < (size_t)kyp * k; ++e) cp[e] = dd_from(cf[e]);
     }
@@ -788,6 +866,92 @@ int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
     }
   }
   free(rtot); free(ctot); free(cur); free(rp); free(cp); free(rf); free(cf);
+  return status;
+}
+
+/* O2 iterated scheme (Sec. 4.2: phase I and phase II alternated until the
+ * block no longer changes): pass j projects the current block S_j (X, then
+ * the previous result) against Y and orthonormalizes it, S_{j+1} =
+ * (S_j - Y C_j) Z_j, with the Gram matrix and the factor in binary64
+ * (dd = 0) or DD (dd = 1, the corrected coefficients of pass_dd), by
+ * Cholesky (fact 0) or SVQB (fact 1, symmetric Z = M^{-1/2}).  The pass is
+ * applied, then the iteration stops once ||C_j||_F <= eps and
+ * ||R_j - I||_F <= eps (the reading of the stop test, with R_j the pass's
+ * factor: triangular, or M^{1/2}), or after max_iter passes.
+ * Outputs: Q (m x k), R = R_j ... R_1 and C = the total coefficients (dense,
+ * hi/lo), X = Y C + Q R; out[0] = passes run, out[1] = 1 if the test held,
+ * out[2] = ||C_j||_F, out[3] = ||R_j - I||_F of the last pass.  Returns 0, or
+ * 100 * pass + pivot (1-based) on a breakdown. */
+int or_iterate(int64_t m, int k, const double* X, int64_t ldx, int ky, const double* Y,
+               int64_t ldy, int dd_mode, int fact, double eps, int max_iter, double* Q,
+               int64_t ldq, double* rhi, double* rlo, double* chi, double* clo, double* out) {
+  const size_t n = (size_t)k * k;
+  const size_t nc = (size_t)(ky > 0 ? ky : 1) * k;
+  dd* rtot = (dd*)malloc(sizeof(dd) * (n + 1));
+  dd* ctot = (dd*)malloc(sizeof(dd) * (nc + 1));
+  dd* rp = (dd*)malloc(sizeof(dd) * (n + 1));
+  dd* cp = (dd*)malloc(sizeof(dd) * (nc + 1));
+  dd* tmp = (dd*)malloc(sizeof(dd) * (n + nc + 1));
+  double* rf = (double*)malloc(sizeof(double) * (n + 1));
+  double* cf = (double*)malloc(sizeof(double) * (nc + 1));
+  double* cur = (double*)malloc(sizeof(double) * ((size_t)m * k + 1));
+  for (size_t e = 0; e < n; ++e) rtot[e] = dd_from(0.0);
+  for (int i = 0; i < k; ++i) rtot[i * k + i] = dd_from(1.0);
+  for (size_t e = 0; e < nc; ++e) ctot[e] = dd_from(0.0);
+  for (int64_t r = 0; r < m; ++r)
+    for (int j = 0; j < k; ++j) cur[(size_t)r * k + j] = X[r * ldx + j];
+  int status = 0, passes = 0, conv = 0;
+  double cn = 0, rd = 0;
+  for (int p = 0; p < max_iter; ++p) {
+    int info;
+    if (dd_mode) {
+      info = pass_dd(m, k, cur, k, ky, Y, ldy, cur, k, rp, cp, 1, fact);
+    } else {
+      info = pass_f64(m, k, cur, k, ky, Y, ldy, cur, k, rf, cf, 0, fact);
+      for (size_t e = 0; e < n; ++e) rp[e] = dd_from(rf[e]);
+      for (size_t e = 0; e < (size_t)ky * k; ++e) cp[e] = dd_from(cf[e]);
+    }
+    passes = p + 1;
+    if (info) { status = 100 * (p + 1) + info; break; }
+    /* this pass's norms */
+    double c2 = 0, r2 = 0;
+    for (size_t e = 0; e < (size_t)ky * k; ++e) { const double v = cp[e].h + cp[e].l; c2 += v * v; }
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        const double v = (rp[i * k + j].h - (i == j ? 1.0 : 0.0)) + rp[i * k + j].l;
+        r2 += v * v;
+      }
+    cn = sqrt(c2);
+    rd = sqrt(r2);
+    /* totals: C_tot += C_p R_tot, R_tot = R_p R_tot (dense products in DD) */
+    for (int l = 0; l < ky; ++l)
+      for (int j = 0; j < k; ++j) {
+        dd acc = ctot[(size_t)l * k + j];
+        for (int i = 0; i < k; ++i) acc = dd_add(acc, dd_mul(cp[(size_t)l * k + i], rtot[(size_t)i * k + j]));
+        tmp[(size_t)l * k + j] = acc;
+      }
+    for (size_t e = 0; e < (size_t)ky * k; ++e) ctot[e] = tmp[e];
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        dd acc = {0, 0};
+        for (int l = 0; l < k; ++l) acc = dd_add(acc, dd_mul(rp[(size_t)i * k + l], rtot[(size_t)l * k + j]));
+        tmp[(size_t)i * k + j] = acc;
+      }
+    for (size_t e = 0; e < n; ++e) rtot[e] = tmp[e];
+    if (cn <= eps && rd <= eps) { conv = 1; break; }
+  }
+  for (int64_t r = 0; r < m; ++r)
+    for (int j = 0; j < k; ++j) Q[r * ldq + j] = cur[(size_t)r * k + j];
+  for (size_t e = 0; e < n; ++e) { rhi[e] = rtot[e].h; if (rlo) rlo[e] = rtot[e].l; }
+  for (size_t e = 0; e < (size_t)ky * k; ++e) {
+    if (chi) chi[e] = ctot[e].h;
+    if (clo) clo[e] = ctot[e].l;
+  }
+  out[0] = passes;
+  out[1] = conv;
+  out[2] = cn;
+  out[3] = rd;
+  free(rtot); free(ctot); free(rp); free(cp); free(tmp); free(rf); free(cf); free(cur);
   return status;
 }
 

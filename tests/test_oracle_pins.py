@@ -476,6 +476,112 @@ def test_fig7_levels():
         assert oracle.metrics(s["Q"], X, s["R_hi"], W, s["C_hi"])["omega"] > 1e-2
 
 
+def test_fig7_levels_svqb():
+    """The paper's Fig. 7 method itself (one project / SVQB pass): the
+    oracle's binary64 pass shows the plotted slope of ~2 decades per decade of
+    kappa(X) and its levels; the DD pass stays at the output floor."""
+    fig = _fig7_right_panel()
+    paper_plain = {}
+    for e, lv in fig["plain"]:
+        paper_plain.setdefault(e, []).append(lv)
+    slope_paper = (np.mean(paper_plain[6]) - np.mean(paper_plain[0])) / 6.0
+    n, kw, nb = 1000, 20, 4
+    ours = {}
+    for e in (0, 3, 6):
+        X, W = synth.projected_pair(n, nb, kw, 10.0 ** e, 10.0 ** e, 700 + e)
+        s = oracle.iterate(X, W, gram="f64", fact="svqb", max_iter=1)
+        assert s["info"] == 0 and s["passes"] == 1
+        ours[e] = np.log10(max(oracle.metrics(s["Q"], X, s["R_hi"], W, s["C_hi"])["omega"], 1e-20))
+        d = oracle.iterate(X, W, gram="dd", fact="svqb", max_iter=1)
+        assert oracle.metrics(d["Q"], X, d["R_hi"], W, d["C_hi"])["omega"] <= 1e-15
+    assert abs((ours[6] - ours[0]) / 6.0 - slope_paper) <= 0.35
+    for e in (3, 6):
+        assert abs(ours[e] - np.mean(paper_plain[e])) <= 2.5
+
+
+# --------------------------------------------------------------------------
+# The iterated scheme and kappa_true
+
+@pytest.mark.parametrize("gram", ["f64", "dd"])
+@pytest.mark.parametrize("fact", ["chol", "svqb"])
+def test_iterate_hadamard_stops_after_one_pass(gram, fact):
+    """X orthonormal and orthogonal to Y exactly (Sylvester-Hadamard
+    columns): the first pass finds C = 0 and M = I, so Q = X, R = I and C = 0
+    bit for bit and the stop test holds at once; a test that never holds
+    (eps < 0) runs max_iter passes instead."""
+    Y = synth.hadamard_columns(5, [40, 41, 42, 43])
+    X = synth.hadamard_columns(5, [1, 2, 3])
+    s = oracle.iterate(X, Y, gram=gram, fact=fact, eps=1e-10, max_iter=5)
+    assert s["info"] == 0 and s["passes"] == 1 and s["converged"]
+    assert np.array_equal(s["Q"], X)
+    assert np.array_equal(s["R_hi"], np.eye(3)) and not s["R_lo"].any()
+    assert not s["C_hi"].any()
+    assert s["c_norm"] == 0.0 and s["r_dev"] == 0.0
+    t = oracle.iterate(X, Y, gram=gram, fact=fact, eps=-1.0, max_iter=4)
+    assert t["passes"] == 4 and not t["converged"]
+
+
+@pytest.mark.parametrize("gram,bound", [("dd", 50.0), ("f64", 50.0)])
+def test_iterate_svqb_pass_is_the_polar_factor(gram, bound):
+    """One symmetric-SVQB pass on X = U diag(sigma) V^T returns the polar
+    factor U V^T (closed form of the generator): within ~kappa u with the DD
+    Gram, within ~kappa^2 u with the binary64 one (the Gram matrix's own
+    rounding), and R = V diag(sigma) V^T."""
+    m, k, kappa, seed = 3000, 6, 1e4, 77
+    rng = np.random.default_rng(seed)
+    U = synth.haar(rng, m, k)
+    V = synth.haar(rng, k, k)
+    sig = synth.sigma_logspace(k, kappa)
+    X = (U * sig[None, :]) @ V.T
+    assert np.array_equal(X, synth.svd_matrix(m, k, kappa, seed))
+    s = oracle.iterate(X, gram=gram, fact="svqb", max_iter=1)
+    P = U @ V.T
+    err = np.max(np.abs(s["Q"] - P))
+    lim = bound * (kappa if gram == "dd" else kappa ** 2) * U64
+    assert err <= lim, (err, lim)
+    Rex = (V * sig[None, :]) @ V.T
+    assert np.max(np.abs(s["R_hi"] - Rex)) <= 1e-12
+    # planted mistake: a Cholesky pass is not the polar factor
+    c = oracle.iterate(X, gram=gram, fact="chol", max_iter=1)
+    assert np.max(np.abs(c["Q"] - P)) > 1e-3
+
+
+@pytest.mark.parametrize("fact", ["chol", "svqb"])
+def test_iterate_converges_on_the_runtime_experiment_shape(fact):
+    """X close to span(Y) (kappa(X) = 1e6, kappa(X, Y) = 1e12, the paper's
+    runtime experiment at fewer rows): the passes converge at eps = 1e-10
+    within five passes to an orthonormal Q orthogonal to Y with X = Y C + Q R,
+    and the DD variant needs no more passes than the binary64 one (the
+    paper's point about DD)."""
+    X, Y = synth.projected_pair(20000, 4, 20, 1e6, 1e12, 7100)
+    res = {}
+    for gram in ("f64", "dd"):
+        s = oracle.iterate(X, Y, gram=gram, fact=fact, eps=1e-10, max_iter=8)
+        assert s["info"] == 0 and s["converged"] and s["passes"] <= 5, (gram, s["passes"])
+        met = oracle.metrics(s["Q"], X, s["R_hi"], Y, s["C_hi"])
+        assert met["omega"] <= 1e-14 and met["omega_y"] <= 1e-14, met
+        assert met["rho"] <= (1e-14 if fact == "chol" else 1e-12), met
+        assert s["c_norm"] <= 1e-10 and s["r_dev"] <= 1e-10
+        res[gram] = s["passes"]
+    assert res["dd"] <= res["f64"]
+
+
+def test_kappa_true():
+    """kappa from the exact Gram matrix: the generator's nominal kappa for
+    moderate kappa (U orthonormal to ~1e-15), LAPACK's singular values where
+    they are accurate, and the projected block's kappa with a locked basis."""
+    for kappa in (1e2, 1e6):
+        X = synth.svd_matrix(5000, 8, kappa, 81)
+        kt = oracle.kappa_true(X)
+        assert abs(kt / kappa - 1) <= 1e-8
+        sv = np.linalg.svd(X, compute_uv=False)
+        assert abs(kt / (sv[0] / sv[-1]) - 1) <= 1e-8
+    X, Y = synth.projected_pair(4000, 4, 6, 10.0, 1e8, 82)
+    Xt = X - Y @ (Y.T @ X)
+    sv = np.linalg.svd(Xt, compute_uv=False)
+    assert abs(oracle.kappa_true(X, Y) / (sv[0] / sv[-1]) - 1) <= 1e-6
+
+
 # --------------------------------------------------------------------------
 # Metrics and the split-BF16 model
 
