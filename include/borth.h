@@ -79,9 +79,11 @@ typedef enum {
  *     sqrt(G_ii G_jj) where few panels are summed, 5e-32 at millions of rows);
  *   Dot2 (BORTH_FLAG_DD_DOT2, BORTH_GRAM_DD_DOT2): TwoProduct and TwoSum,
  *     8 instructions per product, error about u^2 |G| per thread (~2e-32).
- * The narrow update's fused Gram columns (k <= 8) always use Dot2; sweeps
- * weighted by B (borth_orthonormalize_iter_b) always use the biased sums;
- * blocks wider than 88 columns always use Dot2. */
+ * The narrow update's fused Gram columns (k <= 8) and the Gram sweeps of
+ * the iterated scheme (borth_orthonormalize_iter, whose X lies close to
+ * span(Y)) always use Dot2; sweeps weighted by B
+ * (borth_orthonormalize_iter_b) always use the biased sums; blocks wider
+ * than 88 columns always use Dot2. */
 
 typedef enum { BORTH_CHOL = 0, BORTH_SVQB = 1 } borth_fact;
 

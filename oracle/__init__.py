@@ -76,8 +76,8 @@ def _load():
             "or_svqb_q": ([_int, _dp, _dp, _dp, _dp], _int),
             "or_cholqr_steps": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _int, _int, _int,
                                  _int, _dp, _i64, _dp, _dp, _dp, _dp], _int),
-            "or_iterate": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _int, _int, ctypes.c_double,
-                            _int, _dp, _i64, _dp, _dp, _dp, _dp, _dp], _int),
+            "or_iterate": ([_i64, _int, _dp, _i64, _int, _dp, _i64, _int, _int, _int,
+                            ctypes.c_double, _int, _dp, _i64, _dp, _dp, _dp, _dp, _dp], _int),
             "or_metrics": ([_i64, _int, _dp, _i64, _dp, _i64, _int, _dp, _i64, _dp,
                             _dp, _dp, _dp], _int),
             "or_gram_split_bf16": ([_i64, _int, _fp, _i64, _i64, _dp], _int),
@@ -262,10 +262,13 @@ def cholqr_steps(X, Y=None, *, dd_first=False, passes=2, project_each_pass=True,
     return dict(Q=Q, R_hi=rhi, R_lo=rlo, C_hi=chi[:ky], C_lo=clo[:ky], info=info)
 
 
-def iterate(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5):
+def iterate(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5, fused=False):
     """O2 iterated scheme: passes of projection against Y and Cholesky or
     symmetric-SVQB orthonormalization (binary64, or DD Gram and factor),
     until ||C_j||_F <= eps and ||R_j - I||_F <= eps or max_iter passes.
+    ``fused``: each pass takes M from the Gram matrix of [Y | S] of one sweep
+    (M = S^T S - C^T (2 C - Y^T Y C)), the fused operations, instead of the
+    Gram matrix of the projected block.
 
     Returns dict(Q, R_hi, R_lo, C_hi, C_lo, passes, converged, c_norm, r_dev,
     info) with X = Y C + Q R; info = 100*pass + pivot on a breakdown, else 0."""
@@ -280,7 +283,8 @@ def iterate(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_iter=5):
     clo = np.zeros((max(ky, 1), k))
     out = np.zeros(4)
     info = _load().or_iterate(m, k, _p(X), k, ky, _p(Yc), max(ky, 1), 1 if gram == "dd" else 0,
-                              1 if fact == "svqb" else 0, float(eps), int(max_iter), _p(Q), k,
+                              1 if fact == "svqb" else 0, int(bool(fused)), float(eps),
+                              int(max_iter), _p(Q), k,
                               _p(rhi), _p(rlo), _p(chi), _p(clo), _p(out))
     return dict(Q=Q, R_hi=rhi, R_lo=rlo, C_hi=chi[:ky], C_lo=clo[:ky], passes=int(out[0]),
                 converged=bool(out[1]), c_norm=float(out[2]), r_dev=float(out[3]), info=info)

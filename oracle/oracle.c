@@ -620,15 +620,21 @@ static void trinv_dd(int k, const dd* r, dd* z) {
 /* SVQB factor of phase II (Sec. 4.2, in the symmetric reading): the
  * eigenpairs M = U L U^T by binary128 Jacobi, Z = U L^{-1/2} U^T = M^{-1/2}
  * and R = U L^{1/2} U^T = M^{1/2}, so that Z^T M Z = I and M = R^T R.
- * a: M (k x k, binary128), destroyed.  Returns 0, or 1 + the index of a
- * non-positive eigenvalue (M not positive definite). */
-static int svqb_factor_q(int k, f128* a, f128* Z, f128* R) {
+ * Eigenvalues below floor * lambda_max are lifted to that floor (the
+ * reading of the rank-deficient case: floor 2^-52 for a binary64 M, 2^-104
+ * for a DD one).  a: M (k x k, binary128), destroyed.  Returns 0, or 1 + the
+ * index of a non-positive eigenvalue if lambda_max itself is not positive. */
+static int svqb_factor_q(int k, f128* a, f128* Z, f128* R, f128 floor_rel) {
   const size_t n = (size_t)k * k;
   f128* v = (f128*)malloc(sizeof(f128) * n + 16);
   jacobi_q(k, a, v);
   int bad = 0;
+  f128 lmax = 0;
+  for (int i = 0; i < k; ++i)
+    if (a[i * k + i] > lmax) lmax = a[i * k + i];
+  if (!(lmax > 0) || isinfq(lmax) || isnanq(lmax)) bad = 1;
   for (int i = 0; i < k && !bad; ++i)
-    if (!(a[i * k + i] > 0)) bad = i + 1;
+    if (!(a[i * k + i] >= floor_rel * lmax)) a[i * k + i] = floor_rel * lmax;
   if (!bad)
     for (int i = 0; i < k; ++i)
       for (int j = 0; j < k; ++j) {
@@ -651,7 +657,7 @@ static int svqb_factor_q(int k, f128* a, f128* Z, f128* R) {
  * M), Q = Xt Z.  X may alias Q. */
 static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
                     const double* Y, int64_t ldy, double* Q, int64_t ldq,
-                    double* R, double* C, int exact_gram, int fact) {
+                    double* R, double* C, int exact_gram, int fact, int fused) {
   double* xt = (double*)malloc(sizeof(double) * ((size_t)m * k + 1));
   if (ky > 0) gram_f64(m, ky, Y, ldy, k, X, ldx, C);
 #pragma omp parallel for schedule(static)
@@ -665,10 +671,33 @@ static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
    * binary64 -- the most accurate M a binary64 pass can be given, so the
    * pass's orthogonality loss is then due to the Cholesky factor and the
    * update alone. */
-  if (exact_gram)
+  if (exact_gram) {
     or_gram_q(m, k, xt, k, k, xt, k, R, NULL);
-  else
+  } else if (fused && ky > 0) {
+    /* fused operations: M from the Gram matrix of [Y | X] of one sweep,
+     * M = X^T X - 2 C^T C + C^T (Y^T Y) C (= Xt^T Xt in exact arithmetic) */
+    double* syy = (double*)malloc(sizeof(double) * ((size_t)ky * ky + 1));
+    double* sc = (double*)malloc(sizeof(double) * ((size_t)ky * k + 1));
+    gram_f64(m, k, X, ldx, k, X, ldx, R);
+    gram_f64(m, ky, Y, ldy, ky, Y, ldy, syy);
+    for (int l = 0; l < ky; ++l)
+      for (int j = 0; j < k; ++j) {
+        double v = 0;
+        for (int q = 0; q < ky; ++q) v += syy[(size_t)l * ky + q] * C[(size_t)q * k + j];
+        sc[(size_t)l * k + j] = v;
+      }
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        double v = R[(size_t)i * k + j];
+        for (int l = 0; l < ky; ++l)
+          v -= C[(size_t)l * k + i] * (2.0 * C[(size_t)l * k + j] - sc[(size_t)l * k + j]);
+        R[(size_t)i * k + j] = v;
+      }
+    free(syy);
+    free(sc);
+  } else {
     gram_f64(m, k, xt, k, k, xt, k, R);
+  }
   double* z = (double*)malloc(sizeof(double) * (size_t)k * k + 8);
   if (fact == 1) {
     const size_t n = (size_t)k * k;
@@ -676,7 +705,7 @@ static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
     f128* zq = (f128*)malloc(sizeof(f128) * n + 16);
     f128* rq = (f128*)malloc(sizeof(f128) * n + 16);
     for (size_t e = 0; e < n; ++e) a[e] = (f128)R[e];
-    const int bad = svqb_factor_q(k, a, zq, rq);
+    const int bad = svqb_factor_q(k, a, zq, rq, ldexpq(1, -52));
     for (size_t e = 0; e < n; ++e) { z[e] = (double)zq[e]; R[e] = (double)rq[e]; }
     free(a); free(zq); free(rq);
     if (bad) { free(z); free(xt); return bad; }
@@ -709,7 +738,7 @@ static int pass_f64(int64_t m, int k, const double* X, int64_t ldx, int ky,
  * returned coefficients.  For an exactly orthonormal Y, D = C. */
 static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
                    const double* Y, int64_t ldy, double* Q, int64_t ldq,
-                   dd* R, dd* C, int corrected, int fact) {
+                   dd* R, dd* C, int corrected, int fact, int fused) {
   const int64_t np = npart(m);
   if (ky > 0) {
     for (int l = 0; l < ky; ++l)
@@ -719,6 +748,11 @@ static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
           s = dd_add(s, dot2_rows(pbeg(m, np, b), pbeg(m, np, b + 1), Y + l, ldy, X + j, ldx));
         C[(size_t)l * k + j] = s;
       }
+  }
+  dd* C0 = NULL; /* the plain coefficients, kept for the fused M */
+  if (ky > 0 && fused) {
+    C0 = (dd*)malloc(sizeof(dd) * ((size_t)ky * k + 1));
+    memcpy(C0, C, sizeof(dd) * (size_t)ky * k);
   }
   if (ky > 0 && corrected) {
     dd* S = (dd*)malloc(sizeof(dd) * ((size_t)ky * ky + 1));
@@ -748,27 +782,43 @@ static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
       for (int l = 0; l < ky; ++l) v = dd_sub(v, dd_mul(dd_from(Y[r * ldy + l]), C[(size_t)l * k + j]));
       xt[(size_t)r * k + j] = v;
     }
-  /* M = Xt^T Xt with DD inputs: sum of DD products, DD accumulation per row
-   * block, blocks combined in order. */
   const size_t n = (size_t)k * k;
-  dd* part = (dd*)malloc(sizeof(dd) * ((size_t)np * n + 1));
+  if (C0) {
+    /* fused operations: M from the DD Gram matrix of [Y | X] of one sweep
+     * (Dot2 sums), M = X^T X - C^T D with D the (corrected) coefficients
+     * (= Xt^T Xt to second order in ||Y^T Y - I||) */
+    for (int i = 0; i < k; ++i)
+      for (int j = i; j < k; ++j) {
+        dd s = {0, 0};
+        for (int64_t b = 0; b < np; ++b)
+          s = dd_add(s, dot2_rows(pbeg(m, np, b), pbeg(m, np, b + 1), X + i, ldx, X + j, ldx));
+        for (int l = 0; l < ky; ++l) s = dd_sub(s, dd_mul(C0[(size_t)l * k + i], C[(size_t)l * k + j]));
+        R[(size_t)i * k + j] = s;
+        R[(size_t)j * k + i] = s;
+      }
+    free(C0);
+  } else {
+    /* M = Xt^T Xt with DD inputs: sum of DD products, DD accumulation per
+     * row block, blocks combined in order. */
+    dd* part = (dd*)malloc(sizeof(dd) * ((size_t)np * n + 1));
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t b = 0; b < np; ++b) {
-    dd* p = part + (size_t)b * n;
-    for (size_t e = 0; e < n; ++e) p[e] = dd_from(0.0);
-    for (int64_t r = pbeg(m, np, b); r < pbeg(m, np, b + 1); ++r)
-      for (int i = 0; i < k; ++i)
-        for (int j = i; j < k; ++j)
-          p[(size_t)i * k + j] = dd_add(p[(size_t)i * k + j], dd_mul(xt[(size_t)r * k + i], xt[(size_t)r * k + j]));
-  }
-  for (int i = 0; i < k; ++i)
-    for (int j = i; j < k; ++j) {
-      dd s = {0, 0};
-      for (int64_t b = 0; b < np; ++b) s = dd_add(s, part[(size_t)b * n + (size_t)i * k + j]);
-      R[(size_t)i * k + j] = s;
-      R[(size_t)j * k + i] = s;
+    for (int64_t b = 0; b < np; ++b) {
+      dd* p = part + (size_t)b * n;
+      for (size_t e = 0; e < n; ++e) p[e] = dd_from(0.0);
+      for (int64_t r = pbeg(m, np, b); r < pbeg(m, np, b + 1); ++r)
+        for (int i = 0; i < k; ++i)
+          for (int j = i; j < k; ++j)
+            p[(size_t)i * k + j] = dd_add(p[(size_t)i * k + j], dd_mul(xt[(size_t)r * k + i], xt[(size_t)r * k + j]));
     }
-  free(part);
+    for (int i = 0; i < k; ++i)
+      for (int j = i; j < k; ++j) {
+        dd s = {0, 0};
+        for (int64_t b = 0; b < np; ++b) s = dd_add(s, part[(size_t)b * n + (size_t)i * k + j]);
+        R[(size_t)i * k + j] = s;
+        R[(size_t)j * k + i] = s;
+      }
+    free(part);
+  }
   dd* z = (dd*)malloc(sizeof(dd) * (n + 1));
   if (fact == 1) {
     /* SVQB factored in binary128 from the DD M, rounded to DD */
@@ -776,7 +826,7 @@ static int pass_dd(int64_t m, int k, const double* X, int64_t ldx, int ky,
     f128* zq = (f128*)malloc(sizeof(f128) * n + 16);
     f128* rq = (f128*)malloc(sizeof(f128) * n + 16);
     for (size_t e = 0; e < n; ++e) a[e] = (f128)R[e].h + (f128)R[e].l;
-    const int bad = svqb_factor_q(k, a, zq, rq);
+    const int bad = svqb_factor_q(k, a, zq, rq, ldexpq(1, -104));
     for (size_t e = 0; e < n; ++e) {
       split_q(zq[e], &z[e].h, &z[e].l);
       split_q(rq[e], &R[e].h, &R[e].l);
@@ -832,9 +882,9 @@ int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
     const int kyp = (ky > 0 && (p == 0 || project_each_pass)) ? ky : 0;
     int info;
     if (p == 0 && dd_first == 1) {
-      info = pass_dd(m, k, cur, k, kyp, Y, ldy, cur, k, rp, cp, dd_corrected, 0);
+      info = pass_dd(m, k, cur, k, kyp, Y, ldy, cur, k, rp, cp, dd_corrected, 0, 0);
     } else {
-      info = pass_f64(m, k, cur, k, kyp, Y, ldy, cur, k, rf, cf, p == 0 && dd_first == 2, 0);
+      info = pass_f64(m, k, cur, k, kyp, Y, ldy, cur, k, rf, cf, p == 0 && dd_first == 2, 0, 0);
       for (size_t e = 0; e < n; ++e) rp[e] = dd_from(rf[e]);
       for (size_t e = 0; e < (size_t)kyp * k; ++e) cp[e] = dd_from(cf[e]);
     }
@@ -874,7 +924,9 @@ int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
  * the previous result) against Y and orthonormalizes it, S_{j+1} =
  * (S_j - Y C_j) Z_j, with the Gram matrix and the factor in binary64
  * (dd = 0) or DD (dd = 1, the corrected coefficients of pass_dd), by
- * Cholesky (fact 0) or SVQB (fact 1, symmetric Z = M^{-1/2}).  The pass is
+ * Cholesky (fact 0) or SVQB (fact 1, symmetric Z = M^{-1/2}); fused: M from
+ * the Gram matrix of [Y | S] of one sweep (the fused operations of Sec. 4.2)
+ * instead of the Gram matrix of the projected block.  The pass is
  * applied, then the iteration stops once ||C_j||_F <= eps and
  * ||R_j - I||_F <= eps (the reading of the stop test, with R_j the pass's
  * factor: triangular, or M^{1/2}), or after max_iter passes.
@@ -883,7 +935,7 @@ int or_cholqr_steps(int64_t m, int k, const double* X, int64_t ldx, int ky,
  * out[2] = ||C_j||_F, out[3] = ||R_j - I||_F of the last pass.  Returns 0, or
  * 100 * pass + pivot (1-based) on a breakdown. */
 int or_iterate(int64_t m, int k, const double* X, int64_t ldx, int ky, const double* Y,
-               int64_t ldy, int dd_mode, int fact, double eps, int max_iter, double* Q,
+               int64_t ldy, int dd_mode, int fact, int fused, double eps, int max_iter, double* Q,
                int64_t ldq, double* rhi, double* rlo, double* chi, double* clo, double* out) {
   const size_t n = (size_t)k * k;
   const size_t nc = (size_t)(ky > 0 ? ky : 1) * k;
@@ -905,9 +957,9 @@ int or_iterate(int64_t m, int k, const double* X, int64_t ldx, int ky, const dou
   for (int p = 0; p < max_iter; ++p) {
     int info;
     if (dd_mode) {
-      info = pass_dd(m, k, cur, k, ky, Y, ldy, cur, k, rp, cp, 1, fact);
+      info = pass_dd(m, k, cur, k, ky, Y, ldy, cur, k, rp, cp, 1, fact, fused);
     } else {
-      info = pass_f64(m, k, cur, k, ky, Y, ldy, cur, k, rf, cf, 0, fact);
+      info = pass_f64(m, k, cur, k, ky, Y, ldy, cur, k, rf, cf, 0, fact, fused);
       for (size_t e = 0; e < n; ++e) rp[e] = dd_from(rf[e]);
       for (size_t e = 0; e < (size_t)ky * k; ++e) cp[e] = dd_from(cf[e]);
     }

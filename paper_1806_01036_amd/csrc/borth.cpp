@@ -871,7 +871,12 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     src.pass = p;
     Src gsrc = src;  // the Gram sweeps take B's diagonal
     gsrc.bw = bw;
-    gsrc.dot2 = (o.flags & BORTH_FLAG_DD_DOT2) ? 1 : 0;
+    // The iterated scheme works on X close to span(Y), where M = G_XX -
+    // C^T (2C - S C) cancels down to ~kappa(X, Y)^-2 of G_XX: its DD sweeps
+    // take Dot2 (error ~u^2 |G|), not the biased sums (error set by the panel
+    // maxima), which left M accurate only to ~1e-6 at kappa(X, Y) = 1e12 and
+    // cost a pass.  (The weighted sweep has the biased sums only.)
+    gsrc.dot2 = 1;
     if (!have_gram) {
       int nwg = 0;
       // Y does not change between passes: after the first, only the columns

@@ -34,17 +34,39 @@ def test_iterated_scheme_converges(k, ky, gram, fact, kxy):
     assert met["omega_y"] <= 1e-14
     o1 = oracle.qr_q(X, Y)
     assert np.max(np.abs(host(C) - o1["C"])) <= 1e-13
-    # the oracle's iterated scheme (same precision, factor and stop test)
-    # takes as many passes and reaches the same Q: the Cholesky and the
-    # symmetric SVQB results are unique, so they agree elementwise to within
-    # ~kappa u of the projected block (kappa from its exact Gram matrix)
-    o2 = oracle.iterate(X, Y, gram=gram, fact=fact, eps=1e-10, max_iter=8)
-    kt = oracle.kappa_true(X, Y)
-    dq = np.max(np.abs(host(Q) - o2["Q"]))
-    note("  oracle passes", o2["passes"], "gpu", it.passes_run, "kappa_true", kt, "max |dQ|", dq)
+    # The oracle's iterated scheme with the same steps: the same precision,
+    # factor and stop test, and M from the Gram matrix of [Y | S] of one
+    # sweep (the fused operations; its cancellation near span(Y) sets how
+    # good the first pass is and so the number of passes).  The pass counts
+    # agree unless a stop-test norm sits within a decade of eps at the pass
+    # where they part.  kappa(X, Y) = ||X||_2 / sigma_min(Xt) is the paper's
+    # kappa(X, W) (sigma_min from the exact Gram matrix of Xt via kappa_true).
+    o2 = oracle.iterate(X, Y, gram=gram, fact=fact, eps=1e-10, max_iter=8, fused=True)
+    Xt = X - Y @ (Y.T @ X)
+    kxy = np.linalg.norm(X, 2) * oracle.kappa_true(X, Y) / np.linalg.norm(Xt, 2)
+    Qg = host(Q)
+    dq = np.max(np.abs(Qg - o2["Q"]))
+    sin_max = np.linalg.norm(Qg - o2["Q"] @ (o2["Q"].T @ Qg), 2)  # largest principal angle
+    note("  oracle passes", o2["passes"], "gpu", it.passes_run, "kappa(X, Y)", kxy, "max |dQ|", dq,
+         "sin angle", sin_max)
     assert o2["info"] == 0 and o2["converged"]
-    assert it.passes_run == o2["passes"]
-    assert dq <= 100 * kt * U64
+    if it.passes_run != o2["passes"]:
+        p = min(it.passes_run, o2["passes"])
+        ob = oracle.iterate(X, Y, gram=gram, fact=fact, eps=1e-10, max_iter=p, fused=True)
+        worst = max(ob["c_norm"], ob["r_dev"])
+        note("  pass counts differ; oracle norms at pass", p, ob["c_norm"], ob["r_dev"])
+        assert abs(it.passes_run - o2["passes"]) == 1 and 1e-11 <= worst <= 1e-9
+    if gram == "f64" and fact == "svqb" and kxy ** 2 * U64 > 1e-6:
+        # binary64 symmetric SVQB near span(Y): the first pass's M is
+        # dominated by cancellation, the later passes' symmetric transforms
+        # multiply to a non-symmetric one, and the result is another
+        # orthonormal basis of the same span, known to ~u kappa(X, Y)
+        assert sin_max <= 100 * kxy * U64
+    else:
+        # the thin QR factor is unique, and so is the symmetric SVQB result
+        # when M is accurate: the same Q to the ~u kappa(X, Y) a binary64
+        # projection leaves in Xt
+        assert dq <= 100 * kxy * U64
     m2 = oracle.metrics(o2["Q"], X, o2["R_hi"] + o2["R_lo"], Y, o2["C_hi"] + o2["C_lo"])
     assert m2["omega_y"] <= 1e-14 and m2["omega"] <= 1e-14
 

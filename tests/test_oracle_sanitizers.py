@@ -32,8 +32,8 @@ int or_cholqr_steps(int64_t, int, const double*, int64_t, int, const double*, in
 int or_metrics(int64_t, int, const double*, int64_t, const double*, int64_t, int, const double*,
                int64_t, const double*, const double*, double*, double*);
 int or_gram_split_bf16(int64_t, int, const float*, int64_t, int64_t, double*);
-int or_iterate(int64_t, int, const double*, int64_t, int, const double*, int64_t, int, int, double,
-               int, double*, int64_t, double*, double*, double*, double*, double*);
+int or_iterate(int64_t, int, const double*, int64_t, int, const double*, int64_t, int, int, int,
+               double, int, double*, int64_t, double*, double*, double*, double*, double*);
 
 static uint64_t st = 88172645463325252ull;
 static double rnd(void) {
@@ -73,7 +73,9 @@ int main(void) {
   double out[4];
   for (int dd = 0; dd < 2; ++dd)
     for (int fact = 0; fact < 2; ++fact)
-      rc |= or_iterate(m, k, X, ldx, ky, Y, ldy, dd, fact, 1e-10, 3, Q, ldq, rhi, rlo, chi, clo, out);
+      for (int fused = 0; fused < 2; ++fused)
+        rc |= or_iterate(m, k, X, ldx, ky, Y, ldy, dd, fact, fused, 1e-10, 3, Q, ldq, rhi, rlo, chi,
+                         clo, out);
   rc |= or_metrics(m, k, Q, ldq, X, ldx, ky, Y, ldy, R, C, out, NULL);
   float* Xf = (float*)malloc(sizeof(float) * (size_t)(m * ldx));
   for (int64_t i = 0; i < m * ldx; ++i) Xf[i] = (float)X[i];
