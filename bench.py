@@ -8,9 +8,11 @@ path on device-resident input: DD Gram sweep, DD k x k Cholesky, update sweep
 with the fused binary64 Gram of Q_1, binary64 Cholesky, final update sweep.
 
 value = algorithmic bytes / time (CholQR2: 32 m k bytes per step), counted
-only if ||Q^T Q - I||_F <= 1e-14 (checked after the timed region with the
-library's DD Gram of Q).  The plain binary64 CholQR on the same input is
-timed beside it (its GB/s and time ratio are reported; it does not reach the
+only if ||Q^T Q - I||_F <= 1e-14 and the residual <= 1e-14, both measured
+after the timed region by the CPU oracle (binary128-accurate measures of the
+binary64 Q and R; with --no-cpu the library's DD Gram of Q stands in, and
+the line says so).  The plain binary64 CholQR on the same input is timed
+beside it (its GB/s and time ratio are reported; it does not reach the
 orthogonality gate at this kappa).
 
 Other workloads (--workload): c2 (binary64 CholQR2, 1e7 x k), c4 (fp32
@@ -37,23 +39,30 @@ FP64_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP64 lane-ops per second (39.3 T
 # accumulation's fma, exact difference, fma for the remainder and add (its
 # once-per-panel fold and the padding of diagonal tiles are overhead).
 DD_GRAM_OPS = 4.0
+# The same work counted as a Dot2 step (TwoProduct + TwoSum and the error
+# accumulation, about 10 binary64 instructions per product): the count the
+# measurement plan prices a DD Gram at.  A fraction against it can exceed 1,
+# as the biased sums need fewer instructions for the same accuracy.
+DD_GRAM_OPS_DOT2 = 10.0
 
 # HBM bytes per dispatch of the dominant kernel of the default workload, from
 # two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; calibrated on a plain
 # device copy of known size, see profiles/dd_cholqr2_4Mx32_hbm_counters.md).
 # Valid only for the kernel sources they were taken on: reported as null once
 # those sources change.
-DD_GRAM_TRAFFIC = {"bytes": 1.0337e9,
+DD_GRAM_TRAFFIC = {"bytes": None, "lane_ops": None,
                    "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
-                   "sha256": "f82c05898bbd52adf5d908b1486ad6e1b0a0f8561e5d70cca29d05fe40e67c98"}
+                   "sha256": None}
 
 
-def measured_traffic(rec):
+def measured_traffic(rec, key="bytes"):
     import hashlib
+    if rec.get("sha256") is None:
+        return None
     h = hashlib.sha256()
     for f in rec["sources"]:
         h.update((ROOT / "paper_1806_01036_amd" / "csrc" / f).read_bytes())
-    return rec["bytes"] if h.hexdigest() == rec["sha256"] else None
+    return rec[key] if h.hexdigest() == rec["sha256"] else None
 
 
 def log(*a):
@@ -109,6 +118,43 @@ def cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def oracle_metrics(X, Q, R):
+    """omega and rho of the GPU's result by the CPU oracle (binary128-
+    accurate measures), and the seconds they took."""
+    import oracle
+    t0 = time.perf_counter()
+    met = oracle.metrics(Q.cpu().numpy(), X, R.cpu().numpy())
+    return float(met["omega"]), float(met["rho"]), time.perf_counter() - t0
+
+
+def cpu_baseline_extra(X, dd, rows1=500_000, rows_q=250_000):
+    """The oracle's DD CholQR2 at one thread, and its binary128 thin QR (O1),
+    each on the first rows of X, in GB/s of the same algorithmic bytes."""
+    import oracle
+    k = X.shape[1]
+    nthr = oracle.num_threads()
+    out = {}
+    try:
+        oracle.set_num_threads(1)
+        r = min(rows1, X.shape[0])
+        t0 = time.perf_counter()
+        oracle.cholqr_steps(X[:r], dd_first=dd, passes=2)
+        dt = time.perf_counter() - t0
+        out["one_thread"] = dict(value=32.0 * r * k / dt / 1e9, unit="GB/s", cores=1,
+                                 sample=f"oracle step-by-step {'DD' if dd else 'binary64'} CholQR2, "
+                                        f"first {r} rows, 1 thread ({dt:.1f} s)")
+    finally:
+        oracle.set_num_threads(nthr)
+    r = min(rows_q, X.shape[0])
+    t0 = time.perf_counter()
+    oracle.qr_q(X[:r])
+    dt = time.perf_counter() - t0
+    out["o1_binary128_qr"] = dict(value=24.0 * r * k / dt / 1e9, unit="GB/s", cores=nthr,
+                                  sample=f"oracle exact thin QR in binary128 (Gram, Cholesky, "
+                                         f"update; 24 m k bytes), first {r} rows ({dt:.1f} s)")
+    return out
 
 
 def cpu_baseline_cholqr2(X, dd, target_s=10.0):
@@ -172,9 +218,14 @@ def run_c3(args, torch, borth, synth):
     upd_ms, upd_n = ctx.kernel_time(1)
     ctx.set_profiling(False)
     per_step = step_stats(torch, step)
-    om = omega_dd(borth, Q)
-    rho = rho_gpu(torch, Xd, Q, R)
-    log(f"DD CholQR2: {t*1e3:.3f} ms/step omega={om:.2e} rho={rho:.2e} "
+    om_dd = omega_dd(borth, Q)
+    rho_dd = rho_gpu(torch, Xd, Q, R)
+    if args.no_cpu:
+        om, rho, gate = om_dd, rho_dd, "library DD Gram of Q (--no-cpu)"
+    else:
+        om, rho, t_met = oracle_metrics(X, Q, R)
+        gate = f"CPU oracle, binary128-accurate measures ({t_met:.1f} s)"
+    log(f"DD CholQR2: {t*1e3:.3f} ms/step omega={om:.2e} rho={rho:.2e} ({gate}) "
         f"gram {gram_ms:.3f} ms x{gram_n}, update {upd_ms:.3f} ms x{upd_n}")
 
     # plain binary64 CholQR on the same input
@@ -192,20 +243,21 @@ def run_c3(args, torch, borth, synth):
                              ctx=ctx)
     tf2 = timed(torch, step_f2, args.steps, args.warmup)
 
-    # streaming probes on the same X: a plain read (torch's sum reduction,
-    # 8 m k bytes) and a plain copy (8 m k read + 8 m k written)
-    acc = torch.empty((), dtype=torch.float64, device="cuda")
-    t_read = timed(torch, lambda: torch.sum(Xd, dim=(0, 1), out=acc), 20, 5)
-    t_copy = timed(torch, lambda: Qp.copy_(Xd), 20, 5)
-    read_gbs = 8.0 * m * k / t_read / 1e9
-    copy_gbs = 16.0 * m * k / t_copy / 1e9
+    # streaming probes on the same X (the library's plain HIP kernels): a
+    # read of 8 m k bytes, a copy (8 m k read + 8 m k written) with ordinary
+    # and with non-temporal stores
+    _, read_gbs, _ = borth.stream_probe("read", Xd, Qp, reps=10, ctx=ctx)
+    _, copy_gbs, _ = borth.stream_probe("copy", Xd, Qp, reps=10, ctx=ctx)
+    _, copynt_gbs, _ = borth.stream_probe("copy_nt", Xd, Qp, reps=10, ctx=ctx)
 
     bytes_step = 32.0 * m * k
-    gbs = bytes_step / t / 1e9 if om <= 1e-14 else 0.0
+    gbs = bytes_step / t / 1e9 if (om <= 1e-14 and rho <= 1e-14) else 0.0
     # dominant kernel: the DD Gram sweep, bound by the FP64 vector ALUs.
     # Algorithmic work: DD_GRAM_OPS FP64 VALU lane-ops per (i <= j) pair per row.
-    ops = DD_GRAM_OPS * k * (k + 1) / 2 * m
+    pairs = k * (k + 1) / 2 * m
+    ops = DD_GRAM_OPS * pairs
     achieved = ops / (gram_ms * 1e-3) / 1e12
+    executed = measured_traffic(DD_GRAM_TRAFFIC, "lane_ops")
     out = {
         "metric": "block-orth GB/s (% HBM peak) at ||Q^T Q - I|| <= 1e-14: DD/split vs plain FP64 CholQR",
         "value": round(gbs, 2),
@@ -224,10 +276,14 @@ def run_c3(args, torch, borth, synth):
                    "m": m, "k": k, "kappa": kappa, "passes": 2, "gram": "dd"},
         "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
         "step_ms": per_step,
-        "stream_probe": {"read_GBs": round(read_gbs, 1), "copy_GBs": round(copy_gbs, 1),
+        "stream_probe": {"kernel": "borth_stream_probe (hand-written HIP, 16-byte vectors)",
+                         "read_GBs": round(read_gbs, 1), "copy_GBs": round(copy_gbs, 1),
+                         "copy_nt_GBs": round(copynt_gbs, 1),
                          "value_over_read_probe": round(gbs / read_gbs, 4)},
         "omega": om,
         "rho": rho,
+        "gate": gate,
+        "omega_dd_gram": om_dd,
         "plain_fp64_cholqr": {"ms_per_step": round(tp * 1e3, 4),
                               "GB/s": round(24.0 * m * k / tp / 1e9, 2),
                               "status": infp.status,
@@ -235,13 +291,19 @@ def run_c3(args, torch, borth, synth):
         "fp64_cholqr2_ms_per_step": round(tf2 * 1e3, 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VALU_TOPS,
                      "unit": "Tops/s (FP64 VALU lane-ops)", "frac": round(achieved / FP64_VALU_TOPS, 4),
+                     "work": "4 lane-ops per (i <= j) pair and row (the biased DD sums)",
+                     "frac_dot2_count": round(DD_GRAM_OPS_DOT2 * pairs / (gram_ms * 1e-3) / 1e12
+                                              / FP64_VALU_TOPS, 4),
+                     "frac_executed": (round(executed / (gram_ms * 1e-3) / 1e12 / FP64_VALU_TOPS, 4)
+                                       if executed else None),
                      "traffic": measured_traffic(DD_GRAM_TRAFFIC),
                      "traffic_unit": "bytes per launch (algorithmic 8 m k = %d)" % (8 * m * k),
-                     "kernel": "gram_tiles_kernel<DD>",
+                     "kernel": "gram_dd_dma_kernel",
                      "kernel_ms": round(gram_ms, 4)},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_cholqr2(X, dd=True)
+        out["cpu_baseline"].update(cpu_baseline_extra(X, dd=True))
     return out
 
 
@@ -255,19 +317,30 @@ def run_c1(args, torch, borth, synth):
     R = torch.empty((k, k), dtype=torch.float64, device="cuda")
     ctx = borth.default_context()
     res = {}
+    # one pass of plain CholQR loses c kappa^2 u of orthogonality: the
+    # per-stage gate is omega <= 100 kappa^2 u and rho <= 1e-14
+    kappa = 1e4
+    om_gate = 100.0 * kappa ** 2 * 2.0 ** -53
     for graph in (False, True):
         def step():
             borth.orthonormalize(Xd, gram="f64", passes=1, graph=graph, out=Q, R=R, sync=False,
                                  ctx=ctx)
         steps = max(args.steps, 200)
         t = timed(torch, step, steps, max(args.warmup, 20))
-        om = omega_dd(borth, Q)
-        res["graph" if graph else "eager"] = dict(us=t * 1e6, GBs=24.0 * m * k / t / 1e9, omega=om)
+        if args.no_cpu:
+            om, rho = omega_dd(borth, Q), rho_gpu(torch, Xd, Q, R)
+        else:
+            om, rho, _ = oracle_metrics(X, Q, R)
+        res["graph" if graph else "eager"] = dict(us=t * 1e6, GBs=24.0 * m * k / t / 1e9, omega=om,
+                                                  rho=rho)
         log("graph" if graph else "eager", res["graph" if graph else "eager"])
     r = res["graph"]
+    ok = r["omega"] <= om_gate and r["rho"] <= 1e-14
     return {
         "metric": "block-orth GB/s (% HBM peak) at ||Q^T Q - I|| <= 1e-14: DD/split vs plain FP64 CholQR",
-        "value": round(r["GBs"] if r["omega"] <= 1e-14 else 0.0, 3), "unit": "GB/s", "n_gpus": 1,
+        "value": round(r["GBs"] if ok else 0.0, 3), "unit": "GB/s", "n_gpus": 1,
+        "gate": f"one plain CholQR pass: omega <= 100 kappa^2 u = {om_gate:.2e}, rho <= 1e-14"
+                + (" (library DD Gram, --no-cpu)" if args.no_cpu else " (CPU oracle)"),
         "steps": max(args.steps, 200), "warmup": max(args.warmup, 20),
         "ms_per_step": round(r["us"] * 1e-3, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -350,7 +423,7 @@ def run_c5(args, torch, borth, synth):
     """256 independent blocks (rows uniform in [1e4, 1e6], widths {8, 16, 32,
     64}, kappa log-uniform in [1e3, 1e10], a 16-column locked basis each):
     projection + DD-Gram CholQR2 (P,C,P,C) of all blocks per step, one graph
-    launch, launch shapes from the autotuner."""
+    launch."""
     nb = args.blocks
     table = synth.batch_table(nb, seed=5000)
     ky = 16
