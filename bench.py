@@ -50,9 +50,9 @@ DD_GRAM_OPS_DOT2 = 10.0
 # device copy of known size, see profiles/dd_cholqr2_4Mx32_hbm_counters.md).
 # Valid only for the kernel sources they were taken on: reported as null once
 # those sources change.
-DD_GRAM_TRAFFIC = {"bytes": None, "lane_ops": None,
+DD_GRAM_TRAFFIC = {"bytes": 1.0337e9, "lane_ops": 10229489664,
                    "sources": ["gram.hip", "dd.hpp", "internal.hpp"],
-                   "sha256": None}
+                   "sha256": "270c9a63183ca0866cd2876491be9668ac6ffdf9804cdd985ad02fd9cff423d1"}
 
 
 def measured_traffic(rec, key="bytes"):
@@ -249,6 +249,10 @@ def run_c3(args, torch, borth, synth):
     _, read_gbs, _ = borth.stream_probe("read", Xd, Qp, reps=10, ctx=ctx)
     _, copy_gbs, _ = borth.stream_probe("copy", Xd, Qp, reps=10, ctx=ctx)
     _, copynt_gbs, _ = borth.stream_probe("copy_nt", Xd, Qp, reps=10, ctx=ctx)
+    # FP64 vector-ALU probe (register-only chains): the issue ceiling the DD
+    # Gram sweep is bound by, plain FMAs and the DD step's fma/add/fma/add
+    fma_rate, fma_waves = borth.valu_probe("fma", Qp, ctx=ctx)
+    dd_rate, dd_waves = borth.valu_probe("dd_step", Qp, ctx=ctx)
 
     bytes_step = 32.0 * m * k
     gbs = bytes_step / t / 1e9 if (om <= 1e-14 and rho <= 1e-14) else 0.0
@@ -280,6 +284,10 @@ def run_c3(args, torch, borth, synth):
                          "read_GBs": round(read_gbs, 1), "copy_GBs": round(copy_gbs, 1),
                          "copy_nt_GBs": round(copynt_gbs, 1),
                          "value_over_read_probe": round(gbs / read_gbs, 4)},
+        "valu_probe": {"kernel": "borth_valu_probe (hand-written HIP, register-only FP64 chains)",
+                       "fma_Tops": round(fma_rate / 1e12, 2), "fma_waves_per_simd": fma_waves,
+                       "dd_step_Tops": round(dd_rate / 1e12, 2), "dd_step_waves_per_simd": dd_waves,
+                       "unit": "T FP64 VALU lane-ops/s"},
         "omega": om,
         "rho": rho,
         "gate": gate,
@@ -296,6 +304,7 @@ def run_c3(args, torch, borth, synth):
                                               / FP64_VALU_TOPS, 4),
                      "frac_executed": (round(executed / (gram_ms * 1e-3) / 1e12 / FP64_VALU_TOPS, 4)
                                        if executed else None),
+                     "frac_of_fma_probe": round(achieved * 1e12 / fma_rate, 4),
                      "traffic": measured_traffic(DD_GRAM_TRAFFIC),
                      "traffic_unit": "bytes per launch (algorithmic 8 m k = %d)" % (8 * m * k),
                      "kernel": "gram_dd_dma_kernel",

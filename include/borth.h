@@ -370,6 +370,20 @@ borth_status borth_kernel_time(borth_ctx ctx, int kind, double* avg_ms, int* cou
 borth_status borth_stream_probe(borth_ctx ctx, int kind, const void* src, void* dst,
                                 int64_t nbytes, int reps, double* best_ms, int* best_grid);
 
+/* Measurement helper (not part of the method): the FP64 vector-ALU rate a
+ * register-only kernel reaches on this device, the yardstick of the DD Gram
+ * sweep, which is bound by FP64 VALU issue.  Each thread runs chains over 16
+ * independent binary64 sums held in registers, with no memory traffic in
+ * the loop: kind 0 plain FMAs, kind 1 the biased DD step of the Gram sweep
+ * (fma, add, fma, add per product).  Launches of 1, 2, 4 and 8 waves per
+ * SIMD are timed with HIP events (three each, after a warm-up launch) and
+ * the fastest is returned: *lane_ops_per_s the FP64 lane operations per
+ * second, *waves (may be NULL) its waves per SIMD.  sink: device, 8-byte
+ * aligned, nbytes >= 8 x 256 x 8 bytes per compute unit (the sums are
+ * written there so that nothing is elided); the call synchronizes. */
+borth_status borth_valu_probe(borth_ctx ctx, int kind, void* sink, int64_t nbytes,
+                              double* lane_ops_per_s, int* waves);
+
 #ifdef __cplusplus
 }
 #endif

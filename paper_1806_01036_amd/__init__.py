@@ -19,7 +19,7 @@ from . import _lib
 
 __all__ = [
     "BorthError", "Breakdown", "Context", "Info", "default_context", "gram", "factor",
-    "update", "orthonormalize", "orthonormalize_noalloc", "orthonormalize_dd", "stream_probe",
+    "update", "orthonormalize", "orthonormalize_noalloc", "orthonormalize_dd", "stream_probe", "valu_probe",
     "orthonormalize_iter",
     "batch_orthonormalize", "GRAM", "FACT",
     "SCHED",
@@ -330,6 +330,23 @@ def stream_probe(kind, src, dst, nbytes=None, reps=10, ctx=None):
                                          ctypes.byref(ms), ctypes.byref(grid)))
     moved = n * (1 if k == 0 else 2)
     return ms.value, moved / (ms.value * 1e-3) / 1e9, grid.value
+
+
+def valu_probe(kind, sink, ctx=None):
+    """FP64 vector-ALU probe (borth_valu_probe): kind "fma" (plain FMA
+    chains) or "dd_step" (the DD Gram's fma, add, fma, add step) in registers,
+    on the device tensor ``sink`` (at least 8 x 256 doubles per compute unit).
+    Returns (FP64 lane operations per second, waves per SIMD of the fastest
+    launch)."""
+    ctx = ctx or default_context(sink.device.index)
+    k = {"fma": 0, "dd_step": 1}[kind]
+    if not sink.is_cuda:
+        raise ArgumentError("valu_probe: sink must be a device tensor")
+    rate = ctypes.c_double()
+    waves = ctypes.c_int()
+    ctx.check(ctx.lib.borth_valu_probe(ctx.h, k, _ptr(sink), sink.numel() * sink.element_size(),
+                                       ctypes.byref(rate), ctypes.byref(waves)))
+    return rate.value, waves.value
 
 
 def orthonormalize_noalloc(X, Y=None, *, gram="dd", fact="chol", passes=2, sched="auto",

@@ -59,6 +59,8 @@ EXPORTS = {
                               ctypes.POINTER(borth_info)], _int),
     "borth_stream_probe": ([_vp, _int, _vp, _vp, _i64, _int, ctypes.POINTER(_dbl),
                             ctypes.POINTER(_int)], _int),
+    "borth_valu_probe": ([_vp, _int, _vp, _i64, ctypes.POINTER(_dbl), ctypes.POINTER(_int)],
+                          _int),
     "borth_orthonormalize_noalloc": ([_vp, _i64, _int, _int, _vp, _i64, _vp, _i64, _int, _vp,
                                       _i64, _vp, _vp, ctypes.POINTER(borth_opts),
                                       ctypes.POINTER(borth_info)], _int),

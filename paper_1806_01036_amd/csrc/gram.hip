@@ -1,24 +1,30 @@
 // Gram sweeps (TSMTTSM): G = V^T V for the tall-skinny V = [Y | X].
 //
-// The Gram matrix is where Sec. 4.2 places most of the orthogonalization's work
-// (Sec. 4.2); for a few columns it is bound by the HBM stream.  Three
+// The Gram matrix is where most of the orthogonalization's work lies
+// (Sec. 4.2); for a few columns it is bound by the HBM stream.  Four
 // kernels, all writing per-workgroup partials in one shared layout (4x4
 // tiles of the upper triangle, see GramLayout) that a fixed-order reduction
 // turns into G:
 //
-//  gram_mfma_kernel   binary64 on the matrix cores, v_mfma_f64_16x16x4:
-//                     each wave streams 4-row groups straight from HBM into
-//                     registers; lane l holds V[r0 + l/16][16 I + l%16], which
-//                     is both the A operand of tile row I and the B operand of
-//                     tile column I, so a 16x16 tile of G costs one MFMA per
-//                     4 rows and no LDS traffic.
-//  gram_tiles_kernel  binary64 or double-double on the vector ALUs: row panels
-//                     are staged in LDS with coalesced loads, each thread owns
-//                     a 4x4 tile of G (and a row phase) and accumulates it;
-//                     the DD variant uses the 8-instruction Dot2 step (dd.hpp).
-//  reduce_kernel      sums the partials in workgroup order (DD additions in DD
-//                     mode) -- no floating-point atomics, so every result is
-//                     bitwise reproducible.
+//  gram_mfma_kernel    binary64 on the matrix cores, v_mfma_f64_16x16x4:
+//                      each wave streams 4-row groups straight from HBM into
+//                      registers; lane l holds V[r0 + l/16][16 I + l%16],
+//                      which is both the A operand of tile row I and the B
+//                      operand of tile column I, so a 16x16 tile of G costs
+//                      one MFMA per 4 rows and no LDS traffic.
+//  gram_tiles_kernel   binary64 or double-double on the vector ALUs: row
+//                      panels are staged in LDS with coalesced loads, each
+//                      thread owns a 4x4 tile of G (and a row phase) and
+//                      accumulates it.  DD runs the 4-instruction biased
+//                      error-free sum (each panel summed on a power-of-two
+//                      bias and folded into a DD total), or on request the
+//                      8-instruction Dot2 step (dd.hpp).
+//  gram_dd_dma_kernel  the biased DD sum with its row panels copied from HBM
+//                      straight into LDS (gfx950 global_load_lds_dwordx4);
+//                      the default DD sweep for 16-byte aligned binary64 rows.
+//  reduce_kernel       sums the partials in workgroup order (DD additions in
+//                      DD mode) -- no floating-point atomics, so every result
+//                      is bitwise reproducible.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -386,20 +392,25 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
 // it.  That frees the registers the register-staged kernel spent on its
 // prefetch and lets a panel be two to three times taller, so the fold, the
 // bias set-up and the barriers are paid over more rows.  The panel's load
-// latency is covered by the other workgroup resident on the compute unit.
+// latency is covered by the other workgroup resident on the compute unit
+// (a second buffer per workgroup would halve the panel height within the
+// same LDS, and the extra folds cost more than the overlap gains).
 //
-// Per panel: transfer (each wave issues its share of the chunks, waits for
-// them) -> barrier -> rows past m zeroed, column maxima into LDS -> barrier
-// -> tile sums on the bias, fold -> barrier.  The LDS row stride is Wp + 2
-// doubles (Wp / 2 + 1 chunks); the chunk after a row's Wp columns, and the
-// chunks of the padding columns between Y and X or after X, are filled with
-// a copy of a valid chunk of that row: they are read only into products that
-// land in padded Gram entries, which the reduction drops.
+// Per panel: transfer (each wave issues its share of the chunks) while the
+// previous panel's sums are folded -> wait, barrier -> rows past m zeroed,
+// column maxima into LDS -> barrier -> tile sums on the bias -> barrier.
+// The LDS row stride is Wp + 2 doubles (Wp / 2 + 1 chunks); the chunk after
+// a row's Wp columns, and the chunks of the padding columns between Y and X
+// or after X, are filled with a copy of a valid chunk of that row: they are
+// read only into products that land in padded Gram entries, which the
+// reduction drops.
 //
 // Needs 16-byte aligned rows: X and Y 16-byte aligned, even ldx, ldy, ky and
 // k, binary64, no weights (host check gram_dma_ok).  HASY: the sweep has Y
-// columns (ky > 0), so a chunk's source may be either matrix.
-template <bool BATCH, bool HASY>
+// columns (ky > 0), so a chunk's source may be either matrix.  WPC > 0: the
+// padded width is WPC and the row phases 256 / ntiles (checked on the host),
+// so that the LDS offsets of a loop trip are immediates.
+template <bool BATCH, bool HASY, int WPC>
 __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
                                                              const GramSeg* __restrict__ tab,
                                                              const int* __restrict__ wg2seg) {
@@ -410,14 +421,17 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   const Src& s = g.s;
   if (stopped(s.stop, s.pass)) return;
   const GramLayout& L = g.L;
-  const int P = g.P, S = g.S;
+  const int Wp = WPC > 0 ? WPC : L.Wp;
+  const int T4 = Wp / 4;
+  const int nt = WPC > 0 ? T4 * (T4 + 1) / 2 : L.ntiles;
+  const int S = WPC > 0 ? 256 / nt : g.S;
+  const int P = g.P;
   const int np = P / S;  // rows per thread and panel (P = S np, np a multiple of 4)
   const int64_t npanels = g.nunits;
   const int wg = (int)blockIdx.x - g.wg0, nwg = g.nwg;
-  const int Wp = L.Wp, stride = Wp + 2, cpr = stride / 2;
+  const int stride = Wp + 2, cpr = stride / 2;
   const int nchunks = P * cpr;
   const int tid = threadIdx.x, wave = tid >> 6;
-  const int nt = L.ntiles;
   const bool active = tid < nt * S;
   const int t = active ? tid % nt : 0;
   const int phase = active ? tid / nt : 0;
@@ -429,7 +443,6 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   // out): their maximum has the exponent field of the column maximum
   unsigned* cmx = (unsigned*)lds_all;
   double* lds = lds_all + Wp;
-  for (int x = tid; x < Wp; x += 256) cmx[x] = 0u;
 
   double acs[16], acc[16], th[16];
 #pragma unroll
@@ -452,9 +465,15 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   const int nfull = nchunks / 256, nci = (nchunks + 255) / 256;
   unsigned off[kMaxChunks];  // bytes
   unsigned ymask = 0u;
+  // Within a row the chunks are permuted: slot h T4 + c (h = 0, 1) holds
+  // columns 4 c + 2 h, 4 c + 2 h + 1 -- the first halves of the 4-column
+  // groups, then the second halves -- so that the lanes of one LDS read,
+  // which take the same half of up to eight different groups, fall into
+  // different banks; slot 2 T4 is the padding chunk.
+  auto slot_col = [&](int p) { return p < 2 * T4 ? 4 * (p % T4) + 2 * (p / T4) : Wp; };
   auto chunk_src = [&](int q, int& r, int& o) -> bool {
     r = q / cpr;
-    const int col = 2 * (q - r * cpr);
+    const int col = slot_col(q - r * cpr);
     if (HASY && col + 1 < L.ky) {
       o = col;
       return true;
@@ -533,8 +552,10 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   for (int64_t pnl = wg; pnl < npanels; pnl += nwg) {
     const int64_t rem = s.m - pnl * P;
     const int rows = rem < P ? (int)rem : P;
-    // this panel's transfers fly while the previous panel's sums are folded
-    // (every thread passed the barrier after reading that panel)
+    // every thread has finished the previous panel (its sums and its reads
+    // of the column maxima): this panel's transfers fly while that panel's
+    // sums are folded
+    __syncthreads();
     transfer(pnl);
     if (!folded && active) fold();
     for (int x = tid; x < Wp; x += 256) cmx[x] = 0u;
@@ -552,8 +573,9 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
         m0 = max(m0, v.y << 1);
         m1 = max(m1, v.w << 1);
       }
-      atomicMax(&cmx[2 * mcol], m0);
-      atomicMax(&cmx[2 * mcol + 1], m1);
+      const int c0 = slot_col(mcol);
+      atomicMax(&cmx[c0], m0);
+      atomicMax(&cmx[c0 + 1], m1);
     }
     __syncthreads();
     if (active) {
@@ -564,33 +586,51 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
       }
 #pragma unroll
       for (int e = 0; e < 16; ++e) acs[e] = __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
-      // two rows per trip: the first row's sums go to sn, the second's back
-      // into acs, so no copies are needed
-      const double* rp = lds + phase * stride;
+      // One row at a time, the next row's operands read from LDS while this
+      // row's products are summed (two register sets, A and B, alternate;
+      // np is even).  Column 4 c + x of a row sits at double 2 c + x (x < 2)
+      // or 2 T4 + 2 c + x - 2 (x >= 2) of its slots.
       const int rstep = S * stride;
-      for (int i = 0; i < np; i += 2, rp += 2 * rstep) {
-        double a0[4], b0[4], a1[4], b1[4];
+      const double* pa = lds + phase * stride + 2 * ti;
+      const double* pb = lds + phase * stride + 2 * tj;
+      auto load_row = [&](double* a, double* b, int row) {
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-          a0[x] = rp[4 * ti + x];
-          b0[x] = rp[4 * tj + x];
-          a1[x] = rp[rstep + 4 * ti + x];
-          b1[x] = rp[rstep + 4 * tj + x];
+          const int xo = x < 2 ? x : 2 * T4 + x - 2;
+          a[x] = pa[row * rstep + xo];
+          b[x] = pb[row * rstep + xo];
         }
+      };
+      // each of the four steps runs over eight sums before the next step,
+      // so that neighbouring instructions are independent
+      auto sum_row = [&](const double* a, const double* b) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const double sn = __builtin_fma(a0[e / 4], b0[e % 4], acs[e]);
-          const double d0 = sn - acs[e];  // exact
-          acc[e] = acc[e] + __builtin_fma(a0[e / 4], b0[e % 4], -d0);
-          const double s2 = __builtin_fma(a1[e / 4], b1[e % 4], sn);
-          const double d1 = s2 - sn;  // exact
-          acc[e] = acc[e] + __builtin_fma(a1[e / 4], b1[e % 4], -d1);
-          acs[e] = s2;
+        for (int g8 = 0; g8 < 16; g8 += 8) {
+          double sn[8], d[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) sn[e] = __builtin_fma(a[(g8 + e) / 4], b[e % 4], acs[g8 + e]);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) d[e] = sn[e] - acs[g8 + e];  // exact
+#pragma unroll
+          for (int e = 0; e < 8; ++e) d[e] = __builtin_fma(a[(g8 + e) / 4], b[e % 4], -d[e]);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) acc[g8 + e] = acc[g8 + e] + d[e];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) acs[g8 + e] = sn[e];
         }
+      };
+      // (the last step reads its own row again instead of a row past the
+      // panel, which keeps the loop body free of branches)
+      double ra[4], rb[4], qa[4], qb[4];
+      load_row(ra, rb, 0);
+      for (int i = 0; i < np; i += 2) {
+        load_row(qa, qb, i + 1);
+        sum_row(ra, rb);
+        load_row(ra, rb, i + 2 < np ? i + 2 : i + 1);
+        sum_row(qa, qb);
       }
     }
     folded = false;
-    __syncthreads();
   }
   if (!folded && active) fold();
   __syncthreads();
@@ -625,7 +665,6 @@ __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
   double BORTH_GLOBAL* out = gmem(g.part) + (int64_t)wg * E * 2;
   for (int x = tid; x < E * 2; x += 256) out[x] = red[x];
 }
-
 // ---------------------------------------------------------------------------
 // binary64 Gram of a narrow block (padded width WP <= 8, no weights): one row
 // per lane and step, UR rows in flight per lane, all WP (WP + 1) / 2 products
@@ -937,32 +976,39 @@ static int gram_tiles_rows(const GramLayout& L, int NT, bool biased) {
   return best * RS;
 }
 
+// LDS of one DMA-sweep workgroup (two are resident per compute unit, which
+// has 160 KiB).
+constexpr size_t kDmaLdsBytes = 80 * 1024;
+
+// LDS of a DMA-sweep workgroup with panels of P rows: the panel (rows of
+// stride Wp + 2, then 1 KiB of slack) and the column maxima.
+static size_t gram_dma_lds(const GramLayout& L, int P) {
+  return (size_t)P * (L.Wp + 2) * sizeof(double) + 1024 + (size_t)L.Wp * sizeof(double);
+}
+
 // The DMA-staged DD sweep (gram_dd_dma_kernel): biased DD on 256 threads
 // over 16-byte aligned rows of binary64 data without weights.
 bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT) {
   if (mode != 1 || NT != 256 || s.bw || s.dot2 || s.x_f32) return false;
   if (L.ntiles > 256) return false;
+  // the shortest panel (4 rows per phase) must fit
+  if (gram_dma_lds(L, 4 * (NT / L.ntiles)) > kDmaLdsBytes) return false;
   if ((reinterpret_cast<uintptr_t>(s.X) & 15) || (s.ldx & 1) || (L.k & 1)) return false;
   if (L.ky > 0 && ((reinterpret_cast<uintptr_t>(s.Y) & 15) || (s.ldy & 1) || (L.ky & 1)))
     return false;
   return true;
 }
 
-// LDS of one DMA-sweep workgroup (two are resident per compute unit, which
-// has 160 KiB).
-constexpr size_t kDmaLdsBytes = 80 * 1024;
-
-// Rows per panel of the DMA sweep: S phases of np rows each, np even and at
-// most 40 (the bias exponent cb then stays at 7), a multiple of 4 (four rows
-// per loop trip), the tallest panel whose
-// rows (stride Wp + 2) and column maxima fit the workgroup's LDS.  A
-// panel's rounding error grows about as np 2^cb ~ 2 np^2 per thread and is
-// averaged over the panels summed, so a short block (fewer than 16 panels'
-// worth of rows at the full height) takes shorter panels.
+// Rows per panel of the DMA sweep: S phases of np rows each, np at most 40
+// (the bias exponent cb then stays at most 7) and a multiple of 4, the
+// tallest panel whose rows (stride Wp + 2, 1 KiB of slack) and column maxima
+// fit the workgroup's LDS.  A panel's
+// rounding error grows about as np 2^cb ~ 2 np^2 per thread and is averaged
+// over the panels summed, so a short block (fewer than 16 panels' worth of
+// rows at the full height) takes shorter panels.
 static int gram_dma_rows(const GramLayout& L, int S, int64_t m) {
-  const size_t stride = (size_t)L.Wp + 2;
   int np = 40;
-  while (np > 4 && ((size_t)S * np * stride + L.Wp) * sizeof(double) + 1024 > kDmaLdsBytes) np -= 4;
+  while (np > 4 && gram_dma_lds(L, S * np) > kDmaLdsBytes) np -= 4;
   const int64_t short_np = m / (16 * (int64_t)S);
   if (short_np < np) np = short_np < 4 ? 4 : (int)(short_np & ~(int64_t)3);
   return S * np;
@@ -1000,7 +1046,7 @@ bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part,
     g.nunits = (s.m + g.P - 1) / g.P;
     // panel rows, column maxima, and slack for the spare lanes of the last
     // transfer instruction (a wave writes 64 chunks of 16 bytes)
-    const size_t panel = ((size_t)g.P * (L.Wp + 2) + L.Wp) * sizeof(double) + 1024;
+    const size_t panel = gram_dma_lds(L, g.P);
     const size_t redn = g.S > 1 ? (size_t)L.E * 2 * sizeof(double) : 0;
     *shmem = panel > redn ? panel : redn;
     if (*shmem > kDmaLdsBytes) return false;
@@ -1054,20 +1100,23 @@ hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int g
     if (mode != 1) return hipErrorInvalidValue;
     static std::once_flag attr;
     std::call_once(attr, [] {
-      const void* fns[4] = {(const void*)gram_dd_dma_kernel<false, false>,
-                            (const void*)gram_dd_dma_kernel<false, true>,
-                            (const void*)gram_dd_dma_kernel<true, false>,
-                            (const void*)gram_dd_dma_kernel<true, true>};
+      const void* fns[4] = {(const void*)gram_dd_dma_kernel<false, false, 0>,
+                            (const void*)gram_dd_dma_kernel<false, false, 32>,
+                            (const void*)gram_dd_dma_kernel<false, true, 0>,
+                            (const void*)gram_dd_dma_kernel<true, true, 0>};
       for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDmaLdsBytes);
     });
     // a batched launch takes the Y-capable kernel (its segments may differ)
+    // 32 columns without Y: the instance with the row layout built in
     if (b)
-      hipLaunchKernelGGL((gram_dd_dma_kernel<true, true>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+      hipLaunchKernelGGL((gram_dd_dma_kernel<true, true, 0>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
     else if (one.L.ky > 0)
-      hipLaunchKernelGGL((gram_dd_dma_kernel<false, true>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+      hipLaunchKernelGGL((gram_dd_dma_kernel<false, true, 0>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+    else if (one.L.Wp == 32 && one.L.ntiles == 36 && one.S == 256 / 36)
+      hipLaunchKernelGGL((gram_dd_dma_kernel<false, false, 32>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
     else
-      hipLaunchKernelGGL((gram_dd_dma_kernel<false, false>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+      hipLaunchKernelGGL((gram_dd_dma_kernel<false, false, 0>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
   } else if (NT_or_T == 256) {
     if (mode == 1) BORTH_TILES(true, 256); else BORTH_TILES(false, 256);
   } else if (NT_or_T == 1024) {
@@ -1096,7 +1145,7 @@ int gram_tiles_resident(int mode, int NT, size_t shmem) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   hipError_t e;
   if (NT == kGramDmaArg)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_dd_dma_kernel<false, false>, 256, shmem);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_dd_dma_kernel<false, false, 32>, 256, shmem);
   else if (NT == 256)
     e = mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<true, 256, false, false>, 256, shmem)
              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gram_tiles_kernel<false, 256, false, false>, 256, shmem);
