@@ -131,6 +131,13 @@ typedef struct {
   double orth_est;
   double kappa_est;
   int escalation;   /* BORTH_FLAG_AUTO_ESCALATE: 0 none, 1 DD Gram, 2 shifted DD */
+  /* SVQB (without BORTH_FLAG_RANK_REVEAL): the largest number of eigenvalues
+   * of M that one pass lifted to its floor (u lambda_max in binary64,
+   * 2^-104 lambda_max in DD), i.e. directions of the block that were
+   * numerically dependent; 0 for Cholesky and in batched calls (with
+   * BORTH_FLAG_RANK_REVEAL such directions are dropped, not lifted, and
+   * borth_iter_info reports the rank). */
+  int svqb_lifted;
 } borth_info;
 
 /* Fills *opts with the defaults: DD Gram, Cholesky, 2 passes, automatic

@@ -62,11 +62,12 @@ class Info:
     orth_est: float = 0.0   # ||R_p - I||_F of the last pass
     kappa_est: float = 0.0  # condition estimate from the first pass's factor
     escalation: int = 0     # escalate=True: 0 none, 1 DD Gram, 2 shifted DD
+    svqb_lifted: int = 0    # SVQB: most eigenvalues one pass lifted to its floor
 
 
 def _info(i):
     return Info(i.status, i.failed_pass, i.failed_pivot, i.passes_run, i.orth_est, i.kappa_est,
-                i.escalation)
+                i.escalation, i.svqb_lifted)
 
 
 def _torch():

@@ -27,7 +27,7 @@ class borth_opts(ctypes.Structure):
 class borth_info(ctypes.Structure):
     _fields_ = [("status", _int), ("failed_pass", _int), ("failed_pivot", _int),
                 ("passes_run", _int), ("orth_est", _dbl), ("kappa_est", _dbl),
-                ("escalation", _int)]
+                ("escalation", _int), ("svqb_lifted", _int)]
 
 
 class borth_block(ctypes.Structure):

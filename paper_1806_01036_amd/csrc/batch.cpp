@@ -632,6 +632,7 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
       infos[b].orth_est = 0.0;
       infos[b].kappa_est = 0.0;
       infos[b].escalation = 0;
+      infos[b].svqb_lifted = 0;
     }
     if (h[0] != 0 && first == BORTH_OK) first = (borth_status)h[0];
   }

@@ -143,7 +143,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
   if (shift < 0) shift = split ? std::ldexp(1.0, -13) : 0.0;
   const bool hasy = a.ky > 0;
 
-  HIPCHK(c, launch_fill_int(c->status, 4, 0, st), "fill");
+  HIPCHK(c, launch_fill_int(c->status, 7, 0, st), "fill");
 
   // ---- pass 1: Gram sweep + reduction + factor
   Src s1{a.Y, a.ldy, a.X, a.ldx, a.dt == BORTH_F32 ? 1 : 0, a.m};
@@ -205,6 +205,7 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     f.Rtot = ws + W.rtot;
     f.Ctot = ws + W.ctot;
     f.status = c->status;
+    f.lifted = c->status + 6;
     f.conv = ws + W.cu;  // the last pass's ||R_p - I|| stays (orth_est)
     f.kappa = pass == 0 ? ws + W.cu + 2 : nullptr;
     f.R_out = last ? a.R : nullptr;
@@ -339,7 +340,7 @@ int64_t partial_need(int ky, int k, int gmode) {
 // I||_F of its last pass and the first pass's condition estimate, in the
 // spare k x k area of the workspace).
 borth_status read_status(borth_ctx c, borth_info* info) {
-  HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream),
+  HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int) * 7, hipMemcpyDeviceToHost, c->stream),
          "status readback");
   double est[3] = {0.0, 0.0, 0.0};
   if (c->last_est)
@@ -354,6 +355,7 @@ borth_status read_status(borth_ctx c, borth_info* info) {
     info->orth_est = est[1];
     info->kappa_est = est[2];
     info->escalation = 0;
+    info->svqb_lifted = c->h_status[6];
   }
   return (borth_status)c->h_status[0];
 }
@@ -503,7 +505,7 @@ borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const 
   hipSetDevice(c->device);
   c->cur = c->stream;
   const WsLayout W = ws_layout();
-  HIPCHK(c, launch_fill_int(c->status, 4, 0, c->stream), "fill");
+  HIPCHK(c, launch_fill_int(c->status, 7, 0, c->stream), "fill");
   c->last_est = false;
   FactorArgs f;
   memset(&f, 0, sizeof(f));
@@ -521,6 +523,7 @@ borth_status borth_factor(borth_ctx c, int ky, int k, const double* G_hi, const 
   f.Rtot = c->ws + W.rtot;
   f.Ctot = c->ws + W.ctot;
   f.status = c->status;
+  f.lifted = c->status + 6;
   f.R_out = R;
   f.C_out = C;
   f.Z_out = Z;
@@ -747,7 +750,7 @@ extern "C" borth_status borth_orthonormalize_noalloc(borth_ctx c, int64_t m, int
   if (r) return r;
   const bool sync = info || (o.flags & BORTH_FLAG_SYNC);
   if (!sync) return BORTH_OK;
-  int hs[4] = {0, 0, 0, 0};
+  int hs[7] = {0, 0, 0, 0, 0, 0, 0};
   double est[3] = {0.0, 0.0, 0.0};
   HIPCHK(c, hipMemcpyAsync(hs, sp, sizeof(hs), hipMemcpyDeviceToHost, c->stream), "status readback");
   HIPCHK(c, hipMemcpyAsync(est, sp + ws_off + W.cu, sizeof(est), hipMemcpyDeviceToHost, c->stream),
@@ -761,6 +764,7 @@ extern "C" borth_status borth_orthonormalize_noalloc(borth_ctx c, int64_t m, int
     info->orth_est = est[1];
     info->kappa_est = est[2];
     info->escalation = 0;
+    info->svqb_lifted = hs[6];
   }
   return (borth_status)hs[0];
 }
@@ -841,7 +845,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
   const int kp = pow2pad(k);
   double* conv = ws + W.cu;  // two doubles of the spare k x k area
   // status[5]: the stop word (0 = running; else the number of passes made)
-  HIPCHK(c, launch_fill_int(c->status, 6, 0, c->stream), "fill");
+  HIPCHK(c, launch_fill_int(c->status, 7, 0, c->stream), "fill");
   int* stop = c->status + 5;
   c->last_est = true;
   it->converged = 0;
@@ -908,6 +912,7 @@ borth_status iter_impl(borth_ctx c, int64_t m, int k, const double* X, int64_t l
     f.Rtot = ws + W.rtot;
     f.Ctot = ws + W.ctot;
     f.status = c->status;
+    f.lifted = c->status + 6;
     f.conv = conv;
     f.kappa = p == 0 ? conv + 2 : nullptr;
     f.rank_reveal = rank_reveal ? 1 : 0;

@@ -651,13 +651,18 @@ __global__ void __launch_bounds__(NTF) svqb_kernel(FactorArgs one,
     for (int i = 0; i < k; ++i) lmax = fmax(lmax, sM[i * LD + i]);
     const double floor_ = lmax * 2.220446049250313e-16;
     double lmin = lmax;
+    int nl = 0;
     for (int i = 0; i < k; ++i) {
       double l = sM[i * LD + i];
-      if (!(l > floor_)) l = floor_;
+      if (!(l > floor_)) {
+        l = floor_;
+        ++nl;
+      }
       lam[i] = l;
       lmin = fmin(lmin, l);
     }
     if (a.kappa) a.kappa[0] = sqrt(lmax / lmin);
+    if (a.lifted && !a.rank_reveal && nl > *a.lifted) *a.lifted = nl;
     int r = 0;
     if (a.rank_reveal) {
       const double thr = lmax * k * 0x1p-52;
@@ -980,14 +985,19 @@ __global__ void __launch_bounds__(NTF) svqb_dd_kernel(FactorArgs one,
     for (int i = 0; i < k; ++i) lmax = fmax(lmax, sMh[i * LD + i]);
     const double floor_ = lmax * 0x1p-104;
     double lmin = lmax;
+    int nl = 0;
     for (int i = 0; i < k; ++i) {
       dd_t l = ldm(sMh, sMl, i, i);
-      if (!(l.hi > floor_)) l = dd_from(floor_);
+      if (!(l.hi > floor_)) {
+        l = dd_from(floor_);
+        ++nl;
+      }
       lh[i] = l.hi;
       ll[i] = l.lo;
       lmin = fmin(lmin, l.hi);
     }
     if (a.kappa) a.kappa[0] = sqrt(lmax / lmin);
+    if (a.lifted && !a.rank_reveal && nl > *a.lifted) *a.lifted = nl;
     int r = 0;
     if (a.rank_reveal) {
       const double thr = lmax * k * 0x1p-104;

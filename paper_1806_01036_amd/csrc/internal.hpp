@@ -169,6 +169,9 @@ struct FactorArgs {
   // (with conv) once both norms are <= stop_eps, set *stop = pass + 1.
   int* stop;
   double stop_eps;
+  // SVQB without rank revelation, optional: a status word that keeps the
+  // largest number of eigenvalues one pass lifted to its floor
+  int* lifted;
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 // One workgroup per entry of the device table `tab` (n entries, all with
