@@ -250,16 +250,18 @@ typedef struct {
 /* One project / orthonormalize pass with a double-double result (Sec. 4.2:
  * kernels that return DD results; the DD variant of Fig. 7): the DD Gram of
  * [Y | X], the DD factor (opts->fact, Cholesky or SVQB, with the corrected
- * projection coefficients) and the DD update of the narrow path, rounded
- * once into Q + Q_lo: Q (binary64, m x k, ldq) holds the rounded result and
- * Q_lo its DD low word (same layout), |Q_lo| <= ulp(Q)/2.  k <= 8.  X_lo
- * (may be NULL, same layout as X) makes the input DD as well, X + X_lo: the
- * DD Gram then also sweeps [X | X_lo] and [Y | X_lo] and combines the
- * blocks (ky + k <= 64), and the update starts from X + X_lo.  The other
- * options are fixed (DD Gram, one pass, no shift); opts->flags may carry
- * BORTH_FLAG_SYNC and BORTH_FLAG_DD_DOT2.  R and C: binary64 words of the
- * factors.  Q and Q_lo must not alias X, X_lo or each other.  Without X_lo,
- * Q alone equals what borth_orthonormalize returns for the same DD pass. */
+ * projection coefficients) and a DD update (Dot2 steps on the vector ALUs),
+ * rounded once into Q + Q_lo: Q (binary64, m x k, ldq) holds the rounded
+ * result and Q_lo its DD low word (same layout), |Q_lo| <= ulp(Q)/2.
+ * 1 <= k <= 64, 0 <= ky <= 64.  X_lo (may be NULL, same layout as X) makes
+ * the input DD as well, X + X_lo: the DD Gram then also sweeps [X | X_lo]
+ * and [Y | X_lo] and combines the blocks (k <= 32 and ky + k <= 64), and the
+ * update starts from X + X_lo.  The other options are fixed (DD Gram, one
+ * pass, no shift); opts->flags may carry BORTH_FLAG_SYNC and
+ * BORTH_FLAG_DD_DOT2.  R and C: binary64 words of the factors.  Q and Q_lo
+ * must not alias X, X_lo or each other.  Without X_lo and for k <= 8, Q
+ * alone equals what borth_orthonormalize returns for the same DD pass (for
+ * wider blocks that call updates in binary64 on the matrix cores). */
 borth_status borth_orthonormalize_dd(borth_ctx ctx, int64_t m, int k, const double* X,
                                      const double* X_lo, int64_t ldx, const double* Y,
                                      int64_t ldy, int ky, double* Q, double* Q_lo, int64_t ldq,

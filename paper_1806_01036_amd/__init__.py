@@ -385,9 +385,10 @@ def orthonormalize_noalloc(X, Y=None, *, gram="dd", fact="chol", passes=2, sched
 
 def orthonormalize_dd(X, Y=None, *, X_lo=None, fact="chol", dot2=False, out=None, out_lo=None,
                       R=None, C=None, check=True, ctx=None):
-    """One DD pass (k <= 8) returning the result in double-double:
+    """One DD pass (k <= 64) returning the result in double-double:
     (Q, Q_lo, R, C, Info) with Q + Q_lo the DD Q (borth_orthonormalize_dd).
-    ``X_lo``: low words of a DD input X + X_lo (same shape and strides)."""
+    ``X_lo``: low words of a DD input X + X_lo (same shape and strides;
+    k <= 32 and ky + k <= 64)."""
     torch = _torch()
     ctx = ctx or default_context(X.device.index)
     _mat(X, "X", ctx)

@@ -32,6 +32,7 @@ SOURCES = [
     "update_k64.hip",
     "update_narrow.hip",
     "update_narrow_gram.hip",
+    "update_dd.hip",
     "noalloc.hip",
     "probe.hip",
     "batch.cpp",

@@ -184,9 +184,11 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
              "combine");
     }
   }
-  // One DD pass on a narrow block: the update runs in DD as well (the
-  // factor then also gives the low words of Z and C).
-  const bool dd_update = dd && passes == 1 && a.dt == BORTH_F64 && a.k <= 8;
+  // One DD pass on a narrow block, or with a DD result requested on a block
+  // of up to 64 columns: the update runs in DD as well (the factor then also
+  // gives the low words of Z and C).
+  const bool dd_update =
+      dd && passes == 1 && a.dt == BORTH_F64 && (a.k <= 8 || (a.Qlo && a.k <= 64));
   auto factor = [&](int pass, int kyp_pass, const double* ghi, const double* glo, bool ddm,
                     double shrel, bool last) -> borth_status {
     FactorArgs f;
@@ -1000,13 +1002,13 @@ borth_status borth_orthonormalize_dd(borth_ctx c, int64_t m, int k, const double
   if (!c) return BORTH_ERR_ARG;
   borth_opts o;
   if (opts) o = *opts; else borth_default_opts(&o);
-  if (k < 1 || k > 8 || ky < 0 || ky > 64 || m < (int64_t)k + ky) return fail_arg(c, "shape (k <= 8)");
+  if (k < 1 || k > 64 || ky < 0 || ky > 64 || m < (int64_t)k + ky) return fail_arg(c, "shape (k <= 64)");
   if (!X || !Q || !Q_lo || ldx < k || ldq < k) return fail_arg(c, "X/Q/Q_lo");
   if (ky > 0 && (!Y || ldy < ky)) return fail_arg(c, "Y");
   if ((const void*)Q == (const void*)X || (const void*)Q_lo == (const void*)X || Q_lo == Q ||
       (X_lo && ((const void*)X_lo == (const void*)Q || (const void*)X_lo == (const void*)Q_lo)))
     return fail_arg(c, "Q and Q_lo must not alias X, X_lo or each other");
-  if (X_lo && ky + k > 64) return fail_arg(c, "a DD input needs ky + k <= 64");
+  if (X_lo && (ky + k > 64 || 2 * k > 64)) return fail_arg(c, "a DD input needs ky + k <= 64 and k <= 32");
   if (o.fact != BORTH_CHOL && o.fact != BORTH_SVQB) return fail_arg(c, "opts.fact");
   o.gram = BORTH_GRAM_DD;
   o.passes = 1;

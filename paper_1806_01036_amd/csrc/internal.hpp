@@ -219,15 +219,15 @@ struct UpdDev {
   int dense;
   double* Q;
   int64_t ldq;
-  double* Qlo;  // narrow DD update: the DD result's low words (ldq), or null
-  const double* Xlo;  // narrow DD update: low words of a DD input X (ldx), or null
+  double* Qlo;  // DD update: the DD result's low words (ldq), or null
+  const double* Xlo;  // DD update: low words of a DD input X (ldx), or null
   double* part;
   int64_t npanels;
   const double* C1;  // stage coefficients (ky x K C, K x K Z, zero padded)
   const double* Z1;
   const double* C2;
   const double* Z2;
-  const double* C1lo;  // low words of C1 and Z1: DD arithmetic (narrow kernel), or null
+  const double* C1lo;  // low words of C1 and Z1: DD arithmetic (narrow or DD kernel), or null
   const double* Z1lo;
   const double* bw;    // diagonal of B for the narrow kernel's fused Gram, or null
   const int* stop;     // as in Src
@@ -251,6 +251,11 @@ bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32);
 // stream kernel of update_narrow.hip.  kp: row stride of C and Z.
 bool update_narrow_ok(int k, int ky, int kp);
 hipError_t launch_update_narrow(const UpdDev& d, int kp, hipStream_t st);
+// DD update with a DD result for 8 < k <= 64 (update_dd.hip): the same
+// arithmetic as the narrow kernel's DD branch; needs Q, Qlo, C1, Z1, C1lo,
+// Z1lo; single stage, no fused Gram.
+bool update_dd_ok(int k, int ky, int kp);
+hipError_t launch_update_dd(const UpdDev& d, int kp, hipStream_t st);
 // The same sweep with the next pass's Gram columns [Y | T]^T T written as
 // partials (binary64, or DD when mode = 1) in the layout G =
 // make_layout_xcols(ky, k, 4), one per workgroup, at most max_wg of them;

@@ -85,10 +85,15 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.stop = a.src.stop;
   d.pass = a.src.pass;
   if (a.bw && !(a.partials && a.gram_xcols)) return hipErrorInvalidValue;
-  // DD arithmetic exists in the narrow kernel only (and with it DD results)
+  // DD arithmetic: the narrow kernel (k <= 8, with or without a DD result)
+  // or the DD kernel (8 < k <= 64, DD result)
   if ((a.Qlo || a.Xlo) && !(a.C1lo && a.Z1lo)) return hipErrorInvalidValue;
-  if ((a.C1lo || a.Z1lo) && (a.two_stage || a.src.x_f32 || !update_narrow_ok(L.k, L.ky, K)))
-    return hipErrorInvalidValue;
+  if ((a.C1lo || a.Z1lo) && (a.two_stage || a.src.x_f32)) return hipErrorInvalidValue;
+  if ((a.C1lo || a.Z1lo) && !update_narrow_ok(L.k, L.ky, K)) {
+    if (a.partials || !a.Q || !a.Qlo || !update_dd_ok(L.k, L.ky, K)) return hipErrorInvalidValue;
+    a.nwg = 0;
+    return launch_update_dd(d, K, st);
+  }
   if (!a.partials && !a.two_stage && !a.src.x_f32 && a.Q && update_narrow_ok(L.k, L.ky, K)) {
     a.nwg = 0;
     return launch_update_narrow(d, K, st);

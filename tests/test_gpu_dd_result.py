@@ -1,8 +1,9 @@
 """GPU tests of the double-double result (borth_orthonormalize_dd: one DD
 pass, Q returned as Q + Q_lo), on the shape of the paper's accuracy
-experiment (Sec. 4.2, Fig. 7: n = 1000, k_y = 20, n_b = 4).  The levels of
-the DD result are measured by the oracle's binary128 Gram matrix of
-[Y | Q | Q_lo]."""
+experiment (Sec. 4.2, Fig. 7: n = 1000, k_y = 20, n_b = 4) and on blocks of
+up to 64 columns.  The levels of the DD result are measured by the oracle's
+binary128 Gram matrix of [Y | Q | Q_lo]; its binary64 words are compared
+with the oracle's DD pass."""
 import numpy as np
 import pytest
 
@@ -78,9 +79,12 @@ def test_dd_result_exact_hadamard():
 
 def test_dd_result_argument_checks():
     borth = lib()
-    X = dev(synth.svd_matrix(2000, 16, 10.0, 7960))
-    with pytest.raises(Exception):  # k > 8
+    X = dev(synth.svd_matrix(2000, 65, 10.0, 7960))
+    with pytest.raises(Exception):  # k > 64
         borth.orthonormalize_dd(X)
+    X40 = synth.svd_matrix(2000, 40, 10.0, 7962)
+    with pytest.raises(Exception):  # a DD input needs k <= 32
+        borth.orthonormalize_dd(dev(X40), X_lo=dev(np.zeros_like(X40)))
     X4 = dev(synth.svd_matrix(2000, 4, 10.0, 7961))
     with pytest.raises(Exception):  # Q_lo aliasing X
         borth.orthonormalize_dd(X4, out_lo=X4)
@@ -106,3 +110,42 @@ def test_dd_input(ky):
     Q0, Ql0, _, _, _ = borth.orthonormalize_dd(dev(X), Yd, dot2=True)
     d = np.max(np.abs((host(Q) - host(Q0)) + (host(Ql) - host(Ql0))))
     assert 1e-20 < d < 1e-14
+
+
+@pytest.mark.parametrize("k,fact,dot2", [(12, "chol", False), (16, "chol", True), (32, "chol", False),
+                                         (64, "chol", False), (24, "svqb", False),
+                                         (64, "svqb", True)])
+def test_dd_result_wide(k, fact, dot2):
+    """Blocks of 9 to 64 columns (the DD update kernel for wide blocks): the
+    DD result is orthonormal and orthogonal to Y at the DD pass's level
+    (binary128 Gram of [Y | Q | Q_lo]), its low words are normalized, and
+    for Cholesky its binary64 words agree with the oracle's DD pass."""
+    borth = lib()
+    n, ky, kx, kxy = 3000, 20, 10.0, 1e3
+    X, Y = synth.projected_pair(n, k, ky, kx, kxy, 8100 + k)
+    Q, Ql, R, C, info = borth.orthonormalize_dd(dev(X), dev(Y), fact=fact, dot2=dot2)
+    assert info.status == 0
+    Qh, Qlh = host(Q), host(Ql)
+    om, omy = dd_levels(Qh, Qlh, Y)
+    note("dd result wide", k, fact, dot2, om, omy)
+    assert om <= 1e-28 * kxy ** 2 and omy <= 1e-28 * kxy ** 2
+    assert np.all(np.abs(Qlh) <= np.spacing(np.abs(Qh)) / 2)
+    if fact == "chol":
+        o = oracle.cholqr_steps(X, Y, dd_first=True, dd_corrected=True, passes=1)
+        assert o["info"] == 0
+        dq = np.max(np.abs(Qh - o["Q"])) / np.max(np.abs(o["Q"]))
+        note("  vs oracle DD pass", dq)
+        assert dq <= 8 * U64
+
+
+def test_dd_input_wide():
+    """A DD input X + X_lo on a 16-column block with 20 locked columns."""
+    borth = lib()
+    X, Y = synth.projected_pair(N, 16, KY, 10.0, 10.0, 8170)
+    rng = np.random.default_rng(8171)
+    Xl = (rng.random(X.shape) - 0.5) * np.spacing(np.abs(X))
+    Q, Ql, R, C, info = borth.orthonormalize_dd(dev(X), dev(Y), X_lo=dev(Xl), dot2=True)
+    assert info.status == 0
+    om, omy = dd_levels(host(Q), host(Ql), Y)
+    note("dd input wide", om, omy)
+    assert om <= 1e-27 and omy <= 1e-27
