@@ -101,6 +101,7 @@ typedef enum {
 #define BORTH_FLAG_RANK_REVEAL 16u  /* iterated scheme, SVQB: drop null directions (see below) */
 #define BORTH_FLAG_DD_DOT2 32u      /* DD Gram sweeps accumulate with Dot2 (see above) */
 #define BORTH_FLAG_AUTO_ESCALATE 64u /* borth_orthonormalize: repeat after a breakdown (below) */
+#define BORTH_FLAG_BATCH_PERSISTENT 128u /* batched calls: one persistent launch (see below) */
 
 typedef struct {
   int gram;       /* borth_gram_prec of pass 1 */
@@ -337,12 +338,24 @@ typedef struct {
 } borth_block;
 
 /* Many independent blocks of uneven shape (e.g. the per-node bases of a
- * contour-integral eigensolver, Sec. 4.1) orthonormalized together: each
- * phase of every block runs in one launch over all blocks, the launch
- * sequence is captured once into a hipGraph cached on the context and
- * replayed.  `blocks` and `infos` are host arrays of nblocks entries
- * (infos may be NULL; non-NULL synchronizes).  Tile shapes come from the
- * autotune table when one is loaded. */
+ * contour-integral eigensolver, Sec. 4.1) orthonormalized together, each
+ * through the passes of borth_orthonormalize (Sec. 4.2).  Each phase of
+ * every block runs in one launch over all blocks.  With
+ * BORTH_FLAG_BATCH_PERSISTENT, and when every block takes the DD Gram
+ * (biased sums), Cholesky, one or two passes, 5 <= k <= 64 and ky <= 16 (Y
+ * projected in every pass), the whole batch runs instead as ONE persistent
+ * launch: resident workgroups take (block, sweep, share) tasks from a queue
+ * of opened sweeps, and the workgroup that finishes the last share of a
+ * block's sweep runs that block's reduction and k x k step and opens its
+ * next sweep, so no block waits for the others' phases.  Both run the
+ * same arithmetic per block (one pass gives the same bits; with two, the
+ * second Gram matrix is summed over the workgroup's waves in another
+ * grouping).  Either launch
+ * sequence is captured once into a hipGraph cached on the context
+ * (BORTH_FLAG_GRAPH) and replayed.  `blocks` and
+ * `infos` are host arrays of nblocks entries (infos may be NULL; non-NULL
+ * synchronizes).  Rows per workgroup share come from the autotune table
+ * when one is loaded. */
 borth_status borth_batch_orthonormalize(borth_ctx ctx, int nblocks, const borth_block* blocks,
                                         const borth_opts* opts, borth_info* infos);
 

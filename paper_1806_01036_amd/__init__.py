@@ -31,7 +31,7 @@ GRAM = {"f64": 0, "dd": 1, "split": 2, "dd_dot2": 3}
 FACT = {"chol": 0, "svqb": 1}
 SCHED = {"auto": 0, "materialize": 1, "recompute": 2}
 FLAG_SYNC, FLAG_PROJECT_ONCE, FLAG_GRAPH, FLAG_NO_FUSE, FLAG_RANK_REVEAL = 1, 2, 4, 8, 16
-FLAG_DD_DOT2, FLAG_AUTO_ESCALATE = 32, 64
+FLAG_DD_DOT2, FLAG_AUTO_ESCALATE, FLAG_BATCH_PERSISTENT = 32, 64, 128
 OK, ERR_ARG, ERR_HIP, ERR_NOMEM, BREAKDOWN, NONFINITE, UNSUPPORTED = range(7)
 
 
@@ -479,14 +479,17 @@ def orthonormalize_iter(X, Y=None, *, gram="f64", fact="chol", eps=1e-10, max_it
 
 
 def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0,
-                         project_once=False, graph=False, sync=True, check=True, ctx=None):
+                         project_once=False, graph=False, persistent=False, sync=True,
+                         check=True, ctx=None):
     """Orthonormalize many independent blocks together (borth_batch_orthonormalize).
 
     blocks: list of dicts with X (m x k float64), optional Y (m x ky, ky <= 16)
-    and optional preallocated Q (may be X itself: in place), R, C.  Every
-    phase runs as one launch over all blocks; with graph=True the launch
-    sequence is captured once and replayed.  Returns the list of (Q, R, C)
-    and the list of Info (None entries when not synchronizing)."""
+    and optional preallocated Q (may be X itself: in place), R, C.  Each
+    phase runs as one launch over all blocks, or with persistent=True (where
+    every block fits it, see borth_batch_orthonormalize) the whole batch as
+    one persistent launch; with graph=True the launch sequence is captured
+    once and replayed.  Returns the list of (Q, R, C) and the list
+    of Info (None entries when not synchronizing)."""
     torch = _torch()
     if not blocks:
         return [], []
@@ -519,7 +522,8 @@ def batch_orthonormalize(blocks, *, gram="dd", fact="chol", passes=2, shift=-1.0
         e.Q, e.ldq, e.R = Q.data_ptr(), _ld(Q), Rt.data_ptr()
         e.C = Ct.data_ptr() if ky else None
         outs.append((Q, Rt, Ct if ky else None))
-    flags = (FLAG_PROJECT_ONCE if project_once else 0) | (FLAG_GRAPH if graph else 0)
+    flags = ((FLAG_PROJECT_ONCE if project_once else 0) | (FLAG_GRAPH if graph else 0)
+             | (FLAG_BATCH_PERSISTENT if persistent else 0))
     o = _opts(gram, fact, passes, "materialize", shift, flags)
     infs = (_lib.borth_info * len(blocks))()
     st = ctx.lib.borth_batch_orthonormalize(ctx.h, len(blocks), arr, ctypes.byref(o),

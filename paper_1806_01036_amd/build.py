@@ -35,6 +35,7 @@ SOURCES = [
     "update_dd.hip",
     "noalloc.hip",
     "probe.hip",
+    "batch_persistent.hip",
     "batch.cpp",
     "borth.cpp",
 ]

@@ -28,6 +28,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_persist.hpp"
 #include "ctx.hpp"
 
 using namespace borth;
@@ -59,6 +60,13 @@ struct BatchPlan {
   int* h_status = nullptr;
   hipGraphExec_t graph = nullptr;
   std::vector<BatchStep> steps;
+  // persistent single launch (batch_persist.hpp), when every block fits it
+  bool persist = false;
+  PBlock* pblocks = nullptr;  // device
+  int* porder = nullptr;      // device
+  int* pstate = nullptr;      // device, batch_persistent_state_ints(nb) ints
+  double* pscratch = nullptr; // device, pgrid x kPersistFactorDoubles
+  int pgrid = 0;
   uint64_t last_use = 0;
   int64_t bytes = 0;  // device bytes held
 };
@@ -75,6 +83,10 @@ void free_plan(BatchPlan* p) {
   if (p->ws) hipFree(p->ws);
   if (p->status) hipFree(p->status);
   if (p->h_status) hipHostFree(p->h_status);
+  if (p->pblocks) hipFree(p->pblocks);
+  if (p->porder) hipFree(p->porder);
+  if (p->pstate) hipFree(p->pstate);
+  if (p->pscratch) hipFree(p->pscratch);
   delete p;
 }
 
@@ -160,6 +172,16 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
   P->nblocks = nb;
   TableBuf tb;
   std::vector<BatchStep> steps;
+  // what the persistent driver needs of each block: its sweeps (table
+  // offsets fixed up after the upload), reductions and factors
+  struct PRec {
+    PBlock pb;
+    int64_t tab_off[3], map_off[3];
+  };
+  std::vector<PRec> pr(nb);
+  for (auto& r : pr) std::memset(&r, 0, sizeof(r));
+  bool persistable = (o.flags & BORTH_FLAG_BATCH_PERSISTENT) && dd && !svqb && passes >= 1 &&
+                     passes <= 2 && !(o.flags & BORTH_FLAG_DD_DOT2);
 
   {
     BatchStep s;
@@ -294,6 +316,12 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       if (!gram_seg(s, L1[b], gmode, NT, part + W[b].part, (int)map.size(), nwg_g[b], &gs, &sh))
         return cleanup(BORTH_ERR_UNSUPPORTED, "batch: block shape outside the Gram kernels");
       shmem = std::max(shmem, sh);
+      PSweep& ps = pr[b].pb.sw[0];
+      ps.kind = arg == kGramDmaArg ? 0 : 1;
+      ps.ntasks = nwg_g[b];
+      ps.wg0 = (int)map.size();
+      pr[b].pb.nsweeps = 1;
+      if (kind != 1 || (arg != kGramDmaArg && arg != 256) || sh > kPersistLds) persistable = false;
       for (int i = 0; i < nwg_g[b]; ++i) map.push_back((int)segs.size());
       segs.push_back(gs);
     }
@@ -306,6 +334,10 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
     s.grid = (int)map.size();
     s.tab_off = tb.add(segs);
     s.map_off = tb.add(map);
+    for (int b : g.blocks) {
+      pr[b].tab_off[0] = s.tab_off;
+      pr[b].map_off[0] = s.map_off;
+    }
     steps.push_back(s);
   }
 
@@ -318,6 +350,10 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       segs[b] = ReduceSeg{L, part + W[b].part, n, ws + W[b].ghi,
                           (sweep == 0 && dd) ? ws + W[b].glo : nullptr};
       red_nb = std::max(red_nb, reduce_blocks(L.E));
+      if (sweep < 2) {
+        pr[b].pb.red[sweep] = segs[b];
+        pr[b].pb.red_dd[sweep] = mode;
+      }
     }
     BatchStep s;
     s.kind = BatchStep::REDUCE;
@@ -359,6 +395,10 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         f.C_out = c_now ? B[b].C : nullptr;
         f.Z_out = nullptr;
         f.Rp_out = nullptr;
+        if (p < 2) {
+          pr[b].pb.fac[p] = f;
+          pr[b].pb.fac_ns[p] = f.k <= 16 ? 1 : (f.k <= 32 ? 2 : 4);
+        }
         if (f.k > kmax) {
           kmax = f.k;
           widest = f;
@@ -405,6 +445,18 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         d.Z1 = ws + W[b].zp[p - 1];
         d.wg0 = (int)map.size();
         d.nwg = nwg_u[p][b];
+        if (p <= 2) {
+          PSweep& ps = pr[b].pb.sw[p];
+          ps.kind = 2;
+          ps.K = uc.K;
+          ps.KYP = uc.KYP;
+          ps.GR = uc.gr;
+          ps.nw = persist_update_waves(uc.K, uc.KYP, uc.gr);
+          ps.ntasks = d.nwg;
+          ps.wg0 = d.wg0;
+          pr[b].pb.nsweeps = p + 1;
+          if (ps.nw < 1 || uc.two || uc.f32) persistable = false;
+        }
         for (int i = 0; i < d.nwg; ++i) map.push_back((int)segs.size());
         segs.push_back(d);
       }
@@ -414,6 +466,10 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       s.grid = (int)map.size();
       s.tab_off = tb.add(segs);
       s.map_off = tb.add(map);
+      for (int b : kv.second) {
+        pr[b].tab_off[p] = s.tab_off;
+        pr[b].map_off[p] = s.map_off;
+      }
       steps.push_back(s);
     }
   };
@@ -436,12 +492,55 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
     return cleanup(BORTH_ERR_HIP, "batch table upload failed");
   P->steps = std::move(steps);
   P->bytes = (int64_t)tbytes + 8 * (wsz + psz) + 16 * (int64_t)nb;
+
+  // ---- the persistent single launch
+  if (persistable) {
+    const int grid = batch_persistent_grid();
+    std::vector<PBlock> hb(nb);
+    std::vector<int> order(nb);
+    std::vector<double> work(nb);
+    for (int b = 0; b < nb; ++b) {
+      hb[b] = pr[b].pb;
+      for (int sw = 0; sw < hb[b].nsweeps; ++sw) {
+        hb[b].sw[sw].tab = P->dtab + pr[b].tab_off[sw];
+        hb[b].sw[sw].map = (const int*)(P->dtab + pr[b].map_off[sw]);
+      }
+      order[b] = b;
+      work[b] = (double)B[b].m * (B[b].ky + B[b].k);
+    }
+    // larger blocks first: their long sweeps start early and the tail is
+    // made of small blocks
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    const size_t sbytes = sizeof(int) * (size_t)batch_persistent_state_ints(nb);
+    const size_t fbytes = sizeof(double) * (size_t)std::max(grid, 1) * kPersistFactorDoubles;
+    if (grid >= 1 && hipMalloc((void**)&P->pblocks, sizeof(PBlock) * nb) == hipSuccess &&
+        hipMalloc((void**)&P->porder, sizeof(int) * nb) == hipSuccess &&
+        hipMalloc((void**)&P->pstate, sbytes) == hipSuccess &&
+        hipMalloc((void**)&P->pscratch, fbytes) == hipSuccess &&
+        hipMemcpy(P->pblocks, hb.data(), sizeof(PBlock) * nb, hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(P->porder, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice) == hipSuccess) {
+      P->persist = true;
+      P->pgrid = grid;
+      P->bytes += (int64_t)(sizeof(PBlock) * nb + sizeof(int) * nb + sbytes + fbytes);
+    } else {
+      return cleanup(BORTH_ERR_NOMEM, "batch: persistent plan allocation failed");
+    }
+  }
   *out = P;
   return BORTH_OK;
 }
 
 borth_status run_plan(borth_ctx c, BatchPlan* P, hipStream_t st) {
   c->cur = st;
+  if (P->persist) {
+    const int nb = P->nblocks;
+    HIPCHK(c, launch_fill_int(P->status, 4 * nb, 0, st), "batch fill");
+    prof_begin(c, 0);
+    HIPCHK(c, launch_batch_persistent(P->pblocks, P->porder, nb, P->pstate, P->pscratch, P->pgrid, st),
+           "batch persistent");
+    prof_end(c, 0);
+    return BORTH_OK;
+  }
   for (const BatchStep& s : P->steps) {
     switch (s.kind) {
       case BatchStep::FILL:
@@ -613,8 +712,8 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
   }();
   if (!infos && !(o.flags & BORTH_FLAG_SYNC)) {
     if (log)
-      std::fprintf(stderr, "borth: batch nblocks=%d gram=%d fact=%d passes=%d flags=%u (async)\n",
-                   nblocks, o.gram, o.fact, o.passes, o.flags);
+      std::fprintf(stderr, "borth: batch nblocks=%d gram=%d fact=%d passes=%d flags=%u persistent=%d grid=%d (async)\n",
+                   nblocks, o.gram, o.fact, o.passes, o.flags, P->persist ? 1 : 0, P->pgrid);
     return BORTH_OK;
   }
   HIPCHK(c, hipMemcpyAsync(P->h_status, P->status, sizeof(int) * 4 * (size_t)nblocks,
@@ -637,8 +736,8 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
     if (h[0] != 0 && first == BORTH_OK) first = (borth_status)h[0];
   }
   if (log)
-    std::fprintf(stderr, "borth: batch nblocks=%d gram=%d fact=%d passes=%d flags=%u -> status=%d\n",
-                 nblocks, o.gram, o.fact, o.passes, o.flags, (int)first);
+    std::fprintf(stderr, "borth: batch nblocks=%d gram=%d fact=%d passes=%d flags=%u persistent=%d grid=%d -> status=%d\n",
+                 nblocks, o.gram, o.fact, o.passes, o.flags, P->persist ? 1 : 0, P->pgrid, (int)first);
   return first;
 }
 

@@ -89,13 +89,17 @@ inline int upd_waves(int K, int KYP, int nst = 1, bool dma = false) {
 // DMA: the panels come in by direct transfers into two LDS buffers per wave
 // (upd_dma_class; binary64 rows with X, Y 16-byte aligned, even ldx, ldy,
 // k and ky).
+//
+// The body runs as workgroup bid of a launch (or a persistent workgroup's
+// task) with NW streaming waves over the LDS at lds; further waves of the
+// workgroup take part in its barriers only.
 template <int K, int KYP, bool TWO, int GR, typename ST, bool BATCH, bool DMA>
-__global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* __restrict__ tab,
-                                                     const int* __restrict__ wg2seg) {
-  extern __shared__ double lds[];
-  const UpdDev a = BATCH ? tab[wg2seg[blockIdx.x]] : one;
+__device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __restrict__ tab,
+                                            const int* __restrict__ wg2seg, int bid, int NW,
+                                            double* lds) {
+  const UpdDev a = BATCH ? tab[wg2seg[bid]] : one;
   if (stopped(a.stop, a.pass)) return;
-  const int wg = (int)blockIdx.x - a.wg0;
+  const int wg = bid - a.wg0;
   constexpr int S = KYP + K + 2;     // LDS row stride (doubles)
   constexpr int KC = (K + 15) / 16;  // 16-column blocks of T
   constexpr int KV = K < 16 ? K : 16;  // valid columns per T block
@@ -115,7 +119,6 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   constexpr int ZS = upd_zs(K);
   constexpr int ZST = (K + KYP) * ZS;  // LDS doubles of one stage's Z / W
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int NW = blockDim.x >> 6;
   const int ky = a.ky;
   const int dense = a.dense;
   const int c16 = lane & 15, r4 = lane >> 4;
@@ -170,7 +173,8 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   for (int i = 0; i < NTL; ++i) gacc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
 
   const int64_t wstride = (int64_t)a.nwg * NW;
-  int64_t pnl = (int64_t)wg * NW + wave;
+  const int64_t npanels = (a.m + PR - 1) / PR;
+  int64_t pnl = wave < NW ? (int64_t)wg * NW + wave : npanels;
   constexpr int KY1 = KYP > 0 ? KYP : 1;
   constexpr int RY = 64 / KY1;
   const int ry0 = lane / KY1, cy = lane % KY1;
@@ -178,7 +182,6 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
   const bool cyin = cy < ky, cxin = cx < a.k;
   const int aoff = c16 * S + r4;  // A operand: row l % 16, column l / 16
   const int doff = r4 * S + c16;  // result layout: row l / 16, column l % 16
-  const int64_t npanels = (a.m + PR - 1) / PR;
   // Direct transfers: chunk q = 64 i + lane (16 bytes) of a panel lands at
   // byte 16 q of the wave's buffer (row q / (S / 2), columns 2 (q % (S / 2))
   // and the next).  Chunks of padding columns and rows past m copy a valid
@@ -412,6 +415,14 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
       }
       ++idx;
     }
+}
+
+template <int K, int KYP, bool TWO, int GR, typename ST, bool BATCH, bool DMA>
+__global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* __restrict__ tab,
+                                                     const int* __restrict__ wg2seg) {
+  extern __shared__ double lds[];
+  update_body<K, KYP, TWO, GR, ST, BATCH, DMA>(one, tab, wg2seg, (int)blockIdx.x,
+                                               (int)(blockDim.x >> 6), lds);
 }
 
 template <int K, int KYP, bool TWO, int GR, typename ST>

@@ -5,6 +5,9 @@ Every block of a batch must satisfy what the single-block method guarantees
 projection repeated, Sec. 4.2), results must not depend on the other blocks
 (a breakdown stays in its block), graph replays and in-place runs are
 bitwise identical to the eager run, and the autotune table round-trips.
+Both drivers are covered: the launch per phase (the default) and the
+persistent single launch (persistent=True where every block fits it;
+BORTH_LOG reports which driver ran).
 """
 import re
 
@@ -36,6 +39,127 @@ MIXED = [(3001, 8, 16, 1e3, 11), (12007, 32, 16, 1e9, 12), (2500, 64, 16, 1e5, 1
          (7003, 16, 0, 1e10, 14), (20011, 13, 5, 1e7, 15), (4099, 1, 0, 1.0, 16),
          (9001, 40, 16, 1e8, 17), (15013, 64, 0, 1e6, 18), (5000, 20, 3, 1e4, 19),
          (6007, 3, 16, 1e2, 20)]
+
+
+# every block fits the persistent launch: 5 <= k <= 64, ky <= 16
+PERSIST = [(3001, 8, 16, 1e3, 41), (12007, 32, 16, 1e9, 42), (2500, 64, 16, 1e5, 43),
+           (7003, 16, 0, 1e10, 44), (20011, 13, 5, 1e7, 45), (4099, 5, 0, 1e2, 46),
+           (9001, 40, 16, 1e8, 47), (15013, 64, 0, 1e6, 48), (5000, 20, 3, 1e4, 49),
+           (60007, 24, 16, 1e6, 50)]
+
+
+def _drivers(capfd):
+    """persistent=0/1 of each batched call since the last read (BORTH_LOG)."""
+    return [int(x) for x in re.findall(r"borth: batch .*persistent=(\d)", capfd.readouterr().err)]
+
+
+def _check_vs_oracle(hostb, outs, infos, specs):
+    for (X, Y), (Q, R, C), inf, spec in zip(hostb, outs, infos, specs):
+        note("block", spec, inf)
+        assert inf.status == 0 and inf.passes_run == 2
+        met = oracle.metrics(host(Q), X, host(R), Y, host(C) if C is not None else None)
+        note("  ", met)
+        assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+        if Y is not None:
+            assert met["omega_y"] <= 1e-14
+            o1 = oracle.qr_q(X, Y)
+            assert np.max(np.abs(host(C) - o1["C"])) <= 1e-13
+        Rh = host(R)
+        assert np.all(np.tril(Rh, -1) == 0) and np.all(np.diag(Rh) > 0)
+
+
+def test_batch_persistent_vs_oracle(monkeypatch, capfd):
+    """The persistent single launch: DD-Gram CholQR2 with the projection
+    repeated on ten blocks of uneven height, width and conditioning."""
+    monkeypatch.setenv("BORTH_LOG", "1")
+    borth = lib()
+    hostb, devb = _blocks(PERSIST)
+    outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2, persistent=True)
+    assert _drivers(capfd) == [1]
+    _check_vs_oracle(hostb, outs, infos, PERSIST)
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_batch_persistent_matches_phases(passes, monkeypatch, capfd):
+    """Both drivers run the same task bodies on the same workgroup shares:
+    one pass (Gram, reduction, factor, update) is bitwise identical; with a
+    second pass the fused Gram of the first update is summed over a
+    different number of waves per workgroup, so the second factor differs
+    in rounding only."""
+    monkeypatch.setenv("BORTH_LOG", "1")
+    borth = lib()
+    torch = torch_gpu()
+    hostb, devb = _blocks(PERSIST)
+    op, ip = borth.batch_orthonormalize(devb, gram="dd", passes=passes, persistent=True)
+    of, inf_ = borth.batch_orthonormalize(devb, gram="dd", passes=passes)
+    assert _drivers(capfd) == [1, 0]
+    for (Qp, Rp, Cp), (Qf, Rf, Cf), a, b, spec in zip(op, of, ip, inf_, PERSIST):
+        assert a.status == b.status == 0 and a.passes_run == b.passes_run == passes
+        if passes == 1:
+            assert torch.equal(Qp, Qf) and torch.equal(Rp, Rf), spec
+            if Cp is not None:
+                assert torch.equal(Cp, Cf)
+        else:
+            kappa = max(spec[3], 1.0)
+            assert np.max(np.abs(host(Qp) - host(Qf))) <= 1e-13, spec
+            assert rel_fro(host(Rp), host(Rf)) <= 1e3 * kappa * U64, spec
+
+
+def test_batch_persistent_graph_replay_and_in_place(monkeypatch, capfd):
+    """The persistent launch takes its tasks in a different order on every
+    run, but each task's arithmetic is fixed: replays of the captured graph
+    and in-place runs give the eager run's bits."""
+    monkeypatch.setenv("BORTH_LOG", "1")
+    borth = lib()
+    torch = torch_gpu()
+    hostb, devb = _blocks(PERSIST[:6])
+    ref, _ = borth.batch_orthonormalize(devb, gram="dd", passes=2, persistent=True)
+    ref = [(Q.clone(), R.clone()) for (Q, R, _) in ref]
+    for d, (Q, R) in zip(devb, ref):
+        d["Q"] = torch.empty_like(Q)
+        d["R"] = torch.empty_like(R)
+    for rep in range(3):
+        for d in devb:
+            d["Q"].fill_(0.0)
+        outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2, graph=True,
+                                                 persistent=True)
+        torch.cuda.synchronize()
+        junk = torch.randn(512, 512, device="cuda", dtype=torch.float64).sum()  # eager work
+        torch.cuda.synchronize()
+        del junk
+        for (Q, R, _), (Qr, Rr), inf in zip(outs, ref, infos):
+            assert inf.status == 0
+            assert torch.equal(Q, Qr) and torch.equal(R, Rr), rep
+    for d in devb:
+        d["X"] = d["X"].clone()
+        d["Q"] = d["X"]
+    outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2, persistent=True)
+    for (Q, R, _), (Qr, Rr), inf in zip(outs, ref, infos):
+        assert inf.status == 0
+        assert torch.equal(Q, Qr) and torch.equal(R, Rr)
+    assert set(_drivers(capfd)) == {1}
+
+
+def test_batch_persistent_breakdown_and_fallback(monkeypatch, capfd):
+    """A breakdown stays in its block in the persistent launch too; a batch
+    that some block does not fit (k = 3) runs per phase even when the
+    persistent launch is asked for."""
+    monkeypatch.setenv("BORTH_LOG", "1")
+    borth = lib()
+    Xbad = synth.hadamard_columns(6, [1, 2, 3, 4, 2, 5])
+    good = [synth.svd_matrix(5000, 8, 1e6, 31), synth.svd_matrix(7000, 24, 1e4, 32)]
+    devb = [{"X": dev(good[0])}, {"X": dev(Xbad)}, {"X": dev(good[1])}]
+    outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2, check=False, persistent=True)
+    assert _drivers(capfd) == [1]
+    assert infos[1].status == 4 and infos[1].failed_pass == 1 and infos[1].failed_pivot == 5
+    for i in (0, 2):
+        assert infos[i].status == 0
+        X = good[0] if i == 0 else good[1]
+        met = oracle.metrics(host(outs[i][0]), X, host(outs[i][1]))
+        assert met["rho"] <= 1e-14 and met["omega"] <= 1e-14
+    narrow = [{"X": dev(synth.svd_matrix(4000, 3, 1e2, 33))}, {"X": dev(good[1])}]
+    _, infos = borth.batch_orthonormalize(narrow, gram="dd", passes=2, persistent=True)
+    assert _drivers(capfd) == [0] and all(i.status == 0 for i in infos)
 
 
 def test_batch_dd_cholqr2_vs_oracle():
