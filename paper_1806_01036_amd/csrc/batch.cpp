@@ -743,7 +743,11 @@ borth_status borth_batch_orthonormalize(borth_ctx c, int nblocks, const borth_bl
 
 // ---------------------------------------------------------------------------
 // Autotuner: for every sweep kind and width class, time each candidate grid
-// size on device-resident synthetic data and keep the fastest.
+// size on device-resident synthetic data and keep the fastest.  The
+// library's own choice (nwg 0) is a candidate, so tuning never makes a sweep
+// slower than the default; a winning explicit grid also sets the rows per
+// workgroup share of the batched sweeps (rows of the tuning block / nwg: the
+// per-workgroup row count the single-block sweep had).
 
 namespace {
 
@@ -772,7 +776,7 @@ borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) 
   };
   const int64_t m = 1 << 21;  // rows of the synthetic block (2M)
   double *X = nullptr, *Y = nullptr, *Q = nullptr, *part = nullptr, *zw = nullptr;
-  const int cand[] = {256, 512, 1024, 2048, 4096};
+  const int cand[] = {0, 256, 512, 1024, 1536, 2048, 4096};
   const int64_t part_n = 4096LL * 2 * 16 * 210;  // largest: DD, Wp = 80
   borth_status res = BORTH_OK;
   std::vector<TuneEntry> found;
@@ -807,7 +811,7 @@ borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) 
             }
             const int ky = hasy ? 16 : 0;
             double best = 1e30;
-            int best_nwg = 0;
+            int best_nwg = -1;
             for (int nwg : cand) {
               std::vector<float> ts;
               for (int rep = 0; rep < 4; ++rep) {
@@ -850,7 +854,10 @@ borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) 
               }
             }
             if (res) break;
-            found.push_back({op == 0 ? "gram" : "update", mode, kp, hasy, best_nwg, best});
+            if (best_nwg < 0) continue;
+            TuneEntry te{op == 0 ? "gram" : "update", mode, kp, hasy, best_nwg, best};
+            te.rows = best_nwg > 0 ? (int)((m + best_nwg - 1) / best_nwg) : 0;
+            found.push_back(te);
           }
   } while (false);
   if (e0) hipEventDestroy(e0);
@@ -864,7 +871,7 @@ borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) 
   if (res) return res;
   for (const TuneEntry& t : found) {
     auto& tab = t.op == "gram" ? c->tune_gram : c->tune_upd;
-    tab[std::make_tuple(t.mode, t.kp, t.hasy)] = TuneGram{t.nwg, 0};
+    tab[std::make_tuple(t.mode, t.kp, t.hasy)] = TuneGram{t.nwg, t.rows};
   }
   ++c->tune_generation;
   ++c->ws_generation;  // cached single-block graphs were captured with the old shapes
@@ -878,8 +885,9 @@ borth_status borth_autotune(borth_ctx c, const char* cache_path, int budget_ms) 
                  tune_device_key(c).c_str(), (long long)m);
     for (size_t i = 0; i < found.size(); ++i) {
       const TuneEntry& t = found[i];
-      std::fprintf(f, "{\"op\": \"%s\", \"mode\": %d, \"kp\": %d, \"hasy\": %d, \"nwg\": %d, \"ms\": %.6f}%s\n",
-                   t.op.c_str(), t.mode, t.kp, t.hasy, t.nwg, t.ms, i + 1 < found.size() ? "," : "");
+      std::fprintf(f, "{\"op\": \"%s\", \"mode\": %d, \"kp\": %d, \"hasy\": %d, \"nwg\": %d, \"ms\": %.6f, \"rows\": %d}%s\n",
+                   t.op.c_str(), t.mode, t.kp, t.hasy, t.nwg, t.ms, t.rows,
+                   i + 1 < found.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
     std::fclose(f);
@@ -923,7 +931,8 @@ borth_status borth_autotune_load(borth_ctx c, const char* cache_path) {
         c->err = "malformed autotune entry";
         return BORTH_ERR_ARG;
       }
-      if ((t.op != "gram" && t.op != "update") || t.mode < 0 || t.mode > 1 || t.nwg < 1 ||
+      // nwg 0: the library's own choice
+      if ((t.op != "gram" && t.op != "update") || t.mode < 0 || t.mode > 1 || t.nwg < 0 ||
           t.nwg > (1 << 20)) {
         std::fclose(f);
         c->err = "malformed autotune entry";

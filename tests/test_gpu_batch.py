@@ -333,6 +333,14 @@ def test_autotune_roundtrip(tmp_path):
         ctx.autotune(path, budget_ms=1500)
         txt = path.read_text()
         assert '"op": "gram"' in txt
+        # the library's own grid (nwg 0) is a candidate; a tuned grid also
+        # gives the batched sweeps their rows per workgroup share
+        entries = re.findall(r'"nwg": (\d+), "ms": [\d.]+, "rows": (\d+)', txt)
+        m_tune = int(re.search(r'"rows": (\d+), "entries"', txt).group(1))
+        assert entries
+        for nwg, rows in entries:
+            nwg, rows = int(nwg), int(rows)
+            assert rows == (-(-m_tune // nwg) if nwg > 0 else 0)
         ctx.autotune_load(path)
         bad = tmp_path / "bad.json"
         bad.write_text("{}\n")
