@@ -244,9 +244,11 @@ struct UpdClass {
   int dma = 0; // panels by direct transfers (update_dma_ok); the same for every block of a launch
 };
 // Whether an update sweep over these rows can take its panels by direct
-// global-to-LDS transfers: binary64, 16-byte aligned rows of X (and Y), even
-// ldx, ldy, k and ky, padded width 16 or 32, ky <= 16.
-bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32);
+// global-to-LDS transfers: padded width 16 or 32 with ky <= 16 (binary64,
+// 16-byte aligned rows of X and Y, even ldx, ldy, k and ky), or padded width
+// 64 without Y in one stage (binary64 or fp32, 16-byte aligned rows of X, ldx
+// and k whole 16-byte chunks).
+bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32, bool two);
 // Narrow blocks (k <= 8, ky <= 64), single stage, no fused Gram: the VALU
 // stream kernel of update_narrow.hip.  kp: row stride of C and Z.
 bool update_narrow_ok(int k, int ky, int kp);

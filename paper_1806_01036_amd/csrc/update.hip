@@ -12,8 +12,14 @@ namespace borth {
 int update_waves(int K, int KYP, bool dma) { return upd::upd_waves(K, KYP, 1, dma); }
 int update_rows(int K) { return upd::upd_rows(K); }
 
-bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32) {
-  if (f32 || !upd::upd_dma_class(K, KYP)) return false;
+bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32, bool two) {
+  if (!upd::upd_dma_class(K, KYP)) return false;
+  if (upd::upd_zl(K)) {
+    // one buffer per wave: single stage; rows of 16-byte chunks
+    const int epc = f32 ? 4 : 2;
+    return !two && !(reinterpret_cast<uintptr_t>(d.X) & 15) && d.ldx % epc == 0 && d.k % epc == 0;
+  }
+  if (f32) return false;
   if ((reinterpret_cast<uintptr_t>(d.X) & 15) || (d.ldx & 1) || (d.k & 1)) return false;
   if (d.ky > 0 && ((reinterpret_cast<uintptr_t>(d.Y) & 15) || (d.ldy & 1) || (d.ky & 1)))
     return false;
@@ -106,8 +112,8 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
     const int64_t slots = a.partial_cap_doubles / ((int64_t)a.glayout.E * (a.gram_dd ? 2 : 1));
     return launch_update_narrow_gram(d, K, a.gram_dd, a.glayout, slots, &a.nwg, st);
   }
-  const bool dma = update_dma_ok(d, K, KYP, a.src.x_f32 != 0);
-  const int NW = upd::upd_waves(K, KYP, a.two_stage ? 2 : 1, dma);
+  const bool dma = update_dma_ok(d, K, KYP, a.src.x_f32 != 0, a.two_stage);
+  const int NW = upd::upd_waves(K, KYP, a.two_stage ? 2 : 1, dma, a.src.x_f32 != 0);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   const int64_t need = (d.npanels + NW - 1) / NW;
   if (nwg > need) nwg = (int)(need > 0 ? need : 1);

@@ -55,25 +55,43 @@ __device__ __forceinline__ void wave_lds_sync() {
 __host__ __device__ constexpr bool upd_zl(int K) { return K >= 64; }
 __host__ __device__ constexpr int upd_rows(int K) { return upd_zl(K) ? 16 : 32; }
 __host__ __device__ constexpr int upd_zs(int K) { return K + 2; }  // LDS row stride of Z / W
-// Panels brought in by direct global-to-LDS transfers, double-buffered per
-// wave (binary64 rows, 16-byte aligned, K <= 32 and at most 16 Y columns):
-// the next panel's rows are in flight while the current one is computed.
-__host__ __device__ constexpr bool upd_dma_class(int K, int KYP) { return K >= 16 && K <= 32 && KYP <= 16; }
+// Panels brought in by direct global-to-LDS transfers, so that the next
+// panel's rows are in flight while the current one is computed (16-byte
+// aligned rows):
+//  * K = 16, 32 with at most 16 Y columns (binary64): two panel buffers per
+//    wave, the next panel lands in the other one;
+//  * K = 64 without Y, single stage (binary64 or fp32 rows): one buffer per
+//    wave; the panel's A operands are read into registers first, then the
+//    next panel's transfer overwrites the buffer during the product.
+__host__ __device__ constexpr bool upd_dma_class(int K, int KYP) {
+  return (K >= 16 && K <= 32 && KYP <= 16) || (K == 64 && KYP == 0);
+}
+__host__ __device__ constexpr int upd_pbufs(int K, bool dma) { return dma ? (upd_zl(K) ? 1 : 2) : 1; }
+// Row stride (elements) of a panel in LDS: [Y | S] converted to binary64
+// with two padding columns; fp32 rows taken by the transfers stay fp32 (four
+// padding columns keep rows 16-byte aligned).
+__host__ __device__ constexpr int upd_prow(int K, int KYP, bool dma, bool f32) {
+  return (dma && f32) ? K + 4 : KYP + K + 2;
+}
+// LDS doubles of one panel buffer.
+__host__ __device__ constexpr int upd_panel_doubles(int K, int KYP, bool dma, bool f32) {
+  return (dma && f32) ? upd_rows(K) * upd_prow(K, KYP, dma, f32) / 2
+                      : upd_rows(K) * upd_prow(K, KYP, dma, f32);
+}
 
-// LDS bytes of a workgroup with nw waves (one panel per wave, two with the
-// transfers, plus the shared Z / W operands of each stage when they live in
-// LDS).
-inline long upd_lds_bytes(int K, int KYP, int nw, int nst = 1, bool dma = false) {
+// LDS bytes of a workgroup with nw waves (its panel buffers plus the shared
+// Z / W operands of each stage when they live in LDS).
+inline long upd_lds_bytes(int K, int KYP, int nw, int nst = 1, bool dma = false, bool f32 = false) {
   const long zreg = upd_zl(K) ? (long)nst * (K + KYP) * upd_zs(K) : 0;
-  return 8L * (zreg + (long)nw * (dma ? 2 : 1) * upd_rows(K) * (KYP + K + 2));
+  return 8L * (zreg + (long)nw * upd_pbufs(K, dma) * upd_panel_doubles(K, KYP, dma, f32));
 }
 
 // Waves per workgroup (1..8): the most resident waves per CU under the 160 KB
 // of LDS, at most 8 (2 per SIMD); larger workgroups preferred.
-inline int upd_waves(int K, int KYP, int nst = 1, bool dma = false) {
+inline int upd_waves(int K, int KYP, int nst = 1, bool dma = false, bool f32 = false) {
   int best = 1, best_waves = 0;
   for (int nw = 1; nw <= 8; nw <<= 1) {
-    const long b = upd_lds_bytes(K, KYP, nw, nst, dma);
+    const long b = upd_lds_bytes(K, KYP, nw, nst, dma, f32);
     const int wgs = (int)((160L * 1024) / b);
     int waves = wgs * nw;
     if (waves > 8) waves = 8;
@@ -122,8 +140,13 @@ __device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __r
   const int ky = a.ky;
   const int dense = a.dense;
   const int c16 = lane & 15, r4 = lane >> 4;
+  // SB: K = 64 with transfers, one panel buffer per wave (upd_dma_class)
+  constexpr bool SB = DMA && ZL;
+  static_assert(!SB || (KYP == 0 && !TWO), "single-buffer transfers: K = 64, no Y, one stage");
+  static_assert(!DMA || SB || sizeof(ST) == 8, "double-buffer transfers: binary64 rows");
+  constexpr int PD = upd_panel_doubles(K, KYP, DMA, sizeof(ST) == 4);
   double* zl = lds;
-  double* pan0 = lds + (ZL ? NST * ZST : 0) + wave * (DMA ? 2 : 1) * PR * S;
+  double* pan0 = lds + (ZL ? NST * ZST : 0) + wave * upd_pbufs(K, DMA) * PD;
   double* pan = pan0;
 
   // B operands: in registers (lane l holds Z[4 s + l / 16][16 J + l % 16] and
@@ -209,9 +232,108 @@ __device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __r
       }
     }
   };
-  if (DMA && pnl < npanels) transfer(pnl, pan0);
+  if constexpr (SB) {
+    // Chunk q (16 bytes) of a panel lands at byte 16 q of the wave's buffer:
+    // row q / CPR, elements EPC (q % CPR) and on; padding chunks and rows past
+    // m copy a valid chunk (as above).
+    constexpr int EPC = 16 / (int)sizeof(ST);
+    constexpr int RS = upd_prow(K, KYP, true, sizeof(ST) == 4);
+    constexpr int CPR = RS / EPC, NCH1 = PR * CPR, NDI1 = (NCH1 + 63) / 64;
+    ST* pst = (ST*)pan0;
+    auto transfer1 = [&](int64_t p) {
+      const int64_t r0 = p * PR;
+      const int64_t last = a.m - 1;
+#pragma unroll
+      for (int i = 0; i < NDI1; ++i) {
+        const int q = 64 * i + lane;
+        if (i + 1 < NDI1 || q < NCH1) {
+          const int r = q / CPR, col = EPC * (q % CPR);
+          int64_t row = r0 + r;
+          row = row < last ? row : last;
+          const ST BORTH_GLOBAL* src = gmem((const ST*)a.X) + row * a.ldx + (col < a.k ? col : 0);
+          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src,
+                                           (void __attribute__((address_space(3)))*)((char*)pst + 1024 * i),
+                                           16, 0, 0);
+        }
+      }
+    };
+    // T of a panel is stored while the next panel is computed (the wait for
+    // a transfer then finds the stores long issued).
+    auto store_t = [&](const d4_t* tt, int64_t r0, int nr) {
+      if (!a.Q) return;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r4 + 4 * v;
+        if (r < nr) {
+          double BORTH_GLOBAL* qrow = gmem(a.Q) + (r0 + r) * a.ldq;
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+            if (16 * J + c16 < a.k) qrow[16 * J + c16] = tt[J][v];
+        }
+      }
+    };
+    if (pnl < npanels) transfer1(pnl);
+    d4_t tp[KC];
+    int64_t prow0 = -1;
+    int pnr = 0;
+    while (pnl < npanels) {
+      const int64_t row0 = pnl * PR;
+      const int nrows = (int)(a.m - row0 < PR ? a.m - row0 : PR);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if (nrows < PR) {
+        for (int x = lane; x < (PR - nrows) * RS; x += 64) pst[nrows * RS + x] = (ST)0;
+      }
+      wave_lds_sync();
+      // the panel's A operands (lane l: row l % 16, column 4 s + l / 16)
+      double ax[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) ax[s] = (double)pst[c16 * RS + 4 * s + r4];
+      // the buffer is free once the reads are done: the next panel's
+      // transfer runs during this panel's products
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      if (pnl + wstride < npanels) transfer1(pnl + wstride);
+      if (prow0 >= 0) store_t(tp, prow0, pnr);
+      d4_t t[KC];
+#pragma unroll
+      for (int J = 0; J < KC; ++J) t[J] = d4_t{0.0, 0.0, 0.0, 0.0};
+      if (dense) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+            t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], bz(0, s, J), t[J], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+            if (4 * s <= 16 * J + 15)
+              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], bz(0, s, J), t[J], 0, 0, 0);
+      }
+      if (GR) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int idx = 0;
+#pragma unroll
+          for (int I = 0; I < KC; ++I)
+#pragma unroll
+            for (int J = I; J < KC; ++J) {
+              gacc[idx] = __builtin_amdgcn_mfma_f64_16x16x4f64(t[I][v], t[J][v], gacc[idx], 0, 0, 0);
+              ++idx;
+            }
+        }
+      }
+#pragma unroll
+      for (int J = 0; J < KC; ++J) tp[J] = t[J];
+      prow0 = row0;
+      pnr = nrows;
+      pnl += wstride;
+    }
+    if (prow0 >= 0) store_t(tp, prow0, pnr);
+  }
+  if (DMA && !SB && pnl < npanels) transfer(pnl, pan0);
   int cur = 0;
-  while (pnl < npanels) {
+  while (!SB && pnl < npanels) {
     const int64_t row0 = pnl * PR;
     const int nrows = (int)(a.m - row0 < PR ? a.m - row0 : PR);
     wave_lds_sync();  // this wave's reads of its previous panel are done
@@ -428,13 +550,14 @@ __global__ void __launch_bounds__(512) update_kernel(UpdDev one, const UpdDev* _
 template <int K, int KYP, bool TWO, int GR, typename ST>
 hipError_t launch_upd_t(int grid, const UpdDev& one, const UpdDev* tab, const int* map,
                         hipStream_t st, bool dma) {
-  constexpr bool DC = upd_dma_class(K, KYP) && sizeof(ST) == 8;
+  constexpr bool DC = upd_dma_class(K, KYP) && (upd_zl(K) ? !TWO : sizeof(ST) == 8);
   dma = dma && DC;
-  const int NW = upd_waves(K, KYP, TWO ? 2 : 1, dma);
+  constexpr bool F32 = sizeof(ST) == 4;
+  const int NW = upd_waves(K, KYP, TWO ? 2 : 1, dma, F32);
   constexpr int KC = (K + 15) / 16;
   constexpr int T16 = (GR == 2 ? 1 : 0) + KC;
   const size_t red = GR ? sizeof(double) * T16 * (T16 + 1) / 2 * 4 * 64 : 0;
-  const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW, TWO ? 2 : 1, dma);
+  const size_t lb = (size_t)upd_lds_bytes(K, KYP, NW, TWO ? 2 : 1, dma, F32);
   const size_t shmem = lb > red ? lb : red;
   if (dma) {
     if (tab)

@@ -270,6 +270,8 @@ def test_factor_svqb_near_identity_k64():
 @pytest.mark.parametrize("m,k,ky,dense", [(5003, 4, 0, False), (5003, 8, 3, False),
                                           (7001, 16, 16, False), (7001, 32, 0, False),
                                           (3001, 64, 16, False), (4099, 20, 5, True),
+                                          (6007, 64, 0, False), (6007, 48, 0, True),
+                                          (5003, 37, 0, False), (17, 64, 0, False),
                                           (1, 5, 0, False)])
 def test_update_vs_oracle(m, k, ky, dense):
     borth = lib()
@@ -342,6 +344,30 @@ def test_update_inplace_and_fp32():
     Q = borth.update(dev(X32), dev(Z))
     ex32 = oracle.update_q(X32.astype(np.float64), Z)
     assert np.max(np.abs(host(Q) - ex32)) <= 100 * U64 * np.max(np.abs(X) @ np.abs(Z))
+
+
+@pytest.mark.parametrize("k", [64, 40, 42])
+def test_update_wide_inplace_and_fp32(k):
+    """Padded width 64 without Y: panels by direct transfers into one buffer
+    per wave (binary64 rows with even k, fp32 rows with k a multiple of 4),
+    the other widths by loads; in place, out of place, fp32 input, and a
+    ragged last panel."""
+    borth = lib()
+    rng = np.random.default_rng(70 + k)
+    m = 4093
+    X = rng.standard_normal((m, k))
+    Z = np.triu(rng.standard_normal((k, k)))
+    ex = oracle.update_q(X, Z)
+    tol = 100 * U64 * np.max(np.abs(X) @ np.abs(Z))
+    Q = host(borth.update(dev(X), dev(Z)))
+    assert np.max(np.abs(Q - ex)) <= tol
+    Xd = dev(X)
+    borth.update(Xd, dev(Z), out=Xd)
+    assert np.max(np.abs(host(Xd) - ex)) <= tol
+    X32 = X.astype(np.float32)
+    Q = borth.update(dev(X32), dev(Z))
+    ex32 = oracle.update_q(X32.astype(np.float64), Z)
+    assert np.max(np.abs(host(Q) - ex32)) <= tol
 
 
 # ---------------------------------------------------------------------------
