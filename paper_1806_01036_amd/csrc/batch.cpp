@@ -126,6 +126,8 @@ std::vector<int> share_wgs(const std::vector<int64_t>& rows, const std::vector<i
   return n;
 }
 // Rows per workgroup from the autotune table's "rows" field (0: default).
+// A persistent plan keeps the defaults: its tasks are these shares, and
+// shares sized for a single-block grid make many small tasks.
 int64_t rows_per_wg(const borth::TuneGram& t, int64_t dflt) {
   return t.rows > 0 ? t.rows : dflt;
 }
@@ -225,7 +227,8 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       hasy |= B[b].ky > 0;
     }
     const std::vector<int> n =
-        share_wgs(rows, cap, rows_per_wg(lookup(c->tune_gram, gmode, kpmax, hasy), kBatchRowsGram));
+        share_wgs(rows, cap, persistable ? kBatchRowsGram
+                                         : rows_per_wg(lookup(c->tune_gram, gmode, kpmax, hasy), kBatchRowsGram));
     for (size_t i = 0; i < kv.second.size(); ++i) {
       const int b = kv.second[i];
       nwg_g[b] = n[i];
@@ -239,6 +242,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
   std::vector<std::vector<int>> nwg_u(passes + 1, std::vector<int>(nb, 0));
   std::vector<std::vector<GramLayout>> Lu(passes + 1, std::vector<GramLayout>(nb));
   std::vector<std::map<std::tuple<int, int, int>, std::vector<int>>> ugroups(passes + 1);
+  std::vector<std::map<std::tuple<int, int, int>, bool>> udma(passes + 1);
   auto uclass = [&](int b, int p) {
     UpdClass uc;
     uc.K = W[b].kp;
@@ -256,7 +260,25 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
     }
     for (auto& kv : ugroups[p]) {
       const int K = std::get<0>(kv.first), KYP = std::get<1>(kv.first), gr = std::get<2>(kv.first);
-      const int NW = update_waves(K, KYP);
+      // panels by direct transfers when every block's rows allow them (not
+      // in a persistent plan: its update tasks stream panels through
+      // registers, and the transfers' workgroup shares would split them into
+      // more, smaller tasks)
+      bool dma = !persistable;
+      for (int b : kv.second) {
+        UpdDev d{};
+        d.X = p == 1 ? (const void*)B[b].X : (const void*)B[b].Q;
+        d.ldx = p == 1 ? B[b].ldx : B[b].ldq;
+        d.k = B[b].k;
+        if (KYP) {
+          d.Y = B[b].Y;
+          d.ldy = B[b].ldy;
+          d.ky = B[b].ky;
+        }
+        dma = dma && update_dma_ok(d, K, KYP, false, false);
+      }
+      udma[p][kv.first] = dma;
+      const int NW = update_waves(K, KYP, dma);
       std::vector<int64_t> rows;
       std::vector<int> cap;
       int hasy = 0;
@@ -267,7 +289,8 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         hasy |= B[b].ky > 0;
       }
       const std::vector<int> n =
-          share_wgs(rows, cap, rows_per_wg(lookup(c->tune_upd, gr ? 1 : 0, K, hasy), kBatchRowsUpd));
+          share_wgs(rows, cap, persistable ? kBatchRowsUpd
+                                           : rows_per_wg(lookup(c->tune_upd, gr ? 1 : 0, K, hasy), kBatchRowsUpd));
       for (size_t i = 0; i < kv.second.size(); ++i) {
         const int b = kv.second[i];
         nwg_u[p][b] = n[i];
@@ -421,6 +444,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       UpdClass uc{};
       for (int b : kv.second) {
         uc = uclass(b, p);
+        uc.dma = udma[p][kv.first] ? 1 : 0;
         UpdDev d;
         std::memset(&d, 0, sizeof(d));
         const bool first = p == 1;

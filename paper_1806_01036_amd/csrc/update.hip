@@ -12,12 +12,18 @@ namespace borth {
 int update_waves(int K, int KYP, bool dma) { return upd::upd_waves(K, KYP, 1, dma); }
 int update_rows(int K) { return upd::upd_rows(K); }
 
+// Padded width 64 (one buffer per wave): binary64 rows with ky <= 16 under the
+// conditions of the narrower widths, or fp32 X without Y with ldx and k
+// multiples of 4.
 bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32, bool two) {
   if (!upd::upd_dma_class(K, KYP)) return false;
   if (upd::upd_zl(K)) {
     // one buffer per wave: single stage; rows of 16-byte chunks
     const int epc = f32 ? 4 : 2;
-    return !two && !(reinterpret_cast<uintptr_t>(d.X) & 15) && d.ldx % epc == 0 && d.k % epc == 0;
+    if (two || (reinterpret_cast<uintptr_t>(d.X) & 15) || d.ldx % epc || d.k % epc) return false;
+    if (d.ky > 0 && (f32 || (reinterpret_cast<uintptr_t>(d.Y) & 15) || (d.ldy & 1) || (d.ky & 1)))
+      return false;
+    return true;
   }
   if (f32) return false;
   if ((reinterpret_cast<uintptr_t>(d.X) & 15) || (d.ldx & 1) || (d.k & 1)) return false;

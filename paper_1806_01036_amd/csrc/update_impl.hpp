@@ -60,11 +60,12 @@ __host__ __device__ constexpr int upd_zs(int K) { return K + 2; }  // LDS row st
 // aligned rows):
 //  * K = 16, 32 with at most 16 Y columns (binary64): two panel buffers per
 //    wave, the next panel lands in the other one;
-//  * K = 64 without Y, single stage (binary64 or fp32 rows): one buffer per
-//    wave; the panel's A operands are read into registers first, then the
-//    next panel's transfer overwrites the buffer during the product.
+//  * K = 64 with at most 16 Y columns, single stage (binary64 rows; fp32
+//    rows without Y): one buffer per wave; the panel's projection is done
+//    and its A operands are read into registers first, then the next
+//    panel's transfer overwrites the buffer during the product.
 __host__ __device__ constexpr bool upd_dma_class(int K, int KYP) {
-  return (K >= 16 && K <= 32 && KYP <= 16) || (K == 64 && KYP == 0);
+  return (K >= 16 && K <= 32 && KYP <= 16) || (K == 64 && KYP <= 16);
 }
 __host__ __device__ constexpr int upd_pbufs(int K, bool dma) { return dma ? (upd_zl(K) ? 1 : 2) : 1; }
 // Row stride (elements) of a panel in LDS: [Y | S] converted to binary64
@@ -142,7 +143,8 @@ __device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __r
   const int c16 = lane & 15, r4 = lane >> 4;
   // SB: K = 64 with transfers, one panel buffer per wave (upd_dma_class)
   constexpr bool SB = DMA && ZL;
-  static_assert(!SB || (KYP == 0 && !TWO), "single-buffer transfers: K = 64, no Y, one stage");
+  static_assert(!SB || (KYP <= 16 && !TWO && (KYP == 0 || sizeof(ST) == 8)),
+                "single-buffer transfers: K = 64, one stage, binary64 rows with Y");
   static_assert(!DMA || SB || sizeof(ST) == 8, "double-buffer transfers: binary64 rows");
   constexpr int PD = upd_panel_doubles(K, KYP, DMA, sizeof(ST) == 4);
   double* zl = lds;
@@ -239,26 +241,42 @@ __device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __r
     constexpr int EPC = 16 / (int)sizeof(ST);
     constexpr int RS = upd_prow(K, KYP, true, sizeof(ST) == 4);
     constexpr int CPR = RS / EPC, NCH1 = PR * CPR, NDI1 = (NCH1 + 63) / 64;
+    // with Y and a fused Gram: the next transfer starts after the product
+    constexpr bool LATE = YS > 0 && GR > 0;
     ST* pst = (ST*)pan0;
-    auto transfer1 = [&](int64_t p) {
-      const int64_t r0 = p * PR;
+    auto chunk = [&](int64_t r0, int i) {
       const int64_t last = a.m - 1;
-#pragma unroll
-      for (int i = 0; i < NDI1; ++i) {
-        const int q = 64 * i + lane;
-        if (i + 1 < NDI1 || q < NCH1) {
-          const int r = q / CPR, col = EPC * (q % CPR);
-          int64_t row = r0 + r;
-          row = row < last ? row : last;
-          const ST BORTH_GLOBAL* src = gmem((const ST*)a.X) + row * a.ldx + (col < a.k ? col : 0);
-          __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src,
-                                           (void __attribute__((address_space(3)))*)((char*)pst + 1024 * i),
-                                           16, 0, 0);
+      const int q = 64 * i + lane;
+      if (i + 1 < NDI1 || q < NCH1) {
+        const int r = q / CPR, col = EPC * (q % CPR);
+        int64_t row = r0 + r;
+        row = row < last ? row : last;
+        const ST BORTH_GLOBAL* src;
+        if (KYP > 0 && col < KYP) {
+          src = (const ST BORTH_GLOBAL*)(gmem(a.Y) + row * a.ldy + (col + 1 < ky ? col : 0));
+        } else {
+          const int xc = col - KYP;
+          src = gmem((const ST*)a.X) + row * a.ldx + (xc < a.k ? xc : 0);
         }
+        __builtin_amdgcn_global_load_lds((const void BORTH_GLOBAL*)src,
+                                         (void __attribute__((address_space(3)))*)((char*)pst + 1024 * i),
+                                         16, 0, 0);
       }
     };
-    // T of a panel is stored while the next panel is computed (the wait for
-    // a transfer then finds the stores long issued).
+    auto transfer1 = [&](int64_t p) {
+      if constexpr (KYP == 0) {
+#pragma unroll
+        for (int i = 0; i < NDI1; ++i) chunk(p * PR, i);
+      } else {
+        // rolled: unrolled, the chunks' lane offsets stay live across the
+        // whole stream and push the Y variants into spills
+#pragma unroll 1
+        for (int i = 0; i < NDI1; ++i) chunk(p * PR, i);
+      }
+    };
+    // T of a panel is stored at the start of the next panel, so that the
+    // wait for a transfer (which also waits for the wave's stores) finds the
+    // stores issued a panel's products earlier.
     auto store_t = [&](const d4_t* tt, int64_t r0, int nr) {
       if (!a.Q) return;
 #pragma unroll
@@ -284,18 +302,78 @@ __device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __r
         for (int x = lane; x < (PR - nrows) * RS; x += 64) pst[nrows * RS + x] = (ST)0;
       }
       wave_lds_sync();
+      // the previous panel's T (its registers are free before this panel's
+      // operands are read)
+      if (prow0 >= 0) store_t(tp, prow0, pnr);
+      d4_t t[KC];
+      double yv[4];  // the Y block in the result layout (Gram of [Y | T])
+      if constexpr (YS > 0) {
+        // projection in the paper's order, Xt = S - Y C accumulated onto S
+        // on the matrix cores (result layout), then written back over S as
+        // the A operand of the product with Z (binary64 panel, stride S)
+        const double* pd = (const double*)pst;
+#pragma unroll
+        for (int J = 0; J < KC; ++J)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) t[J][v] = pd[doff + 4 * v * S + KYP + 16 * J];
+        double ay[YS > 0 ? YS : 1];
+#pragma unroll
+        for (int s = 0; s < YS; ++s) ay[s] = pd[aoff + 4 * s];
+        if (YB) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) yv[v] = pd[doff + 4 * v * S];
+        }
+#pragma unroll
+        for (int s = 0; s < YS; ++s)
+#pragma unroll
+          for (int J = 0; J < KC; ++J)
+            t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[s], bw(0, s, J), t[J], 0, 0, 0);
+        wave_lds_sync();
+#pragma unroll
+        for (int J = 0; J < KC; ++J)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ((double*)pst)[doff + 4 * v * S + KYP + 16 * J] = t[J][v];
+        wave_lds_sync();
+      }
+#pragma unroll
+      for (int J = 0; J < KC; ++J) t[J] = d4_t{0.0, 0.0, 0.0, 0.0};
+      if constexpr (LATE) {
+        // A operands read from the buffer as the product goes (all of them
+        // in registers next to the [Y | T] Gram accumulators would spill);
+        // the next transfer starts after the product, during the Gram
+        const double* pd = (const double*)pst;
+        if (dense) {
+#pragma unroll 2
+          for (int s = 0; s < KS; ++s) {
+            const double av = pd[aoff + KYP + 4 * s];
+#pragma unroll
+            for (int J = 0; J < KC; ++J)
+              t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bz(0, s, J), t[J], 0, 0, 0);
+          }
+        } else {
+          // upper-triangular Z: k-step s meets column blocks J >= s / 4
+#pragma unroll
+          for (int s4 = 0; s4 < KC; ++s4) {
+#pragma unroll 2
+            for (int s = 4 * s4; s < 4 * s4 + 4; ++s) {
+              const double av = pd[aoff + KYP + 4 * s];
+#pragma unroll
+              for (int J = s4; J < KC; ++J)
+                t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bz(0, s, J), t[J], 0, 0, 0);
+            }
+          }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (pnl + wstride < npanels) transfer1(pnl + wstride);
+      } else {
       // the panel's A operands (lane l: row l % 16, column 4 s + l / 16)
       double ax[KS];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) ax[s] = (double)pst[c16 * RS + 4 * s + r4];
+      for (int s = 0; s < KS; ++s) ax[s] = (double)pst[c16 * RS + KYP + 4 * s + r4];
       // the buffer is free once the reads are done: the next panel's
       // transfer runs during this panel's products
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
       if (pnl + wstride < npanels) transfer1(pnl + wstride);
-      if (prow0 >= 0) store_t(tp, prow0, pnr);
-      d4_t t[KC];
-#pragma unroll
-      for (int J = 0; J < KC; ++J) t[J] = d4_t{0.0, 0.0, 0.0, 0.0};
       if (dense) {
 #pragma unroll
         for (int s = 0; s < KS; ++s)
@@ -310,15 +388,20 @@ __device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __r
             if (4 * s <= 16 * J + 15)
               t[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], bz(0, s, J), t[J], 0, 0, 0);
       }
+      }
       if (GR) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          double op[T16];
+          if (YB) op[0] = yv[v];
+#pragma unroll
+          for (int J = 0; J < KC; ++J) op[YB + J] = t[J][v];
           int idx = 0;
 #pragma unroll
-          for (int I = 0; I < KC; ++I)
+          for (int I = 0; I < T16; ++I)
 #pragma unroll
-            for (int J = I; J < KC; ++J) {
-              gacc[idx] = __builtin_amdgcn_mfma_f64_16x16x4f64(t[I][v], t[J][v], gacc[idx], 0, 0, 0);
+            for (int J = I; J < T16; ++J) {
+              gacc[idx] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], gacc[idx], 0, 0, 0);
               ++idx;
             }
         }

@@ -272,6 +272,8 @@ def test_factor_svqb_near_identity_k64():
                                           (3001, 64, 16, False), (4099, 20, 5, True),
                                           (6007, 64, 0, False), (6007, 48, 0, True),
                                           (5003, 37, 0, False), (17, 64, 0, False),
+                                          (6007, 64, 10, True), (4093, 50, 6, False),
+                                          (4093, 64, 7, False), (23, 64, 16, False),
                                           (1, 5, 0, False)])
 def test_update_vs_oracle(m, k, ky, dense):
     borth = lib()
