@@ -282,8 +282,8 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     u3.dense = a.o.fact == BORTH_SVQB;
     u3.Q = a.Q;
     u3.ldq = a.ldq;
-    if (!later_proj) {
-      // pass 2 did not project: its C is zero
+    if (!later_proj && hasy) {
+      // pass 2 did not project: its C is zero (without Y no sweep reads C)
       HIPCHK(c, launch_fill_int((int*)(ws + W.cp[1]), 2 * 64 * 64, 0, st), "zero C2");
     }
     prof_begin(c, 1);
@@ -313,7 +313,8 @@ borth_status enqueue_ortho(borth_ctx c, const OrthoCall& a) {
     r = factor(p, later_proj ? a.ky : 0, ws + W.g_hi, nullptr, false, 0.0, p == passes - 1);
     if (r) return r;
     cur = Src{a.Y, a.ldy, a.Q, a.ldq, 0, a.m};
-    if (!later_proj) HIPCHK(c, launch_fill_int((int*)(ws + W.cp[p]), 2 * 64 * 64, 0, st), "zero C");
+    if (!later_proj && hasy)
+      HIPCHK(c, launch_fill_int((int*)(ws + W.cp[p]), 2 * 64 * 64, 0, st), "zero C");
   }
   UpdateArgs u;
   memset(&u, 0, sizeof(u));

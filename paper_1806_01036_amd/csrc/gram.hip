@@ -267,9 +267,9 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
   const int e = blockIdx.x * EPB + el;
   double h = 0.0, l = 0.0;
   if (e < E) {
-    // partials g, g + G, ...: loaded 8 at a time so their latencies overlap,
-    // added in index order
-    constexpr int B = 8;
+    // partials g, g + G, ...: loaded 16 (DD) or 32 at a time so that their
+    // latencies overlap (the chain is latency-bound), added in index order
+    constexpr int B = DD ? 16 : 32;
     for (int w0 = g; w0 < nwg; w0 += G * B) {
       double vh[B], vl[B];
 #pragma unroll

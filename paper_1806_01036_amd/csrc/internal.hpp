@@ -246,8 +246,8 @@ struct UpdClass {
 // Whether an update sweep over these rows can take its panels by direct
 // global-to-LDS transfers: padded width 16 or 32 with ky <= 16 (binary64,
 // 16-byte aligned rows of X and Y, even ldx, ldy, k and ky), or padded width
-// 64 without Y in one stage (binary64 or fp32, 16-byte aligned rows of X, ldx
-// and k whole 16-byte chunks).
+// 64 with ky <= 16 in one stage (binary64, the same conditions; or fp32 X
+// without Y, 16-byte aligned rows, ldx and k multiples of 4).
 bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32, bool two);
 // Narrow blocks (k <= 8, ky <= 64), single stage, no fused Gram: the VALU
 // stream kernel of update_narrow.hip.  kp: row stride of C and Z.

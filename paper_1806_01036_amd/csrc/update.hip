@@ -12,9 +12,6 @@ namespace borth {
 int update_waves(int K, int KYP, bool dma) { return upd::upd_waves(K, KYP, 1, dma); }
 int update_rows(int K) { return upd::upd_rows(K); }
 
-// Padded width 64 (one buffer per wave): binary64 rows with ky <= 16 under the
-// conditions of the narrower widths, or fp32 X without Y with ldx and k
-// multiples of 4.
 bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32, bool two) {
   if (!upd::upd_dma_class(K, KYP)) return false;
   if (upd::upd_zl(K)) {
