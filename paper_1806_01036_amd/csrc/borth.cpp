@@ -549,7 +549,8 @@ borth_status borth_update(borth_ctx c, int64_t m, int k, borth_dtype dt, const v
   const WsLayout W = ws_layout();
   const int kp = pow2pad(k);
   double* zp = c->ws + W.zu;
-  double* cp = c->ws + W.cu;
+  double* cp = c->ws + W.cu;  // also where the estimates of a path call live:
+  c->last_est = false;        // they are gone once C is staged here
   HIPCHK(c, launch_fill_int((int*)zp, 2 * 64 * 64, 0, c->stream), "zero Z");
   HIPCHK(c, launch_fill_int((int*)cp, 2 * 64 * 64, 0, c->stream), "zero C");
   borth_status r = pad_copy(c, zp, kp, Z, k, k);

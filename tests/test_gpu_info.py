@@ -150,3 +150,19 @@ def test_profiling_mask():
     u_ms, u_n = ctx.kernel_time(1)
     ctx.set_profiling(False)
     assert g_n == 1 and u_n == 2 and u_ms > 0.0
+
+
+def test_update_clears_the_estimates():
+    """borth_update stages its C where a path call leaves its estimates; the
+    info read after it reports no estimates instead of entries of C."""
+    borth = lib()
+    ctx = borth.default_context(0)
+    X = synth.svd_matrix(4000, 8, 1e3, 11)
+    _, _, _, i1 = borth.orthonormalize(dev(X), gram="f64", passes=1, ctx=ctx)
+    assert i1.kappa_est > 1.0 and ctx.info().kappa_est == i1.kappa_est
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((4000, 4))
+    C = np.full((4, 8), 123.0)
+    borth.update(dev(X), dev(np.triu(rng.standard_normal((8, 8)))), dev(Y), dev(C), ctx=ctx)
+    inf = ctx.info()
+    assert inf.orth_est == 0.0 and inf.kappa_est == 0.0
