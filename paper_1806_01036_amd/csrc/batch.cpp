@@ -372,7 +372,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       const int n = sweep == 0 ? nwg_g[b] : nwg_u[sweep][b];
       segs[b] = ReduceSeg{L, part + W[b].part, n, ws + W[b].ghi,
                           (sweep == 0 && dd) ? ws + W[b].glo : nullptr};
-      red_nb = std::max(red_nb, reduce_blocks(L.E));
+      red_nb = std::max(red_nb, reduce_blocks(L.E, mode == 1));
       if (sweep < 2) {
         pr[b].pb.red[sweep] = segs[b];
         pr[b].pb.red_dd[sweep] = mode;

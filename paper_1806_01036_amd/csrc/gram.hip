@@ -238,14 +238,13 @@ __global__ void __launch_bounds__(256) gram_mfma_kernel(GramSeg one,
 }
 
 // ---------------------------------------------------------------------------
-// Threads per Gram entry of the reduction (the rest of the 1024-thread block
-// covers 1024 / G entries): more of them for small Grams, so that the chain of
-// partials each thread walks stays short.  A function of the segment's own
-// size only, so a segment's summation order does not depend on the others
-// in a batched launch.
+// Blocks of a reduction launch: G threads per Gram entry (reduce_groups), the
+// 1024-thread block covering 1024 / G entries.  G depends on the segment's
+// own size and precision only, so a segment's summation order does not
+// depend on the others in a batched launch.
 
-int reduce_blocks(int E) {
-  const int epb = 1024 / reduce_groups(E);
+int reduce_blocks(int E, bool dd) {
+  const int epb = 1024 / reduce_groups(E, dd);
   return (E + epb - 1) / epb;
 }
 
@@ -261,7 +260,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceSeg one,
   double BORTH_GLOBAL* __restrict__ Ghi = gmem(rs.Ghi);
   double BORTH_GLOBAL* __restrict__ Glo = rs.Glo ? gmem(rs.Glo) : nullptr;
   const int E = L.E;
-  const int G = reduce_groups(E), EPB = 1024 / G;
+  const int G = reduce_groups(E, DD), EPB = 1024 / G;
   if ((int)blockIdx.x * EPB >= E) return;  // batched launch: a smaller segment
   const int el = threadIdx.x % EPB, g = threadIdx.x / EPB;
   const int e = blockIdx.x * EPB + el;
@@ -635,7 +634,7 @@ hipError_t launch_reduce_segs(int mode, int nb, int nseg, const ReduceSeg& one,
 hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, int nwg,
                          double* G_hi, double* G_lo, hipStream_t st, const int* stop, int pass) {
   ReduceSeg r{L, partials, nwg, G_hi, G_lo, stop, pass};
-  return launch_reduce_segs(mode, reduce_blocks(L.E), 1, r, nullptr, st);
+  return launch_reduce_segs(mode, reduce_blocks(L.E, mode == 1), 1, r, nullptr, st);
 }
 
 // DD Gram of [Y | X] for X = X_hi + X_lo (both binary64 words given), from

@@ -616,7 +616,13 @@ __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramS
 // Partial sums per entry of the reduction: the reduction kernel's thread
 // groups (G of them, G a function of E) each sum the partials g, g + G, ...
 // in index order, and group 0 then adds groups 1 .. G - 1 in order.
-__host__ __device__ inline int reduce_groups(int E) { return E <= 256 ? 64 : (E <= 1024 ? 32 : 16); }
+// Threads per Gram entry of the reduction (a function of the segment's size
+// and precision only): more of them spread the partials over more compute
+// units; the groups' sums are then added one after another, which for DD
+// sums costs more per group.
+__host__ __device__ inline int reduce_groups(int E, bool dd) {
+  return E <= 256 ? 64 : (E <= 1024 ? (dd ? 64 : 128) : 32);
+}
 
 // The whole reduction of one segment by one workgroup (any size), entry by
 // entry in the same order of operations as reduce_kernel, so the two give
@@ -625,7 +631,7 @@ template <bool DD>
 __device__ __forceinline__ void reduce_segment_body(const ReduceSeg& rs) {
   const GramLayout& L = rs.L;
   const double BORTH_GLOBAL* __restrict__ part = gmem(rs.part);
-  const int nwg = rs.nwg, E = L.E, G = reduce_groups(E);
+  const int nwg = rs.nwg, E = L.E, G = reduce_groups(E, DD);
   double BORTH_GLOBAL* __restrict__ Ghi = gmem(rs.Ghi);
   double BORTH_GLOBAL* __restrict__ Glo = rs.Glo ? gmem(rs.Glo) : nullptr;
   const int W = L.ky + L.k;

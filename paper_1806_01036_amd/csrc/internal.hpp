@@ -129,9 +129,9 @@ hipError_t launch_reduce(const GramLayout& L, int mode, const double* partials, 
 hipError_t launch_gram_dd_combine(int ky, int k, double* Ahi, double* Alo, const double* Bhi,
                                   const double* Blo, const double* Chi, const double* Clo,
                                   hipStream_t st);
-// Blocks (grid.x) of the reduction of a Gram with E entries.
-int reduce_blocks(int E);
-// nseg segments (grid.y); nb = the largest reduce_blocks(L.E) among them.
+// Blocks (grid.x) of the reduction of a Gram with E entries (DD or binary64).
+int reduce_blocks(int E, bool dd);
+// nseg segments (grid.y); nb = the largest reduce_blocks(L.E, dd) among them.
 hipError_t launch_reduce_segs(int mode, int nb, int nseg, const ReduceSeg& one,
                               const ReduceSeg* tab, hipStream_t st);
 
