@@ -25,7 +25,8 @@ constexpr int kMaxIdle = 200000;
 
 // Offsets (doubles) in a workgroup's global working memory.
 constexpr int64_t kFmR0 = 0, kFmR1 = 2 * 64 * 65, kFmRow = 4 * 64 * 65, kFmPiv = kFmRow + 256,
-                  kFmFlag = kFmPiv + 128, kFmMsg = kFmFlag + 8;
+                  kFmFlag = kFmPiv + 128, kFmMsg = kFmFlag + 8, kFmDinv = kFmMsg + 8;
+static_assert(kFmDinv + 4 <= kPersistFactorDoubles, "factor working memory");
 
 // Each task body is a function of its own (not inlined into the kernel), so
 // that the register allocator treats it as it treats that body's own
@@ -142,7 +143,8 @@ __global__ void __launch_bounds__(256, 2) batch_persistent_kernel(const PBlock* 
   // messages from thread 0 to the workgroup (global memory, read after a
   // barrier: the workgroup's waves share the compute unit's cache)
   volatile int* msg = (volatile int*)(fm + kFmMsg);
-  const fct::CholMem mem{fm + kFmR0, fm + kFmR1, fm + kFmRow, fm + kFmPiv, (int*)(fm + kFmFlag)};
+  const fct::CholMem mem{fm + kFmR0, fm + kFmR1, fm + kFmRow, fm + kFmPiv, (int*)(fm + kFmFlag),
+                         fm + kFmDinv};
   const int tid = threadIdx.x;
   int idle = 0;
   for (;;) {

@@ -34,8 +34,9 @@ __global__ void __launch_bounds__(T * T) chol_kernel(FactorArgs one,
   __shared__ double s_row[2 * 2 * KP];
   __shared__ double s_piv[2 * 64];
   __shared__ int s_flag;
+  __shared__ double s_dinv[4];
   const FactorArgs a = tab ? tab[blockIdx.x] : one;
-  chol_body<DD, T, NS>(a, CholMem{s_r0, s_r1, s_row, s_piv, &s_flag});
+  chol_body<DD, T, NS>(a, CholMem{s_r0, s_r1, s_row, s_piv, &s_flag, s_dinv});
 }
 
 // ---------------------------------------------------------------------------

@@ -99,9 +99,8 @@ struct Acc {
 // l >= i and L^{-1} for l < i.  At the end R = D^{-1/2} U and
 // Z = R^{-1} = L^{-T} D^{-1/2}, so the inverse needs no second sweep and the
 // square roots leave the serial chain.  Each step costs one reciprocal of
-// the pivot (computed by every thread from the broadcast row) and one
-// barrier; the owners of row j + 1 publish it through a double-buffered
-// LDS row.
+// the pivot and one barrier; the owners of row j + 1 publish it through a
+// double-buffered LDS row, and the owner of the pivot its reciprocal.
 //
 // The body runs in a workgroup of T x T threads (a launch, or a persistent
 // workgroup of that size) with its working arrays at mem: in LDS for the
@@ -113,6 +112,7 @@ struct CholMem {
   double* row;  // 2 x 2 x KP: [buffer][hi, lo][column]
   double* piv;  // 2 x 64
   int* flag;
+  double* dinv; // 2 x 2: [buffer][hi, lo], the reciprocal of the next pivot
 };
 
 template <bool DD, int T, int NS>
@@ -256,12 +256,19 @@ __device__ __forceinline__ void chol_body(const FactorArgs& a, const CholMem& me
         if (i < k && i == l) x[p][q] = A::add(x[p][q], dd_from(sh));
       }
   }
-  // Publish row 0.
+  // Publish row 0, and the reciprocal of its pivot: the thread that holds
+  // a pivot computes it once for all (every thread would otherwise repeat
+  // the same DD division on every column).
   if (ti == 0) {
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       s_row[0][0][tj + T * q] = x[0][q].hi;
       s_row[0][1][tj + T * q] = x[0][q].lo;
+      if (tj + T * q == 0) {
+        const dd_t r = A::recip(x[0][q]);
+        mem.dinv[0] = r.hi;
+        mem.dinv[1] = r.lo;
+      }
     }
   }
   __syncthreads();
@@ -277,7 +284,7 @@ __device__ __forceinline__ void chol_body(const FactorArgs& a, const CholMem& me
       fail = j + 1;
       break;
     }
-    const dd_t dinv = A::recip(d);
+    const dd_t dinv = dd_make(mem.dinv[2 * (j & 1)], mem.dinv[2 * (j & 1) + 1]);
     if (tid == 0) {
       s_piv[0][j] = d.hi;
       s_piv[1][j] = d.lo;
@@ -309,6 +316,11 @@ __device__ __forceinline__ void chol_body(const FactorArgs& a, const CholMem& me
           for (int q = 0; q < NS; ++q) {
             s_row[jn & 1][0][tj + T * q] = x[p][q].hi;
             s_row[jn & 1][1][tj + T * q] = x[p][q].lo;
+            if (tj + T * q == jn) {
+              const dd_t r = A::recip(x[p][q]);
+              mem.dinv[2 * (jn & 1)] = r.hi;
+              mem.dinv[2 * (jn & 1) + 1] = r.lo;
+            }
           }
         }
     }
