@@ -297,6 +297,25 @@ def test_batch_options(gram, fact, passes, project_once):
             assert met["omega_y"] <= 1e-14
 
 
+def test_batch_unaligned_rows_in_a_class():
+    """A block whose rows are not 16-byte aligned (odd leading dimension)
+    takes its whole width class off the direct-transfer update path; the
+    aligned blocks of the other classes keep it.  Every block is checked
+    against the oracle."""
+    borth = lib()
+    torch = torch_gpu()
+    specs = [(6001, 32, 16, 1e6, 61), (4003, 30, 16, 1e8, 62), (5003, 64, 16, 1e5, 63),
+             (3001, 50, 16, 1e7, 64), (7001, 64, 0, 1e6, 65), (2999, 32, 0, 1e4, 66)]
+    hostb, devb = _blocks(specs)
+    for i in (1, 3):  # X as a view with leading dimension k + 1 (odd)
+        m, k = specs[i][0], specs[i][1]
+        W = torch.full((m, k + 1), float("nan"), dtype=torch.float64, device="cuda")
+        W[:, :k] = devb[i]["X"]
+        devb[i]["X"] = W[:, :k]
+    outs, infos = borth.batch_orthonormalize(devb, gram="dd", passes=2)
+    _check_vs_oracle(hostb, outs, infos, specs)
+
+
 def test_batch_c5_shape_reduced():
     """The batched workload's recipe (rows uniform, widths {8,16,32,64},
     kappa log-uniform in [1e3, 1e10], a 16-column locked basis per block) at
