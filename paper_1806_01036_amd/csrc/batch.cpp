@@ -125,11 +125,18 @@ std::vector<int> share_wgs(const std::vector<int64_t>& rows, const std::vector<i
   }
   return n;
 }
-// Rows per workgroup from the autotune table's "rows" field (0: default).
-// A persistent plan keeps the defaults: its tasks are these shares, and
-// shares sized for a single-block grid make many small tasks.
-int64_t rows_per_wg(const borth::TuneGram& t, int64_t dflt) {
-  return t.rows > 0 ? t.rows : dflt;
+// Rows per workgroup from the autotune table's "rows" field.  The tuner
+// times one 2M-row block, where short shares win by filling the device; a
+// batch has rows enough to fill it with default shares, and for sweeps that
+// write partial sums shorter shares only add partials (measured on the
+// 256-block batch with the tuner's 512-row shares: DD Gram 41.8 against
+// 38.5 ms, its reduction 1.0 against 0.23 ms), so those take tuned rows only
+// when longer than the default; update sweeps without a fused Gram take them
+// as tuned.  A persistent plan keeps the defaults: its tasks are these
+// shares.
+int64_t rows_per_wg(const borth::TuneGram& t, int64_t dflt, bool partials = true) {
+  if (t.rows <= 0) return dflt;
+  return (!partials || t.rows > dflt) ? t.rows : dflt;
 }
 
 struct BlkWs {
@@ -290,7 +297,8 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       }
       const std::vector<int> n =
           share_wgs(rows, cap, persistable ? kBatchRowsUpd
-                                           : rows_per_wg(lookup(c->tune_upd, gr ? 1 : 0, K, hasy), kBatchRowsUpd));
+                                           : rows_per_wg(lookup(c->tune_upd, gr ? 1 : 0, K, hasy), kBatchRowsUpd,
+                                                         gr != 0));
       for (size_t i = 0; i < kv.second.size(); ++i) {
         const int b = kv.second[i];
         nwg_u[p][b] = n[i];

@@ -274,6 +274,8 @@ def test_factor_svqb_near_identity_k64():
                                           (5003, 37, 0, False), (17, 64, 0, False),
                                           (6007, 64, 10, True), (4093, 50, 6, False),
                                           (4093, 64, 7, False), (23, 64, 16, False),
+                                          (6007, 32, 16, False), (5003, 24, 10, True),
+                                          (4093, 32, 7, False), (29, 32, 16, False),
                                           (1, 5, 0, False)])
 def test_update_vs_oracle(m, k, ky, dense):
     borth = lib()
