@@ -189,6 +189,8 @@ def run_c3(args, torch, borth, synth):
     m, k, kappa, seed = 4_000_000, 32, 1e12, 302
     log(f"generating X {m}x{k} kappa={kappa:g}")
     X = synth.svd_matrix(m, k, kappa, seed)
+    import hashlib
+    x_sha = hashlib.sha256(X.tobytes()).hexdigest()  # the input, for reproduction
     Xd = torch.from_numpy(X).cuda()
     Q = torch.empty_like(Xd)
     R = torch.empty((k, k), dtype=torch.float64, device="cuda")
@@ -278,6 +280,7 @@ def run_c3(args, torch, borth, synth):
         "config": {"workload": "DD-Gram CholQR2, X 4,000,000 x 32 binary64, kappa=1e12 "
                                "(U diag(sigma) V^T, seed 302)",
                    "m": m, "k": k, "kappa": kappa, "passes": 2, "gram": "dd"},
+        "input_sha256": x_sha,
         "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
         "step_ms": per_step,
         "stream_probe": {"kernel": "borth_stream_probe (hand-written HIP, 16-byte vectors)",
