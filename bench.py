@@ -154,6 +154,19 @@ def cpu_baseline_extra(X, dd, rows1=500_000, rows_q=250_000):
     out["o1_binary128_qr"] = dict(value=24.0 * r * k / dt / 1e9, unit="GB/s", cores=nthr,
                                   sample=f"oracle exact thin QR in binary128 (Gram, Cholesky, "
                                          f"update; 24 m k bytes), first {r} rows ({dt:.1f} s)")
+    # the oracle's DD Gram sweep alone (Dot2), at all threads and at one
+    for nt, rows in ((nthr, 4 * rows1), (1, rows1 // 2)):
+        try:
+            oracle.set_num_threads(nt)
+            r = min(rows, X.shape[0])
+            t0 = time.perf_counter()
+            oracle.gram_dot2(X[:r])
+            dt = time.perf_counter() - t0
+        finally:
+            oracle.set_num_threads(nthr)
+        out["o2_dd_gram" + ("" if nt == nthr else "_one_thread")] = dict(
+            value=8.0 * r * k / dt / 1e9, unit="GB/s", cores=nt,
+            sample=f"oracle DD Gram (Dot2, 8 m k bytes), first {r} rows, {nt} thread(s) ({dt:.1f} s)")
     return out
 
 
