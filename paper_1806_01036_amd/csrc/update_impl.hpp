@@ -89,9 +89,10 @@ inline long upd_lds_bytes(int K, int KYP, int nw, int nst = 1, bool dma = false,
 
 // Waves per workgroup (1..8): the most resident waves per CU under the 160 KB
 // of LDS, at most 8 (2 per SIMD); larger workgroups preferred, except that
-// at K = 32 two workgroups of four waves are taken over one of eight
-// (measured 3 % faster on the K = 32 sweeps: a workgroup's start and its
-// partial-sum epilogue then overlap the other's stream).
+// at K = 32 and 64 two workgroups of four waves are taken over one of eight
+// when both fit (measured 3 % faster on the K = 32 sweeps and 2-4 % on the
+// K = 64 ones: a workgroup's start and its partial-sum epilogue then
+// overlap the other's stream).
 inline int upd_waves(int K, int KYP, int nst = 1, bool dma = false, bool f32 = false) {
   int best = 1, best_waves = 0;
   for (int nw = 1; nw <= 8; nw <<= 1) {
@@ -99,7 +100,7 @@ inline int upd_waves(int K, int KYP, int nst = 1, bool dma = false, bool f32 = f
     const int wgs = (int)((160L * 1024) / b);
     int waves = wgs * nw;
     if (waves > 8) waves = 8;
-    if (wgs >= 1 && (waves > best_waves || (waves == best_waves && !(K == 32 && best == 4)))) {
+    if (wgs >= 1 && (waves > best_waves || (waves == best_waves && !(K >= 32 && best == 4)))) {
       best = nw;
       best_waves = waves;
     }
