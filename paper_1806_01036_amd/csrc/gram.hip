@@ -21,7 +21,8 @@
 //                      8-instruction Dot2 step (dd.hpp).
 //  gram_dd_dma_kernel  the biased DD sum with its row panels copied from HBM
 //                      straight into LDS (gfx950 global_load_lds_dwordx4);
-//                      the default DD sweep for 16-byte aligned binary64 rows.
+//                      the default DD sweep for 16-byte aligned binary64 rows,
+//                      and with Dot2 sums the Dot2 sweep of a single block.
 //  reduce_kernel       sums the partials in workgroup order (DD additions in
 //                      DD mode) -- no floating-point atomics, so every result
 //                      is bitwise reproducible.
@@ -69,12 +70,12 @@ __global__ void __launch_bounds__(NTB) gram_tiles_kernel(GramSeg one,
   gram_tiles_body<DD, NTB, BATCH, WB>(one, tab, wg2seg, (int)blockIdx.x, lds);
 }
 
-template <bool BATCH, bool HASY, int WPC>
+template <bool BATCH, bool HASY, int WPC, bool D2 = false>
 __global__ void __launch_bounds__(256, 2) gram_dd_dma_kernel(GramSeg one,
                                                              const GramSeg* __restrict__ tab,
                                                              const int* __restrict__ wg2seg) {
   extern __shared__ double lds_all[];
-  gram_dd_dma_body<BATCH, HASY, WPC>(one, tab, wg2seg, (int)blockIdx.x, lds_all);
+  gram_dd_dma_body<BATCH, HASY, WPC, D2>(one, tab, wg2seg, (int)blockIdx.x, lds_all);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,9 +398,10 @@ static size_t gram_dma_lds(const GramLayout& L, int P) {
 }
 
 // The DMA-staged DD sweep (gram_dd_dma_kernel): biased DD on 256 threads
-// over 16-byte aligned rows of binary64 data without weights.
-bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT) {
-  if (mode != 1 || NT != 256 || s.bw || s.dot2 || s.x_f32) return false;
+// over 16-byte aligned rows of binary64 data without weights, or Dot2 sums
+// (allow_dot2, a single block).
+bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT, bool allow_dot2) {
+  if (mode != 1 || NT != 256 || s.bw || (s.dot2 && !allow_dot2) || s.x_f32) return false;
   if (L.ntiles > 256) return false;
   // the shortest panel (4 rows per phase) must fit
   if (gram_dma_lds(L, 4 * (NT / L.ntiles)) > kDmaLdsBytes) return false;
@@ -415,44 +417,46 @@ bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT) {
 // fit the workgroup's LDS.  A panel's
 // rounding error grows about as np 2^cb ~ 2 np^2 per thread and is averaged
 // over the panels summed, so a short block (fewer than 16 panels' worth of
-// rows at the full height) takes shorter panels.
-static int gram_dma_rows(const GramLayout& L, int S, int64_t m) {
-  int np = 40;
+// rows at the full height) takes shorter panels.  Dot2 sums have no bias:
+// up to 128 rows per phase.
+static int gram_dma_rows(const GramLayout& L, int S, int64_t m, bool dot2 = false) {
+  int np = dot2 ? 128 : 40;
   while (np > 4 && gram_dma_lds(L, S * np) > kDmaLdsBytes) np -= 4;
   const int64_t short_np = m / (16 * (int64_t)S);
   if (short_np < np) np = short_np < 4 ? 4 : (int)(short_np & ~(int64_t)3);
   return S * np;
 }
 
-int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT) {
+int64_t gram_units(const Src& s, const GramLayout& L, int mode, int NT, bool allow_dot2) {
   if (gram_kind(L, mode, s.bw != nullptr) == 0) return (s.m + 3) / 4;
-  const int P = gram_dma_ok(s, L, mode, NT) ? gram_dma_rows(L, NT / L.ntiles, s.m)
-                                            : gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
+  const int P = gram_dma_ok(s, L, mode, NT, allow_dot2)
+                    ? gram_dma_rows(L, NT / L.ntiles, s.m, s.dot2 != 0)
+                    : gram_tiles_rows(L, NT, gram_biased(mode, s, NT));
   return (s.m + P - 1) / P;
 }
 
-int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT) {
-  const int64_t u = gram_units(s, L, mode, NT);
+int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT, bool allow_dot2) {
+  const int64_t u = gram_units(s, L, mode, NT, allow_dot2);
   const int64_t need = gram_kind(L, mode, s.bw != nullptr) == 0 ? (u + 3) / 4 : u;
   return (int)(need < 1 ? 1 : (need > (1 << 20) ? (1 << 20) : need));
 }
 
 bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part, int wg0,
-              int nwg, GramSeg* out, size_t* shmem) {
+              int nwg, GramSeg* out, size_t* shmem, bool allow_dot2) {
   GramSeg g;
   g.s = s;
   g.L = L;
   g.part = part;
   g.wg0 = wg0;
   g.nwg = nwg;
-  g.nunits = gram_units(s, L, mode, NT);
+  g.nunits = gram_units(s, L, mode, NT, allow_dot2);
   g.P = 0;
   g.S = 0;
   *shmem = 0;
-  if (gram_kind(L, mode, s.bw != nullptr) == 1 && gram_dma_ok(s, L, mode, NT)) {
+  if (gram_kind(L, mode, s.bw != nullptr) == 1 && gram_dma_ok(s, L, mode, NT, allow_dot2)) {
     g.S = NT / L.ntiles;
     if (g.S < 1) return false;
-    g.P = gram_dma_rows(L, g.S, s.m);
+    g.P = gram_dma_rows(L, g.S, s.m, s.dot2 != 0);
     g.nunits = (s.m + g.P - 1) / g.P;
     // panel rows, column maxima, and slack for the spare lanes of the last
     // transfer instruction (a wave writes 64 chunks of 16 bytes)
@@ -510,17 +514,22 @@ hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int g
     if (mode != 1) return hipErrorInvalidValue;
     static std::once_flag attr;
     std::call_once(attr, [] {
-      const void* fns[4] = {(const void*)gram_dd_dma_kernel<false, false, 0>,
+      const void* fns[5] = {(const void*)gram_dd_dma_kernel<false, false, 0>,
                             (const void*)gram_dd_dma_kernel<false, false, 32>,
                             (const void*)gram_dd_dma_kernel<false, true, 0>,
-                            (const void*)gram_dd_dma_kernel<true, true, 0>};
+                            (const void*)gram_dd_dma_kernel<true, true, 0>,
+                            (const void*)gram_dd_dma_kernel<false, true, 0, true>};
       for (const void* f : fns)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDmaLdsBytes);
     });
-    // a batched launch takes the Y-capable kernel (its segments may differ)
-    // 32 columns without Y: the instance with the row layout built in
+    // a batched launch takes the Y-capable kernel (its segments may differ;
+    // their sums are biased); a single block with Dot2 sums the Dot2
+    // instance; 32 columns without Y: the instance with the row layout
+    // built in
     if (b)
       hipLaunchKernelGGL((gram_dd_dma_kernel<true, true, 0>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
+    else if (one.s.dot2)
+      hipLaunchKernelGGL((gram_dd_dma_kernel<false, true, 0, true>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
     else if (one.L.ky > 0)
       hipLaunchKernelGGL((gram_dd_dma_kernel<false, true, 0>), dim3(grid), dim3(256), shmem, st, one, tab, wg2seg);
     else if (one.L.Wp == 32 && one.L.ntiles == 36 && one.S == 256 / 36)
@@ -596,26 +605,26 @@ hipError_t launch_gram(const Src& s, const GramLayout& L, int mode, double* part
   }
   const int kind = gram_kind(L, mode, s.bw != nullptr);
   const int NT = kind == 0 ? 256 : gram_tiles_threads(L);
-  const bool dma = kind == 1 && gram_dma_ok(s, L, mode, NT);
+  const bool dma = kind == 1 && gram_dma_ok(s, L, mode, NT, true);
   int nwg = tune.nwg > 0 ? tune.nwg : 1024;
   if (tune.nwg <= 0 && kind == 1) {
     // ALU-bound tile kernel: two full rounds of resident workgroups (measured
     // best on the 4M x 32 DD Gram: 1536 against 1024 or 2048)
     GramSeg g0;
     size_t sh0 = 0;
-    if (gram_seg(s, L, mode, NT, partials, 0, 1, &g0, &sh0)) {
+    if (gram_seg(s, L, mode, NT, partials, 0, 1, &g0, &sh0, true)) {
       const int r = gram_tiles_resident(mode, dma ? kGramDmaArg : NT, sh0);
       if (r > 0) nwg = 2 * r;
     }
     const int64_t fit = cap / ((int64_t)L.E * (mode ? 2 : 1));  // partial slots available
     if (nwg > fit) nwg = (int)(fit > 0 ? fit : 1);
   }
-  const int mx = gram_max_wg(s, L, mode, NT);
+  const int mx = gram_max_wg(s, L, mode, NT, true);
   if (nwg > mx) nwg = mx;
   if ((int64_t)nwg * L.E * (mode ? 2 : 1) > cap) return hipErrorInvalidValue;
   GramSeg g;
   size_t shmem = 0;
-  if (!gram_seg(s, L, mode, NT, partials, 0, nwg, &g, &shmem)) return hipErrorInvalidValue;
+  if (!gram_seg(s, L, mode, NT, partials, 0, nwg, &g, &shmem, true)) return hipErrorInvalidValue;
   const int arg = kind == 0 ? (L.Wp + 15) / 16 : (dma ? kGramDmaArg : NT);
   *nwg_out = nwg;
   return launch_gram_segs(kind, mode, arg, shmem, nwg, g, nullptr, nullptr, st);

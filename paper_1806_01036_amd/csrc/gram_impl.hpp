@@ -358,8 +358,11 @@ __device__ __forceinline__ void gram_tiles_body(const GramSeg& one, const GramSe
 // k, binary64, no weights (host check gram_dma_ok).  HASY: the sweep has Y
 // columns (ky > 0), so a chunk's source may be either matrix.  WPC > 0: the
 // padded width is WPC and the row phases 256 / ntiles (checked on the host),
-// so that the LDS offsets of a loop trip are immediates.
-template <bool BATCH, bool HASY, int WPC>
+// so that the LDS offsets of a loop trip are immediates.  D2: Dot2 sums
+// (the 8-instruction step of dd.hpp, as the tile kernel's Dot2 mode) in
+// place of the biased ones -- no column maxima, no bias and no folds; the
+// panel height is then set by the LDS alone.
+template <bool BATCH, bool HASY, int WPC, bool D2 = false>
 __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramSeg* __restrict__ tab,
                                                  const int* __restrict__ wg2seg, int bid,
                                                  double* lds_all) {
@@ -505,15 +508,17 @@ __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramS
     // sums are folded
     __syncthreads();
     transfer(pnl);
-    if (!folded && active) fold();
-    for (int x = tid; x < Wp; x += 256) cmx[x] = 0u;
+    if constexpr (!D2) {
+      if (!folded && active) fold();
+      for (int x = tid; x < Wp; x += 256) cmx[x] = 0u;
+    }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (rows < P) {
       // last panel: rows past m (copies of the last row) become zeros
       for (int x = tid; x < (P - rows) * stride; x += 256) lds[rows * stride + x] = 0.0;
     }
-    if (mgrp < ngrp) {
+    if (!D2 && mgrp < ngrp) {
       unsigned m0 = 0u, m1 = 0u;
 #pragma unroll 4
       for (int r = mgrp; r < rows; r += ngrp) {
@@ -527,13 +532,15 @@ __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramS
     }
     __syncthreads();
     if (active) {
+      if constexpr (!D2) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ea[i] = col_exp(4 * ti + i);
-        eb[i] = col_exp(4 * tj + i) + cb;
+        for (int i = 0; i < 4; ++i) {
+          ea[i] = col_exp(4 * ti + i);
+          eb[i] = col_exp(4 * tj + i) + cb;
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acs[e] = __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
       }
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acs[e] = __builtin_amdgcn_ldexp(1.0, ea[e / 4] + eb[e % 4]);
       // One row at a time, the next row's operands read from LDS while this
       // row's products are summed (two register sets, A and B, alternate;
       // np is even).  Column 4 c + x of a row sits at double 2 c + x (x < 2)
@@ -552,6 +559,11 @@ __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramS
       // each of the four steps runs over eight sums before the next step,
       // so that neighbouring instructions are independent
       auto sum_row = [&](const double* a, const double* b) {
+        if constexpr (D2) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) dot2_step(acs[e], acc[e], a[e / 4], b[e % 4]);
+          return;
+        }
 #pragma unroll
         for (int g8 = 0; g8 < 16; g8 += 8) {
           double sn[8], d[8];
@@ -580,7 +592,9 @@ __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramS
     }
     folded = false;
   }
-  if (!folded && active) fold();
+  if constexpr (!D2) {
+    if (!folded && active) fold();
+  }
   __syncthreads();
 
   const int E = L.E;
@@ -589,7 +603,7 @@ __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramS
     double BORTH_GLOBAL* out = gmem(g.part) + (int64_t)wg * E * 2;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const dd_t v = dot2_finish(th[e], acc[e]);
+      const dd_t v = dot2_finish(D2 ? acs[e] : th[e], acc[e]);
       out[2 * (t * 16 + e)] = v.hi;
       out[2 * (t * 16 + e) + 1] = v.lo;
     }
@@ -602,7 +616,7 @@ __device__ __forceinline__ void gram_dd_dma_body(const GramSeg& one, const GramS
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int x = t * 16 + e;
-        dd_t v = dot2_finish(th[e], acc[e]);
+        dd_t v = dot2_finish(D2 ? acs[e] : th[e], acc[e]);
         if (ph > 0) v = dd_add(dd_make(red[2 * x], red[2 * x + 1]), v);
         red[2 * x] = v.hi;
         red[2 * x + 1] = v.lo;

@@ -94,11 +94,13 @@ int gram_tiles_threads(const GramLayout& L);   // 256 or 1024
 // The tile sweep of a DD Gram staged by direct global-to-LDS transfers
 // (biased DD, 256 threads, 16-byte aligned rows); launch_gram_segs takes
 // kGramDmaArg as its thread argument for it.
-bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT);
+// allow_dot2: Dot2 sums (s.dot2) too -- a single block's launch only (the
+// batched and persistent launches run the biased sums).
+bool gram_dma_ok(const Src& s, const GramLayout& L, int mode, int NT, bool allow_dot2 = false);
 constexpr int kGramDmaArg = 257;
-int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT);
+int gram_max_wg(const Src& s, const GramLayout& L, int mode, int NT, bool allow_dot2 = false);
 bool gram_seg(const Src& s, const GramLayout& L, int mode, int NT, double* part, int wg0,
-              int nwg, GramSeg* out, size_t* shmem);
+              int nwg, GramSeg* out, size_t* shmem, bool allow_dot2 = false);
 // kind 0: NT_or_T = column blocks (Wp / 16, rounded up); kind 1: threads
 // (256 or 1024), or kGramDmaArg.
 hipError_t launch_gram_segs(int kind, int mode, int NT_or_T, size_t shmem, int grid,

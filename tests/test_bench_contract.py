@@ -30,10 +30,10 @@ def test_traffic_figure_matches_the_profiled_sources():
     assert bench.measured_traffic(rec, "lane_ops") == rec["lane_ops"]
     # the committed counter summary holds the same figures
     prof = (ROOT / "profiles" / "dd_cholqr2_4Mx32_hbm_counters.md").read_text()
-    m = re.search(r"`gram_dd_dma_kernel<false, false, 32>` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.e+]+) \|", prof)
+    m = re.search(r"`gram_dd_dma_kernel<false, false, 32, false>` \| \d+ \| [\d.]+ \| [\d.]+ \| ([\d.e+]+) \|", prof)
     assert m and abs(float(m.group(1)) - rec["bytes"]) <= 1e-4 * rec["bytes"]
     prof = (ROOT / "profiles" / "dd_cholqr2_4Mx32_valu_mfma_counters.md").read_text()
-    m = re.search(r"`gram_dd_dma_kernel<false, false, 32>` \| [\d.]+ \| [\d.e+]+ \| ([\d.e+]+) \|", prof)
+    m = re.search(r"`gram_dd_dma_kernel<false, false, 32, false>` \| [\d.]+ \| [\d.e+]+ \| ([\d.e+]+) \|", prof)
     assert m and abs(float(m.group(1)) * 64 - rec["lane_ops"]) <= 1e-3 * rec["lane_ops"]
     # any other source text gives no figure
     fake = dict(rec, sha256="0" * 64)
