@@ -36,7 +36,8 @@ def chain(m):
 @pytest.mark.parametrize("m,k,ky", [(5003, 4, 0), (5003, 8, 0), (5003, 16, 0), (5003, 20, 0),
                                     (7001, 32, 0), (7001, 64, 0), (5003, 8, 5), (6007, 32, 16),
                                     (3001, 64, 16), (1, 3, 0), (17, 1, 0), (4001, 3, 2),
-                                    (100_003, 8, 0), (100_003, 4, 0), (150_001, 4, 40)])
+                                    (100_003, 8, 0), (100_003, 4, 0), (150_001, 4, 40),
+                                    (5, 4, 2), (300, 2, 0)])
 @pytest.mark.parametrize("prec", ["f64", "dd", "dd_dot2"])
 def test_gram_vs_oracle(m, k, ky, prec):
     borth = lib()
