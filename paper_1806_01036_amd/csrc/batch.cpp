@@ -290,7 +290,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
       std::vector<int> cap;
       int hasy = 0;
       for (int b : kv.second) {
-        const int64_t np = (B[b].m + update_rows(K) - 1) / update_rows(K);
+        const int64_t np = (B[b].m + update_rows(K, KYP) - 1) / update_rows(K, KYP);
         rows.push_back(B[b].m);
         cap.push_back((int)std::max<int64_t>(1, std::min<int64_t>((np + NW - 1) / NW, 1 << 20)));
         hasy |= B[b].ky > 0;
@@ -472,7 +472,7 @@ borth_status build_plan(borth_ctx c, int nb, const borth_block* B, const borth_o
         d.Q = B[b].Q;
         d.ldq = B[b].ldq;
         d.part = uc.gr ? part + W[b].part : nullptr;
-        d.npanels = (B[b].m + update_rows(uc.K) - 1) / update_rows(uc.K);
+        d.npanels = (B[b].m + update_rows(uc.K, uc.KYP) - 1) / update_rows(uc.K, uc.KYP);
         d.C1 = ws + W[b].cp[p - 1];
         d.Z1 = ws + W[b].zp[p - 1];
         d.wg0 = (int)map.size();

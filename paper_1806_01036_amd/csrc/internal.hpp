@@ -276,7 +276,7 @@ hipError_t launch_update_k64(const UpdClass&, int grid, const UpdDev&, const Upd
 hipError_t launch_update_class(const UpdClass&, int grid, const UpdDev& one, const UpdDev* tab,
                                const int* wg2seg, hipStream_t st);
 int update_waves(int K, int KYP, bool dma = false);  // waves per workgroup of a single-stage class
-int update_rows(int K);            // rows per wave panel
+int update_rows(int K, int KYP);   // rows per wave panel
 // Layout of the fused Gram of an update sweep (of [Y | T] with Y padded to
 // 16 columns when with_y, else of T).
 GramLayout update_gram_layout(int ky, int k, int K, bool with_y);

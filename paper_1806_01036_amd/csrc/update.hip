@@ -10,7 +10,7 @@
 namespace borth {
 
 int update_waves(int K, int KYP, bool dma) { return upd::upd_waves(K, KYP, 1, dma); }
-int update_rows(int K) { return upd::upd_rows(K); }
+int update_rows(int K, int KYP) { return upd::upd_rows(K, KYP); }
 
 bool update_dma_ok(const UpdDev& d, int K, int KYP, bool f32, bool two) {
   if (!upd::upd_dma_class(K, KYP)) return false;
@@ -82,7 +82,7 @@ hipError_t launch_update(UpdateArgs& a, const GramLayout& L, const TuneGram& tun
   d.Qlo = a.Qlo;
   d.Xlo = a.Xlo;
   d.part = a.partials;
-  const int PR = upd::upd_rows(K);
+  const int PR = upd::upd_rows(K, KYP);
   d.npanels = (a.src.m + PR - 1) / PR;
   d.C1 = a.C1;
   d.Z1 = a.Z1;

@@ -53,7 +53,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 // the register file next to the fused Gram accumulators, and 64-row panels
 // of [Y | X] would leave fewer than one wave per SIMD under the LDS budget.
 __host__ __device__ constexpr bool upd_zl(int K) { return K >= 64; }
-__host__ __device__ constexpr int upd_rows(int K) { return upd_zl(K) ? 16 : 32; }
+// Rows per wave panel: 16 at K >= 64, and at K = 32 with Y columns (two
+// 32-row buffers of [Y | S] per wave would leave 1.5 waves per SIMD under
+// the LDS budget; 16-row ones allow 2); 32 otherwise.
+__host__ __device__ constexpr int upd_rows(int K, int KYP) {
+  return (upd_zl(K) || (K == 32 && KYP > 0)) ? 16 : 32;
+}
 __host__ __device__ constexpr int upd_zs(int K) { return K + 2; }  // LDS row stride of Z / W
 // Panels brought in by direct global-to-LDS transfers, so that the next
 // panel's rows are in flight while the current one is computed (16-byte
@@ -76,8 +81,8 @@ __host__ __device__ constexpr int upd_prow(int K, int KYP, bool dma, bool f32) {
 }
 // LDS doubles of one panel buffer.
 __host__ __device__ constexpr int upd_panel_doubles(int K, int KYP, bool dma, bool f32) {
-  return (dma && f32) ? upd_rows(K) * upd_prow(K, KYP, dma, f32) / 2
-                      : upd_rows(K) * upd_prow(K, KYP, dma, f32);
+  return (dma && f32) ? upd_rows(K, KYP) * upd_prow(K, KYP, dma, f32) / 2
+                      : upd_rows(K, KYP) * upd_prow(K, KYP, dma, f32);
 }
 
 // LDS bytes of a workgroup with nw waves (its panel buffers plus the shared
@@ -136,7 +141,7 @@ __device__ __forceinline__ void update_body(const UpdDev& one, const UpdDev* __r
   constexpr int GT4 = GW / 4;
   constexpr int RPQ = 64 / K;        // panel rows per load step
   constexpr bool ZL = upd_zl(K);     // B operands in LDS
-  constexpr int PR = upd_rows(K);    // rows per wave panel
+  constexpr int PR = upd_rows(K, KYP);  // rows per wave panel
   constexpr int NLQ = PR * K / 64;   // X load steps per panel
   constexpr int NLY = PR * KYP / 64; // Y load steps per panel
   constexpr int ZS = upd_zs(K);
