@@ -50,9 +50,9 @@ DD_GRAM_OPS_DOT2 = 10.0
 # device copy of known size, see profiles/dd_cholqr2_4Mx32_hbm_counters.md).
 # Valid only for the kernel sources they were taken on: reported as null once
 # those sources change.
-DD_GRAM_TRAFFIC = {"bytes": 1033705822, "lane_ops": 10228965376,
+DD_GRAM_TRAFFIC = {"bytes": 1033706710, "lane_ops": 10228965376,
                    "sources": ["gram.hip", "gram_impl.hpp", "dd.hpp", "internal.hpp"],
-                   "sha256": None}
+                   "sha256": "2ceb2a0649039a8c2d06e7938f41266fb11b968b1b8fca7126d2550b8afcf7a2"}
 
 
 def measured_traffic(rec, key="bytes"):
