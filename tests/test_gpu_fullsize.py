@@ -97,6 +97,30 @@ def test_c3_dd_gram_full_vs_exact():
     assert np.linalg.norm(err) <= 1e-28 * np.linalg.norm(ex_hi)
 
 
+def test_fig8_dot2_gram_full_sampled():
+    """The first Gram sweep of the iterated DD scheme at the paper's runtime
+    shape (n = 8e6 rows, [Y | X] with k_y = 40 and n_b = 4, kappa(X) = 1e6,
+    kappa(X, Y) = 1e12): Dot2 sums on LDS-staged panels, each workgroup
+    folding many panels, against entries of the binary128 Gram matrix taken
+    one column pair at a time (Y^T Y, Y^T X and X^T X entries, on and off the
+    diagonal): |dG_ij| <= 2e-30 sqrt(G_ii G_jj) (measured up to 1.9e-31)."""
+    borth = lib()
+    torch_gpu()
+    Xd, Yd = synth.projected_pair_device(8_000_000, 4, 40, 1e6, 1e12, 8101)
+    note("Dot2 Gram 8,000,000 x [40 | 4]")
+    ghi, glo = borth.gram(Xd, Yd, prec="dd_dot2")
+    ghi, glo = host(ghi), host(glo)
+    Y, X = host(Yd), host(Xd)
+    for i, j in [(0, 0), (3, 17), (39, 39), (5, 40), (39, 43), (40, 40), (41, 43), (43, 43)]:
+        a = Y[:, i] if i < 40 else X[:, i - 40]
+        b = Y[:, j] if j < 40 else X[:, j - 40]
+        ex_hi, ex_lo = oracle.gram_q(np.ascontiguousarray(np.stack([a, b], axis=1)))
+        d = np.sqrt(ex_hi[0, 0] * ex_hi[1, 1])
+        e = abs((ghi[i, j] - ex_hi[0, 1]) + (glo[i, j] - ex_lo[0, 1])) / d
+        note("  entry", i, j, e)
+        assert e <= 2e-30
+
+
 @pytest.mark.parametrize("k", [32, 64])
 def test_c2_f64_cholqr2_full(k):
     borth = lib()
