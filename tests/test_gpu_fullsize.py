@@ -154,6 +154,43 @@ def test_fig8_iterated_full_sampled(gram, fact, max_passes, bq, by):
             assert abs(ex_hi[0, 1] + ex_lo[0, 1]) <= by
 
 
+@pytest.mark.parametrize("gram,max_passes,bq,by", [("dd", 3, 1e-16, 1e-17), ("f64", 4, 1e-14, 1e-15)])
+def test_binner_iterated_full_sampled(gram, max_passes, bq, by):
+    """B-inner products at the runtime experiment's size: B = diag(w), w
+    log-uniform with kappa(B) = 1e4, n = 8e6, k_y = 20, n_b = 4, the inputs
+    scaled so that Y^T B Y = I; the iterated scheme with SVQB to convergence,
+    judged by binary128 entries of [Y | Q]^T B Q taken one column pair at a
+    time: every entry of Q^T B Q - I and sampled entries of Y^T B Q (measured
+    1.2e-19 / 3.8e-20 with DD sums, 8.9e-16 / 9.8e-18 with binary64 ones)."""
+    borth = lib()
+    torch = torch_gpu()
+    n, ky, k = 8_000_000, 20, 4
+    X0, Y0 = synth.projected_pair_device(n, k, ky, 1e6, 1e12, 7000 + 10 * ky + k)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(8000 + ky + k)
+    w = torch.exp((torch.rand(n, generator=gen, dtype=torch.float64, device="cuda") - 0.5)
+                  * np.log(1e4))
+    s = torch.rsqrt(w)[:, None]
+    X = (X0 * s).contiguous()
+    Y = (Y0 * s).contiguous()
+    del X0, Y0
+    Q = torch.empty_like(X)
+    note("B-inner iterated", gram, "8,000,000 x [20 | 4]")
+    it = borth.orthonormalize_iter(X, Y, gram=gram, fact="svqb", eps=1e-10, max_iter=10, out=Q,
+                                   B=w)[3]
+    note("  passes", it.passes_run, "converged", it.converged)
+    assert it.converged and it.passes_run <= max_passes
+    Qh, Yh, wh = host(Q), host(Y), host(w)
+    for i in range(k):
+        for j in range(i, k):
+            hi, lo = oracle.gram_w_q(np.ascontiguousarray(np.stack([Qh[:, i], Qh[:, j]], axis=1)), wh)
+            assert abs((hi[0, 1] - (1.0 if i == j else 0.0)) + lo[0, 1]) <= bq
+    for i in (0, 5, 11, 19):
+        for j in range(k):
+            hi, lo = oracle.gram_w_q(np.ascontiguousarray(np.stack([Yh[:, i], Qh[:, j]], axis=1)), wh)
+            assert abs(hi[0, 1] + lo[0, 1]) <= by
+
+
 @pytest.mark.parametrize("k", [32, 64])
 def test_c2_f64_cholqr2_full(k):
     borth = lib()
