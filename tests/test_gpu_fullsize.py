@@ -191,6 +191,37 @@ def test_binner_iterated_full_sampled(gram, max_passes, bq, by):
             assert abs(hi[0, 1] + lo[0, 1]) <= by
 
 
+@pytest.mark.parametrize("fact", ["chol", "svqb"])
+def test_dd_result_full_sampled(fact):
+    """One DD pass returning Q + Q_lo (the DD update for wide blocks) at
+    4,000,000 x [16 | 32], kappa(X) = 10, kappa(X, Y) = 1e3, judged by
+    binary128 Gram entries of [q_i, q_i_lo, q_j, q_j_lo] (and [y_i, q_j,
+    q_j_lo]): entries of (Q + Q_lo)^T (Q + Q_lo) - I within 1e-25 and sampled
+    entries of Y^T (Q + Q_lo) within 1e-27 (measured 5.6e-27 / 4.8e-30 with
+    Cholesky, 3.0e-27 / 4.7e-30 with SVQB), far below any binary64 result."""
+    borth = lib()
+    torch_gpu()
+    Xd, Yd = synth.projected_pair_device(4_000_000, 32, 16, 10.0, 1e3, 8200)
+    note("DD result", fact, "4,000,000 x [16 | 32]")
+    Q, Ql, R, C, info = borth.orthonormalize_dd(Xd, Yd, fact=fact)
+    assert info.status == 0
+    Qh, Qlh, Y = host(Q), host(Ql), host(Yd)
+
+    def gram(*cols):
+        return oracle.gram_q(np.ascontiguousarray(np.stack(cols, axis=1)))
+
+    for i, j in [(0, 0), (0, 1), (5, 17), (31, 31), (30, 31), (12, 12)]:
+        hi, lo = gram(Qh[:, i], Qlh[:, i], Qh[:, j], Qlh[:, j])
+        v = (((hi[0, 2] - (1.0 if i == j else 0.0)) + lo[0, 2]) + (hi[0, 3] + hi[1, 2])
+             + (lo[0, 3] + lo[1, 2]) + hi[1, 3])
+        note("  (Q + Q_lo)^T (Q + Q_lo) - I", i, j, v)
+        assert abs(v) <= 1e-25
+    for i in (0, 9, 15):
+        for j in (0, 13, 31):
+            hi, lo = gram(Y[:, i], Qh[:, j], Qlh[:, j])
+            assert abs((hi[0, 1] + hi[0, 2]) + (lo[0, 1] + lo[0, 2])) <= 1e-27
+
+
 @pytest.mark.parametrize("k", [32, 64])
 def test_c2_f64_cholqr2_full(k):
     borth = lib()
