@@ -222,6 +222,36 @@ def test_dd_result_full_sampled(fact):
             assert abs((hi[0, 1] + hi[0, 2]) + (lo[0, 1] + lo[0, 2])) <= 1e-27
 
 
+@pytest.mark.parametrize("gram", ["f64", "dd"])
+def test_rank_revealing_full_sampled(gram):
+    """SVQB with rank revelation at the runtime experiment's size (n = 8e6,
+    k_y = 10, n_b = 4, kappa(X) = kappa(X, Y) = 1e3) with column 3 set to
+    column 0 plus column 1: rank 3, the last column of Q zero, the first
+    three orthonormal and orthogonal to Y by binary128 entries taken one
+    column pair at a time, and X = Y C + Q R to the binary64 level."""
+    borth = lib()
+    torch = torch_gpu()
+    Xd, Yd = synth.projected_pair_device(8_000_000, 4, 10, 1e3, 1e3, 3104)
+    Xd[:, 3] = Xd[:, 0] + Xd[:, 1]
+    note("rank revealing", gram, "8,000,000 x [10 | 4]")
+    Q, R, C, it, info = borth.orthonormalize_iter(Xd, Yd, gram=gram, fact="svqb", eps=1e-10,
+                                                  max_iter=8, rank_reveal=True)
+    note("  ", it)
+    assert info.status == 0 and it.converged and it.rank == 3
+    Qh, Y = host(Q), host(Yd)
+    assert np.all(Qh[:, 3] == 0.0)
+    for i in range(3):
+        for j in range(i, 3):
+            hi, lo = oracle.gram_q(np.ascontiguousarray(np.stack([Qh[:, i], Qh[:, j]], axis=1)))
+            assert abs((hi[0, 1] - (1.0 if i == j else 0.0)) + lo[0, 1]) <= 20 * 4 * U64
+    for i in (0, 4, 9):
+        for j in range(3):
+            hi, lo = oracle.gram_q(np.ascontiguousarray(np.stack([Y[:, i], Qh[:, j]], axis=1)))
+            assert abs(hi[0, 1] + lo[0, 1]) <= 1e-14
+    res = Xd - Yd @ C - Q @ R
+    assert float(torch.linalg.norm(res)) <= 1e3 * 4 * U64 * float(torch.linalg.norm(Xd))
+
+
 @pytest.mark.parametrize("k", [32, 64])
 def test_c2_f64_cholqr2_full(k):
     borth = lib()
