@@ -23,6 +23,8 @@ Inputs are drawn on the device with the seeded generator of the same recipe
 (synth.*_device) and copied to the host for the oracle.  The oracle's
 measures run on the host's cores (a few seconds to a minute per case).
 """
+import re
+
 import numpy as np
 import pytest
 
@@ -303,11 +305,14 @@ def test_c4_split_refinement_full(passes):
     assert met["omega"] <= (1e-6 if passes == 2 else 1e-14), met
 
 
-def test_c5_tallest_blocks_full():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_c5_tallest_blocks_full(persistent, monkeypatch, capfd):
     """The eight tallest blocks of the 256-block batch (rows up to 1e6,
     widths from {8, 16, 32, 64}, kappa log-uniform in [1e3, 1e10]) with
-    their 16-column locked bases, one batched DD CholQR2 call (P,C,P,C):
-    per block omega, rho and omega_Y <= 1e-14."""
+    their 16-column locked bases, one batched DD CholQR2 call (P,C,P,C),
+    with one launch per phase or as the single persistent launch: per block
+    omega, rho and omega_Y <= 1e-14."""
+    monkeypatch.setenv("BORTH_LOG", "1")
     borth = lib()
     torch = torch_gpu()
     table = synth.batch_table(256, seed=5000)
@@ -320,8 +325,11 @@ def test_c5_tallest_blocks_full():
         Y = synth.locked_basis_device(t["m"], ky, t["seed"] + 100_000)
         blocks.append({"X": X, "Y": Y})
     torch.cuda.synchronize()
-    note("batched DD CholQR2 of 8 full-height blocks")
-    outs, infos = borth.batch_orthonormalize(blocks, gram="dd", passes=2)
+    note("batched DD CholQR2 of 8 full-height blocks, persistent =", persistent)
+    capfd.readouterr()
+    outs, infos = borth.batch_orthonormalize(blocks, gram="dd", passes=2, persistent=persistent)
+    drivers = [int(x) for x in re.findall(r"borth: batch .*persistent=(\d)", capfd.readouterr().err)]
+    assert drivers == [int(persistent)]
     for t, b, (Q, R, C), inf in zip(tall, blocks, outs, infos):
         assert inf.status == 0, (t, inf)
         met = oracle.metrics(host(Q), host(b["X"]), host(R), host(b["Y"]), host(C))
